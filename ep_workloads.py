@@ -1,0 +1,205 @@
+"""Seeded synthetic workloads for the per-increment elasto-plastic solve.
+
+This module only builds inputs: model parameters, per-cell cohesion fields and
+seeded random states.  It holds none of the method's arithmetic and is the one
+module that both the HIP path (through its binding) and the CPU oracle read.
+
+Workloads follow the paper's model configuration (Section "Model
+Configuration and Boundary conditions"): pure-shear loading v_x = a x,
+v_y = -a y (and v_z = 0 in 3D) with a = 1, nondimensional scales L_x = 1,
+G_0 = 1 (Tables of independent scales and dimensionless parameters), friction
+angle 30 degrees, dilation 0.  The heterogeneity is a weak inclusion in
+cohesion (c = 0.5 c0 inside a circle / sphere), a synthetic stand-in for the
+paper's Gaussian cohesion field.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+
+@dataclass
+class Model:
+    """One model: grid, material, loading and solver controls."""
+
+    ndim: int = 2
+    nx: int = 63
+    ny: int = 63
+    nz: int = 1
+    lx: float = 1.0
+    ly: float = 1.0
+    lz: float = 1.0
+    bulk: float = 2.0            # K
+    shear: float = 1.0           # G
+    visc: float = math.inf       # mu_s (inf = elasto-plastic)
+    phi_deg: float = 30.0        # friction angle
+    psi_deg: float = 0.0         # dilation angle (must be 0)
+    dt: float = 1e-4             # load increment (time; a = 1 so also strain)
+    erate: Tuple[float, float, float] = (1.0, -1.0, 0.0)
+    tol: float = 1e-8
+    max_iter: int = 200000
+    n_check: int = 0             # 0 -> default chosen by the solver
+    re: float = 0.0              # 0 -> 3 sqrt(10) pi / 2
+    r: float = 0.5               # Ktilde / Gtilde
+    cfl: float = 0.0             # 0 -> 0.9 / sqrt(ndim)
+    # weak inclusion in cohesion
+    c0: float = 1.75e-3
+    incl_radius: float = 0.1
+    incl_centre: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    incl_factor: float = 0.5
+    steps: int = 10
+    name: str = ""
+
+    @property
+    def n_cells(self) -> int:
+        return self.nx * self.ny * (self.nz if self.ndim == 3 else 1)
+
+    def with_(self, **kw) -> "Model":
+        return replace(self, **kw)
+
+
+def cohesion_field(m: Model) -> np.ndarray:
+    """Per-cell cohesion, x fastest: c0 outside the inclusion, factor*c0 in it.
+
+    A cell is inside when its centre lies strictly within incl_radius of the
+    inclusion centre; the domain is centred at the origin.
+    """
+    dx = m.lx / m.nx
+    dy = m.ly / m.ny
+    xc = -0.5 * m.lx + (np.arange(m.nx) + 0.5) * dx
+    yc = -0.5 * m.ly + (np.arange(m.ny) + 0.5) * dy
+    if m.ndim == 2:
+        X, Y = np.meshgrid(xc, yc, indexing="xy")          # shape (ny, nx)
+        d2 = (X - m.incl_centre[0]) ** 2 + (Y - m.incl_centre[1]) ** 2
+    else:
+        dz = m.lz / m.nz
+        zc = -0.5 * m.lz + (np.arange(m.nz) + 0.5) * dz
+        Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")   # shape (nz, ny, nx)
+        d2 = ((X - m.incl_centre[0]) ** 2 + (Y - m.incl_centre[1]) ** 2
+              + (Z - m.incl_centre[2]) ** 2)
+    c = np.full(d2.shape, m.c0, dtype=np.float64)
+    c[d2 < m.incl_radius ** 2] = m.incl_factor * m.c0
+    return np.ascontiguousarray(c.ravel())
+
+
+# --------------------------------------------------------------------------
+# The five workloads (small 2D case, 2D production, 3D production, batched 2D,
+# large 3D).  Sizes and physical values follow the workload definitions; where
+# a value is not given (3D cohesion, 3D increment for the large case) the 3D
+# production values are reused.
+# --------------------------------------------------------------------------
+
+def c1_small_2d() -> Model:
+    return Model(ndim=2, nx=63, ny=63, tol=1e-8, steps=10, name="2d-63x63-fp64")
+
+
+def c2_2d(seed: int = 0, visc: float = math.inf) -> Model:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    off = rng.uniform(-0.1, 0.1, size=2)
+    return Model(ndim=2, nx=1023, ny=1023, tol=1e-6, steps=50, visc=visc,
+                 incl_centre=(float(off[0]), float(off[1]), 0.0),
+                 name=f"2d-1023x1023-seed{seed}" + ("-vp" if math.isfinite(visc) else "-ep"))
+
+
+def c3_3d(n: int = 255, bulk: float = 2.0) -> Model:
+    return Model(ndim=3, nx=n, ny=n, nz=n, dt=5e-5, tol=1e-6, steps=40, bulk=bulk,
+                 name=f"3d-{n}^3-K{bulk:g}")
+
+
+def c5_3d() -> Model:
+    return Model(ndim=3, nx=511, ny=511, nz=511, dt=5e-5, tol=1e-6, steps=100,
+                 name="3d-511^3")
+
+
+def c4_batch(seed: int = 0, n_models: int = 256,
+             sizes=(127, 255, 383, 511)) -> List[Model]:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for b in range(n_models):
+        n = int(rng.choice(np.asarray(sizes)))
+        phi = float(rng.uniform(20.0, 40.0))
+        c0 = float(rng.uniform(1e-3, 3e-3))
+        rad = float(rng.uniform(0.05, 0.15))
+        lo, hi = -0.5 + rad + 0.05, 0.5 - rad - 0.05
+        cx, cy = (float(v) for v in rng.uniform(lo, hi, size=2))
+        out.append(Model(ndim=2, nx=n, ny=n, phi_deg=phi, c0=c0, incl_radius=rad,
+                         incl_centre=(cx, cy, 0.0), dt=1e-4, tol=1e-6, steps=20,
+                         name=f"batch{b}-{n}"))
+    return out
+
+
+# --------------------------------------------------------------------------
+# Random states for single-sweep parity (every field filled, walls included).
+# --------------------------------------------------------------------------
+
+def field_shapes(m: Model) -> dict:
+    """Staggered shapes (x fastest, listed as (nx_, ny_[, nz_]))."""
+    nx, ny, nz = m.nx, m.ny, m.nz
+    if m.ndim == 2:
+        return {
+            "vx": (nx + 1, ny), "vy": (nx, ny + 1),
+            "p": (nx, ny), "txx": (nx, ny), "tyy": (nx, ny), "txy": (nx + 1, ny + 1),
+        }
+    return {
+        "vx": (nx + 1, ny, nz), "vy": (nx, ny + 1, nz), "vz": (nx, ny, nz + 1),
+        "p": (nx, ny, nz), "txx": (nx, ny, nz), "tyy": (nx, ny, nz),
+        "txy": (nx + 1, ny + 1, nz), "txz": (nx + 1, ny, nz + 1),
+        "tyz": (nx, ny + 1, nz + 1),
+    }
+
+
+def random_state(m: Model, seed: int, amp_v: float = 1e-3, amp_s: float = 1e-3) -> dict:
+    """A seeded, smooth-plus-noise state.
+
+    Velocities are the background field plus a perturbation of relative size
+    amp_v; stresses (current and previous-increment copies) are random with
+    amplitude amp_s.  Values are raw inputs only: walls are not made
+    consistent here, the solver's own boundary handling decides that.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = {}
+    shapes = field_shapes(m)
+    for name, shp in shapes.items():
+        n = int(np.prod(shp))
+        if name.startswith("v"):
+            out[name] = rng.standard_normal(n) * amp_v
+        else:
+            out[name] = rng.standard_normal(n) * amp_s
+            out[name + "_old"] = rng.standard_normal(n) * amp_s
+    # the deviatoric stress is trace-free: fill tzz consistently in 3D
+    if m.ndim == 3:
+        out["tzz"] = -(out["txx"] + out["tyy"])
+        out["tzz_old"] = -(out["txx_old"] + out["tyy_old"])
+    return out
+
+
+def background_velocity(m: Model) -> dict:
+    """v = erate * x at every face, domain centred at the origin."""
+    nx, ny, nz = m.nx, m.ny, m.nz
+    dx, dy = m.lx / nx, m.ly / ny
+    xf = -0.5 * m.lx + np.arange(nx + 1) * dx
+    yf = -0.5 * m.ly + np.arange(ny + 1) * dy
+    if m.ndim == 2:
+        vx = np.tile(m.erate[0] * xf, ny)
+        vy = np.repeat(m.erate[1] * yf, nx)
+        return {"vx": vx, "vy": vy}
+    dz = m.lz / nz
+    zf = -0.5 * m.lz + np.arange(nz + 1) * dz
+    vx = np.tile(m.erate[0] * xf, ny * nz)
+    vy = np.tile(np.repeat(m.erate[1] * yf, nx), nz)
+    vz = np.repeat(m.erate[2] * zf, nx * ny)
+    return {"vx": vx, "vy": vy, "vz": vz}
+
+
+def pressure_anomaly(m: Model, amplitude: float, radius: float) -> np.ndarray:
+    """Initial pressure: amplitude inside a centred circle / sphere, else 0.
+
+    Stand-in for the circular pressure anomaly of the symmetry study.
+    """
+    mm = replace(m, c0=0.0, incl_factor=1.0)
+    inside = cohesion_field(replace(mm, c0=1.0, incl_factor=2.0, incl_radius=radius,
+                                    incl_centre=(0.0, 0.0, 0.0))) > 1.5
+    return np.where(inside, amplitude, 0.0)

@@ -1,0 +1,787 @@
+/*
+ * CPU oracle for the per-increment elasto-plastic pseudo-transient solve.
+ *
+ * TEST INFRASTRUCTURE ONLY (see ep_oracle.h).  Plain FP64, unfused full-grid
+ * loops, every intermediate in its own array, Jacobi order.  Built with
+ * -ffp-contract=off.
+ *
+ * What it computes, per load increment (paper, "Accelerated pseudo-transient
+ * method" and "Return mapping algorithm for plasticity"):
+ *
+ *   pseudo-transient momentum   rho~ dv/dt~ = div(tau - p I)
+ *   pseudo-transient pressure   (1/K~) dp/dt~ + (p - p^)/(K dt) = -div v
+ *   pseudo-transient deviator   (1/2G~) dtau/dt~ + (tau - tau^)/(2G dt)
+ *                               + tau/(2 mu_s) = -lambda dQ/dsigma + e'(v)
+ *
+ * discretised on the conservative staggered grid (Discretization section),
+ * backward Euler in pseudo-time for p and tau, explicit for v.  With
+ * Q = sqrt(J2) (psi = 0) the plastic term is Lambda * tau with
+ * Lambda = lambda_dot / tauII, so the stress update is tau = T / (D + Lambda)
+ * with T = tau_old/(G~dtau) + tau^/(G dt) + 2 e', D = 1/(G~dtau) + 1/(G dt)
+ * + 1/mu_s; Lambda is chosen at cell centres so that the returned tauII equals
+ * the Drucker-Prager bound A p + B c (radial return: the trial deviator is
+ * scaled down onto the yield surface), and averaged from the four adjacent
+ * centres to vertices / edges.  The centre J2 uses the four-point average of
+ * the vertex (edge) shear trial.
+ *
+ * Residual (Convergence study section): the L-inf momentum residual
+ * max|div(tau) - grad p| over interior faces, combined (max) with the
+ * pressure and deviator pseudo-rates expressed as the distance of p and tau
+ * from their local fixed point per unit length,
+ *   |p^{k+1}-p^k| K dt / (K~dtau L)  and  |tau^{k+1}-tau^k| eta / (G~dtau L),
+ * so that a homogeneous state whose stresses are still relaxing in pseudo-time
+ * is not taken as converged.  An increment stops when this is at most
+ * tol * max(R_ref, 2 G max|erate| dt / L), R_ref being the momentum residual
+ * of the physical stresses of the plain guess (pseudo-time terms removed).
+ *
+ * PT parameters (equations for rho~, G~, K~, Vp and the optimal Re, r): the
+ * viscosity in rho~ is the visco-elastic eta = 1/(1/(G dt) + 1/mu_s),
+ * L = max extent, V~ dtau = cfl * min spacing.  Then
+ *   G~dtau = Re eta cfl h / (L (r + 4/3)),  K~dtau = r G~dtau,
+ *   dtau/rho~ = cfl h L / (Re eta).
+ */
+#include "ep_oracle.h"
+
+#include <float.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define PI_D 3.14159265358979323846
+
+struct orc_state {
+    orc_params prm;
+    int nx, ny, nz, ndim;
+    double dx, dy, dz;
+    double gdtau, kdtau, dtrho, eta, A, B, h, L, inv_mus;
+    /* state */
+    double *vx, *vy, *vz;
+    double *p, *txx, *tyy, *tzz, *txy, *txz, *tyz;
+    double *p_old, *txx_old, *tyy_old, *tzz_old, *txy_old, *txz_old, *tyz_old;
+    double *coh;
+    /* accumulators and diagnostics */
+    double *ux, *uy, *uz;
+    double *exx, *eyy, *ezz, *exy, *exz, *eyz;
+    double *eps_p;
+    double *lam, *tII, *yld, *lamdot;
+    /* scratch: new values, trial stresses, divergence */
+    double *vxn, *vyn, *vzn;
+    double *pn, *txxn, *tyyn, *tzzn, *txyn, *txzn, *tyzn;
+    double *Txy, *Txz, *Tyz, *dv;
+    double *vx0, *vy0, *vz0;  /* velocities at the start of the increment */
+    /* bookkeeping of the last sweep */
+    double vmax;
+    long long n_yield;
+    double *hist; int hist_cap, hist_len;
+};
+
+/* ---------------------------------------------------------------- sizes */
+static long n_cells(const orc_state* s) { return (long)s->nx * s->ny * (s->ndim == 3 ? s->nz : 1); }
+static long n_vx(const orc_state* s) { return (long)(s->nx + 1) * s->ny * (s->ndim == 3 ? s->nz : 1); }
+static long n_vy(const orc_state* s) { return (long)s->nx * (s->ny + 1) * (s->ndim == 3 ? s->nz : 1); }
+static long n_vz(const orc_state* s) { return s->ndim == 3 ? (long)s->nx * s->ny * (s->nz + 1) : 0; }
+static long n_xy(const orc_state* s) { return (long)(s->nx + 1) * (s->ny + 1) * (s->ndim == 3 ? s->nz : 1); }
+static long n_xz(const orc_state* s) { return s->ndim == 3 ? (long)(s->nx + 1) * s->ny * (s->nz + 1) : 0; }
+static long n_yz(const orc_state* s) { return s->ndim == 3 ? (long)s->nx * (s->ny + 1) * (s->nz + 1) : 0; }
+
+/* ------------------------------------------------------------- indexing */
+/* 2D */
+#define C2(i, j)  ((i) + nx * (j))
+#define VX2(i, j) ((i) + (nx + 1) * (j))
+#define VY2(i, j) ((i) + nx * (j))
+#define XY2(i, j) ((i) + (nx + 1) * (j))
+/* 3D */
+#define C3(i, j, k)  ((i) + nx * ((j) + ny * (k)))
+#define VX3(i, j, k) ((i) + (nx + 1) * ((j) + ny * (k)))
+#define VY3(i, j, k) ((i) + nx * ((j) + (ny + 1) * (k)))
+#define VZ3(i, j, k) ((i) + nx * ((j) + ny * (k)))
+#define XY3(i, j, k) ((i) + (nx + 1) * ((j) + (ny + 1) * (k)))
+#define XZ3(i, j, k) ((i) + (nx + 1) * ((j) + ny * (k)))
+#define YZ3(i, j, k) ((i) + nx * ((j) + (ny + 1) * (k)))
+
+static double* zalloc(long n) { return n > 0 ? (double*)calloc((size_t)n, sizeof(double)) : NULL; }
+
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Drucker-Prager constants (Plasticity section): 2D A = sin phi, B = cos phi;
+ * 3D A = 6 sin phi / (sqrt3 (3 - sin phi)), B = 6 cos phi / (sqrt3 (3 - sin phi)). */
+static void dp_constants(int ndim, double phi_deg, double* A, double* B)
+{
+    double ph = phi_deg * PI_D / 180.0;
+    if (ndim == 2) {
+        *A = sin(ph);
+        *B = cos(ph);
+    } else {
+        double den = sqrt(3.0) * (3.0 - sin(ph));
+        *A = 6.0 * sin(ph) / den;
+        *B = 6.0 * cos(ph) / den;
+    }
+}
+
+static void set_wall_velocities(orc_state* s)
+{
+    const int nx = s->nx, ny = s->ny, nz = s->nz;
+    const double xw = 0.5 * s->prm.lx, yw = 0.5 * s->prm.ly, zw = 0.5 * s->prm.lz;
+    const double ax = s->prm.erate[0], ay = s->prm.erate[1], az = s->prm.erate[2];
+    if (s->ndim == 2) {
+        for (int j = 0; j < ny; ++j) { s->vx[VX2(0, j)] = -ax * xw; s->vx[VX2(nx, j)] = ax * xw; }
+        for (int i = 0; i < nx; ++i) { s->vy[VY2(i, 0)] = -ay * yw; s->vy[VY2(i, ny)] = ay * yw; }
+    } else {
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j) { s->vx[VX3(0, j, k)] = -ax * xw; s->vx[VX3(nx, j, k)] = ax * xw; }
+        for (int k = 0; k < nz; ++k)
+            for (int i = 0; i < nx; ++i) { s->vy[VY3(i, 0, k)] = -ay * yw; s->vy[VY3(i, ny, k)] = ay * yw; }
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) { s->vz[VZ3(i, j, 0)] = -az * zw; s->vz[VZ3(i, j, nz)] = az * zw; }
+    }
+}
+
+orc_state* orc_create(const orc_params* prm, const double* cohesion)
+{
+    if (!prm || (prm->ndim != 2 && prm->ndim != 3)) return NULL;
+    if (prm->nx < 3 || prm->ny < 3 || (prm->ndim == 3 && prm->nz < 3)) return NULL;
+    if (!(prm->bulk > 0) || !(prm->shear > 0) || !(prm->dt > 0) || !(prm->tol > 0)) return NULL;
+    if (prm->psi_deg != 0.0) return NULL;
+    if (!(prm->visc > 0)) return NULL;
+    orc_state* s = (orc_state*)calloc(1, sizeof(orc_state));
+    s->prm = *prm;
+    s->ndim = prm->ndim;
+    s->nx = prm->nx; s->ny = prm->ny; s->nz = prm->ndim == 3 ? prm->nz : 1;
+    s->dx = prm->lx / prm->nx;
+    s->dy = prm->ly / prm->ny;
+    s->dz = prm->ndim == 3 ? prm->lz / prm->nz : 1.0;
+    s->inv_mus = isinf(prm->visc) ? 0.0 : 1.0 / prm->visc;
+    dp_constants(s->ndim, prm->phi_deg, &s->A, &s->B);
+
+    double re = prm->re > 0 ? prm->re : 3.0 * sqrt(10.0) * PI_D / 2.0;
+    double cfl = prm->cfl > 0 ? prm->cfl : 0.9 / sqrt((double)s->ndim);
+    double r = prm->r > 0 ? prm->r : 0.5;
+    s->eta = 1.0 / (1.0 / (prm->shear * prm->dt) + s->inv_mus);
+    s->h = fmin(s->dx, s->dy);
+    s->L = fmax(prm->lx, prm->ly);
+    if (s->ndim == 3) { s->h = fmin(s->h, s->dz); s->L = fmax(s->L, prm->lz); }
+    s->gdtau = re * s->eta * cfl * s->h / (s->L * (r + 4.0 / 3.0));
+    s->kdtau = r * s->gdtau;
+    s->dtrho = cfl * s->h * s->L / (re * s->eta);
+    if (s->prm.n_check <= 0) s->prm.n_check = s->ndim == 3 ? 10 : 100;
+
+    long nc = n_cells(s);
+    s->vx = zalloc(n_vx(s)); s->vy = zalloc(n_vy(s)); s->vz = zalloc(n_vz(s));
+    s->vxn = zalloc(n_vx(s)); s->vyn = zalloc(n_vy(s)); s->vzn = zalloc(n_vz(s));
+    s->vx0 = zalloc(n_vx(s)); s->vy0 = zalloc(n_vy(s)); s->vz0 = zalloc(n_vz(s));
+    s->ux = zalloc(n_vx(s)); s->uy = zalloc(n_vy(s)); s->uz = zalloc(n_vz(s));
+    s->p = zalloc(nc); s->txx = zalloc(nc); s->tyy = zalloc(nc); s->tzz = zalloc(nc);
+    s->p_old = zalloc(nc); s->txx_old = zalloc(nc); s->tyy_old = zalloc(nc); s->tzz_old = zalloc(nc);
+    s->pn = zalloc(nc); s->txxn = zalloc(nc); s->tyyn = zalloc(nc); s->tzzn = zalloc(nc);
+    s->coh = zalloc(nc); s->dv = zalloc(nc);
+    s->exx = zalloc(nc); s->eyy = zalloc(nc); s->ezz = zalloc(nc); s->eps_p = zalloc(nc);
+    s->lam = zalloc(nc); s->tII = zalloc(nc); s->yld = zalloc(nc); s->lamdot = zalloc(nc);
+    s->txy = zalloc(n_xy(s)); s->txy_old = zalloc(n_xy(s)); s->txyn = zalloc(n_xy(s));
+    s->Txy = zalloc(n_xy(s)); s->exy = zalloc(n_xy(s));
+    s->txz = zalloc(n_xz(s)); s->txz_old = zalloc(n_xz(s)); s->txzn = zalloc(n_xz(s));
+    s->Txz = zalloc(n_xz(s)); s->exz = zalloc(n_xz(s));
+    s->tyz = zalloc(n_yz(s)); s->tyz_old = zalloc(n_yz(s)); s->tyzn = zalloc(n_yz(s));
+    s->Tyz = zalloc(n_yz(s)); s->eyz = zalloc(n_yz(s));
+
+    if (cohesion) memcpy(s->coh, cohesion, (size_t)nc * sizeof(double));
+
+    /* initial state: p = tau = 0, v = background pure-shear field */
+    const int nx = s->nx, ny = s->ny, nz = s->nz;
+    const double ax = prm->erate[0], ay = prm->erate[1], az = prm->erate[2];
+    if (s->ndim == 2) {
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i <= nx; ++i) s->vx[VX2(i, j)] = ax * (-0.5 * prm->lx + i * s->dx);
+        for (int j = 0; j <= ny; ++j)
+            for (int i = 0; i < nx; ++i) s->vy[VY2(i, j)] = ay * (-0.5 * prm->ly + j * s->dy);
+    } else {
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i <= nx; ++i) s->vx[VX3(i, j, k)] = ax * (-0.5 * prm->lx + i * s->dx);
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j <= ny; ++j)
+                for (int i = 0; i < nx; ++i) s->vy[VY3(i, j, k)] = ay * (-0.5 * prm->ly + j * s->dy);
+        for (int k = 0; k <= nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) s->vz[VZ3(i, j, k)] = az * (-0.5 * prm->lz + k * s->dz);
+    }
+    return s;
+}
+
+void orc_free(orc_state* s)
+{
+    if (!s) return;
+    double** all[] = {
+        &s->vx, &s->vy, &s->vz, &s->vxn, &s->vyn, &s->vzn, &s->vx0, &s->vy0, &s->vz0,
+        &s->ux, &s->uy, &s->uz, &s->p, &s->txx, &s->tyy, &s->tzz,
+        &s->p_old, &s->txx_old, &s->tyy_old, &s->tzz_old, &s->pn, &s->txxn, &s->tyyn, &s->tzzn,
+        &s->coh, &s->dv, &s->exx, &s->eyy, &s->ezz, &s->eps_p, &s->lam, &s->tII, &s->yld, &s->lamdot,
+        &s->txy, &s->txy_old, &s->txyn, &s->Txy, &s->exy,
+        &s->txz, &s->txz_old, &s->txzn, &s->Txz, &s->exz,
+        &s->tyz, &s->tyz_old, &s->tyzn, &s->Tyz, &s->eyz,
+    };
+    for (size_t q = 0; q < sizeof(all) / sizeof(all[0]); ++q) free(*all[q]);
+    free(s);
+}
+
+static double* field_ptr(const orc_state* s, int f, long* n)
+{
+    switch (f) {
+    case ORC_VX: *n = n_vx(s); return s->vx;
+    case ORC_VY: *n = n_vy(s); return s->vy;
+    case ORC_VZ: *n = n_vz(s); return s->vz;
+    case ORC_P: *n = n_cells(s); return s->p;
+    case ORC_TXX: *n = n_cells(s); return s->txx;
+    case ORC_TYY: *n = n_cells(s); return s->tyy;
+    case ORC_TZZ: *n = s->ndim == 3 ? n_cells(s) : 0; return s->tzz;
+    case ORC_TXY: *n = n_xy(s); return s->txy;
+    case ORC_TXZ: *n = n_xz(s); return s->txz;
+    case ORC_TYZ: *n = n_yz(s); return s->tyz;
+    case ORC_P_OLD: *n = n_cells(s); return s->p_old;
+    case ORC_TXX_OLD: *n = n_cells(s); return s->txx_old;
+    case ORC_TYY_OLD: *n = n_cells(s); return s->tyy_old;
+    case ORC_TZZ_OLD: *n = s->ndim == 3 ? n_cells(s) : 0; return s->tzz_old;
+    case ORC_TXY_OLD: *n = n_xy(s); return s->txy_old;
+    case ORC_TXZ_OLD: *n = n_xz(s); return s->txz_old;
+    case ORC_TYZ_OLD: *n = n_yz(s); return s->tyz_old;
+    case ORC_UX: *n = n_vx(s); return s->ux;
+    case ORC_UY: *n = n_vy(s); return s->uy;
+    case ORC_UZ: *n = n_vz(s); return s->uz;
+    case ORC_EXX: *n = n_cells(s); return s->exx;
+    case ORC_EYY: *n = n_cells(s); return s->eyy;
+    case ORC_EZZ: *n = s->ndim == 3 ? n_cells(s) : 0; return s->ezz;
+    case ORC_EXY: *n = n_xy(s); return s->exy;
+    case ORC_EXZ: *n = n_xz(s); return s->exz;
+    case ORC_EYZ: *n = n_yz(s); return s->eyz;
+    case ORC_EPS_P: *n = n_cells(s); return s->eps_p;
+    case ORC_COHESION: *n = n_cells(s); return s->coh;
+    case ORC_LAMBDA: *n = n_cells(s); return s->lamdot;
+    case ORC_TAU_II: *n = n_cells(s); return s->tII;
+    case ORC_YIELD: *n = n_cells(s); return s->yld;
+    default: *n = -1; return NULL;
+    }
+}
+
+long orc_field_size(const orc_state* s, int field)
+{
+    long n; field_ptr(s, field, &n); return n;
+}
+
+int orc_get(const orc_state* s, int field, double* out)
+{
+    long n; double* p = field_ptr(s, field, &n);
+    if (n < 0) return -1;
+    if (n > 0) memcpy(out, p, (size_t)n * sizeof(double));
+    return 0;
+}
+
+int orc_set(orc_state* s, int field, const double* in)
+{
+    long n; double* p = field_ptr(s, field, &n);
+    if (n < 0) return -1;
+    if (n > 0) memcpy(p, in, (size_t)n * sizeof(double));
+    return 0;
+}
+
+void orc_scalars(const orc_state* s, double out[8])
+{
+    out[0] = s->gdtau; out[1] = s->kdtau; out[2] = s->dtrho; out[3] = s->eta;
+    out[4] = s->A; out[5] = s->B; out[6] = s->h; out[7] = s->L;
+}
+
+void orc_history(orc_state* s, double* buf, int cap) { s->hist = buf; s->hist_cap = cap; s->hist_len = 0; }
+int orc_history_len(const orc_state* s) { return s->hist_len; }
+
+/* Centre return mapping shared by 2D and 3D: given the trial sums, the
+ * pressure and the cohesion, return Lambda (0 when elastic) and the centre
+ * quantities used for diagnostics. */
+static double centre_lambda(double J2, double D, double p, double c, double A, double B,
+                            double* tII_ret, double* Y_out, double* lamdot)
+{
+    double tII_tr = sqrt(J2) / D;            /* trial tauII if Lambda = 0 */
+    double Y = A * p + B * c;
+    if (Y < 0.0) Y = 0.0;                    /* apex: nothing can be carried */
+    double lam = 0.0;
+    *lamdot = 0.0;
+    if (tII_tr > Y) {
+        lam = D * (tII_tr / Y - 1.0);        /* +inf when Y == 0 */
+        *lamdot = D * (tII_tr - Y);
+        *tII_ret = Y;
+    } else {
+        *tII_ret = tII_tr;
+    }
+    *Y_out = Y;
+    return lam;
+}
+
+/* ------------------------------------------------------------------ 2D */
+static double sweep2d(orc_state* s, int physical)
+{
+    const int nx = s->nx, ny = s->ny;
+    const double dx = s->dx, dy = s->dy;
+    const double igt = physical ? 0.0 : 1.0 / s->gdtau;
+    const double ikt = physical ? 0.0 : 1.0 / s->kdtau;
+    const double igd = 1.0 / (s->prm.shear * s->prm.dt);
+    const double ikd = 1.0 / (s->prm.bulk * s->prm.dt);
+    const double D = igt + igd + s->inv_mus;
+    const double A = s->A, B = s->B;
+
+    /* 1. divergence and pressure at centres */
+#pragma omp parallel for
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            double div = (s->vx[VX2(i + 1, j)] - s->vx[VX2(i, j)]) / dx
+                       + (s->vy[VY2(i, j + 1)] - s->vy[VY2(i, j)]) / dy;
+            s->dv[C2(i, j)] = div;
+            s->pn[C2(i, j)] = (s->p[C2(i, j)] * ikt + s->p_old[C2(i, j)] * ikd - div) / (ikt + ikd);
+        }
+    /* 2. shear trial at vertices (zero on the walls: free slip) */
+#pragma omp parallel for
+    for (int j = 0; j <= ny; ++j)
+        for (int i = 0; i <= nx; ++i) {
+            if (i == 0 || i == nx || j == 0 || j == ny) { s->Txy[XY2(i, j)] = 0.0; continue; }
+            double exy = 0.5 * ((s->vx[VX2(i, j)] - s->vx[VX2(i, j - 1)]) / dy
+                              + (s->vy[VY2(i, j)] - s->vy[VY2(i - 1, j)]) / dx);
+            s->Txy[XY2(i, j)] = s->txy[XY2(i, j)] * igt + s->txy_old[XY2(i, j)] * igd + 2.0 * exy;
+        }
+    /* 3. normal trial and return mapping at centres */
+    long long ny_count = 0;
+    double dpm = 0.0, dtm = 0.0;
+#pragma omp parallel for reduction(+ : ny_count) reduction(max : dpm, dtm)
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const long c = C2(i, j);
+            double div = s->dv[c];
+            double exx = (s->vx[VX2(i + 1, j)] - s->vx[VX2(i, j)]) / dx - div / 3.0;
+            double eyy = (s->vy[VY2(i, j + 1)] - s->vy[VY2(i, j)]) / dy - div / 3.0;
+            double Txx = s->txx[c] * igt + s->txx_old[c] * igd + 2.0 * exx;
+            double Tyy = s->tyy[c] * igt + s->tyy_old[c] * igd + 2.0 * eyy;
+            double Tb = 0.25 * (s->Txy[XY2(i, j)] + s->Txy[XY2(i + 1, j)]
+                              + s->Txy[XY2(i, j + 1)] + s->Txy[XY2(i + 1, j + 1)]);
+            double J2 = 0.5 * (Txx * Txx + Tyy * Tyy) + Tb * Tb;
+            double tret, Y, ld;
+            double lam = centre_lambda(J2, D, s->pn[c], s->coh[c], A, B, &tret, &Y, &ld);
+            s->lam[c] = lam;
+            s->lamdot[c] = ld;
+            s->tII[c] = tret;
+            s->yld[c] = Y;
+            if (lam > 0.0) ny_count++;
+            s->txxn[c] = Txx / (D + lam);
+            s->tyyn[c] = Tyy / (D + lam);
+            dpm = fmax(dpm, fabs(s->pn[c] - s->p[c]));
+            dtm = fmax(dtm, fmax(fabs(s->txxn[c] - s->txx[c]), fabs(s->tyyn[c] - s->tyy[c])));
+        }
+    s->n_yield = ny_count;
+    /* 4. vertices: Lambda averaged from the four adjacent centres */
+#pragma omp parallel for reduction(max : dtm)
+    for (int j = 0; j <= ny; ++j)
+        for (int i = 0; i <= nx; ++i) {
+            if (i == 0 || i == nx || j == 0 || j == ny) { s->txyn[XY2(i, j)] = 0.0; continue; }
+            double lv = 0.25 * (s->lam[C2(i - 1, j - 1)] + s->lam[C2(i, j - 1)]
+                              + s->lam[C2(i - 1, j)] + s->lam[C2(i, j)]);
+            s->txyn[XY2(i, j)] = s->Txy[XY2(i, j)] / (D + lv);
+            dtm = fmax(dtm, fabs(s->txyn[XY2(i, j)] - s->txy[XY2(i, j)]));
+        }
+    /* 5. momentum residual and velocity update at interior faces */
+    double rmax = 0.0, vmax = 0.0;
+    long nbad = 0;
+#pragma omp parallel for reduction(max : rmax, vmax) reduction(+ : nbad)
+    for (int j = 0; j < ny; ++j)
+        for (int i = 1; i < nx; ++i) {
+            double sR = s->txxn[C2(i, j)] - s->pn[C2(i, j)];
+            double sL = s->txxn[C2(i - 1, j)] - s->pn[C2(i - 1, j)];
+            double R = (sR - sL) / dx + (s->txyn[XY2(i, j + 1)] - s->txyn[XY2(i, j)]) / dy;
+            double vn = s->vx[VX2(i, j)] + s->dtrho * R;
+            s->vxn[VX2(i, j)] = vn;
+            rmax = fmax(rmax, fabs(R));
+            if (!(fabs(R) <= DBL_MAX)) nbad++;
+            vmax = fmax(vmax, fabs(vn));
+        }
+#pragma omp parallel for reduction(max : rmax, vmax) reduction(+ : nbad)
+    for (int j = 1; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            double sT = s->tyyn[C2(i, j)] - s->pn[C2(i, j)];
+            double sB = s->tyyn[C2(i, j - 1)] - s->pn[C2(i, j - 1)];
+            double R = (sT - sB) / dy + (s->txyn[XY2(i + 1, j)] - s->txyn[XY2(i, j)]) / dx;
+            double vn = s->vy[VY2(i, j)] + s->dtrho * R;
+            s->vyn[VY2(i, j)] = vn;
+            rmax = fmax(rmax, fabs(R));
+            if (!(fabs(R) <= DBL_MAX)) nbad++;
+            vmax = fmax(vmax, fabs(vn));
+        }
+    s->vmax = vmax;
+    if (nbad) rmax = NAN;
+    if (physical) return rmax;
+    rmax = fmax(rmax, fmax(dpm * s->prm.bulk * s->prm.dt / s->kdtau, dtm * s->eta / s->gdtau) / s->L);
+    if (nbad) rmax = NAN;
+    /* commit (Jacobi: every update above read only old values) */
+    for (int j = 0; j < ny; ++j) for (int i = 1; i < nx; ++i) s->vx[VX2(i, j)] = s->vxn[VX2(i, j)];
+    for (int j = 1; j < ny; ++j) for (int i = 0; i < nx; ++i) s->vy[VY2(i, j)] = s->vyn[VY2(i, j)];
+    memcpy(s->p, s->pn, (size_t)n_cells(s) * sizeof(double));
+    memcpy(s->txx, s->txxn, (size_t)n_cells(s) * sizeof(double));
+    memcpy(s->tyy, s->tyyn, (size_t)n_cells(s) * sizeof(double));
+    memcpy(s->txy, s->txyn, (size_t)n_xy(s) * sizeof(double));
+    return rmax;
+}
+
+/* ------------------------------------------------------------------ 3D */
+static double sweep3d(orc_state* s, int physical)
+{
+    const int nx = s->nx, ny = s->ny, nz = s->nz;
+    const double dx = s->dx, dy = s->dy, dz = s->dz;
+    const double igt = physical ? 0.0 : 1.0 / s->gdtau;
+    const double ikt = physical ? 0.0 : 1.0 / s->kdtau;
+    const double igd = 1.0 / (s->prm.shear * s->prm.dt);
+    const double ikd = 1.0 / (s->prm.bulk * s->prm.dt);
+    const double D = igt + igd + s->inv_mus;
+    const double A = s->A, B = s->B;
+
+    /* 1. divergence and pressure */
+#pragma omp parallel for
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                double div = (s->vx[VX3(i + 1, j, k)] - s->vx[VX3(i, j, k)]) / dx
+                           + (s->vy[VY3(i, j + 1, k)] - s->vy[VY3(i, j, k)]) / dy
+                           + (s->vz[VZ3(i, j, k + 1)] - s->vz[VZ3(i, j, k)]) / dz;
+                long c = C3(i, j, k);
+                s->dv[c] = div;
+                s->pn[c] = (s->p[c] * ikt + s->p_old[c] * ikd - div) / (ikt + ikd);
+            }
+    /* 2. shear trials at edges (zero on walls) */
+#pragma omp parallel for
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j <= ny; ++j)
+            for (int i = 0; i <= nx; ++i) {
+                long e = XY3(i, j, k);
+                if (i == 0 || i == nx || j == 0 || j == ny) { s->Txy[e] = 0.0; continue; }
+                double exy = 0.5 * ((s->vx[VX3(i, j, k)] - s->vx[VX3(i, j - 1, k)]) / dy
+                                  + (s->vy[VY3(i, j, k)] - s->vy[VY3(i - 1, j, k)]) / dx);
+                s->Txy[e] = s->txy[e] * igt + s->txy_old[e] * igd + 2.0 * exy;
+            }
+#pragma omp parallel for
+    for (int k = 0; k <= nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i <= nx; ++i) {
+                long e = XZ3(i, j, k);
+                if (i == 0 || i == nx || k == 0 || k == nz) { s->Txz[e] = 0.0; continue; }
+                double exz = 0.5 * ((s->vx[VX3(i, j, k)] - s->vx[VX3(i, j, k - 1)]) / dz
+                                  + (s->vz[VZ3(i, j, k)] - s->vz[VZ3(i - 1, j, k)]) / dx);
+                s->Txz[e] = s->txz[e] * igt + s->txz_old[e] * igd + 2.0 * exz;
+            }
+#pragma omp parallel for
+    for (int k = 0; k <= nz; ++k)
+        for (int j = 0; j <= ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                long e = YZ3(i, j, k);
+                if (j == 0 || j == ny || k == 0 || k == nz) { s->Tyz[e] = 0.0; continue; }
+                double eyz = 0.5 * ((s->vy[VY3(i, j, k)] - s->vy[VY3(i, j, k - 1)]) / dz
+                                  + (s->vz[VZ3(i, j, k)] - s->vz[VZ3(i, j - 1, k)]) / dy);
+                s->Tyz[e] = s->tyz[e] * igt + s->tyz_old[e] * igd + 2.0 * eyz;
+            }
+    /* 3. normal trials and return mapping at centres */
+    long long ny_count = 0;
+    double dpm = 0.0, dtm = 0.0;
+#pragma omp parallel for reduction(+ : ny_count) reduction(max : dpm, dtm)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                long c = C3(i, j, k);
+                double div = s->dv[c];
+                double exx = (s->vx[VX3(i + 1, j, k)] - s->vx[VX3(i, j, k)]) / dx - div / 3.0;
+                double eyy = (s->vy[VY3(i, j + 1, k)] - s->vy[VY3(i, j, k)]) / dy - div / 3.0;
+                double ezz = (s->vz[VZ3(i, j, k + 1)] - s->vz[VZ3(i, j, k)]) / dz - div / 3.0;
+                double Txx = s->txx[c] * igt + s->txx_old[c] * igd + 2.0 * exx;
+                double Tyy = s->tyy[c] * igt + s->tyy_old[c] * igd + 2.0 * eyy;
+                double Tzz = s->tzz[c] * igt + s->tzz_old[c] * igd + 2.0 * ezz;
+                double Txyb = 0.25 * (s->Txy[XY3(i, j, k)] + s->Txy[XY3(i + 1, j, k)]
+                                    + s->Txy[XY3(i, j + 1, k)] + s->Txy[XY3(i + 1, j + 1, k)]);
+                double Txzb = 0.25 * (s->Txz[XZ3(i, j, k)] + s->Txz[XZ3(i + 1, j, k)]
+                                    + s->Txz[XZ3(i, j, k + 1)] + s->Txz[XZ3(i + 1, j, k + 1)]);
+                double Tyzb = 0.25 * (s->Tyz[YZ3(i, j, k)] + s->Tyz[YZ3(i, j + 1, k)]
+                                    + s->Tyz[YZ3(i, j, k + 1)] + s->Tyz[YZ3(i, j + 1, k + 1)]);
+                double J2 = 0.5 * (Txx * Txx + Tyy * Tyy + Tzz * Tzz)
+                          + Txyb * Txyb + Txzb * Txzb + Tyzb * Tyzb;
+                double tret, Y, ld;
+                double lam = centre_lambda(J2, D, s->pn[c], s->coh[c], A, B, &tret, &Y, &ld);
+                s->lam[c] = lam;
+                s->lamdot[c] = ld;
+                s->tII[c] = tret;
+                s->yld[c] = Y;
+                if (lam > 0.0) ny_count++;
+                s->txxn[c] = Txx / (D + lam);
+                s->tyyn[c] = Tyy / (D + lam);
+                s->tzzn[c] = Tzz / (D + lam);
+                dpm = fmax(dpm, fabs(s->pn[c] - s->p[c]));
+                dtm = fmax(dtm, fmax(fabs(s->txxn[c] - s->txx[c]),
+                                     fmax(fabs(s->tyyn[c] - s->tyy[c]), fabs(s->tzzn[c] - s->tzz[c]))));
+            }
+    s->n_yield = ny_count;
+    /* 4. edges: Lambda averaged from the four adjacent centres */
+#pragma omp parallel for reduction(max : dtm)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j <= ny; ++j)
+            for (int i = 0; i <= nx; ++i) {
+                long e = XY3(i, j, k);
+                if (i == 0 || i == nx || j == 0 || j == ny) { s->txyn[e] = 0.0; continue; }
+                double lv = 0.25 * (s->lam[C3(i - 1, j - 1, k)] + s->lam[C3(i, j - 1, k)]
+                                  + s->lam[C3(i - 1, j, k)] + s->lam[C3(i, j, k)]);
+                s->txyn[e] = s->Txy[e] / (D + lv);
+                dtm = fmax(dtm, fabs(s->txyn[e] - s->txy[e]));
+            }
+#pragma omp parallel for reduction(max : dtm)
+    for (int k = 0; k <= nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i <= nx; ++i) {
+                long e = XZ3(i, j, k);
+                if (i == 0 || i == nx || k == 0 || k == nz) { s->txzn[e] = 0.0; continue; }
+                double lv = 0.25 * (s->lam[C3(i - 1, j, k - 1)] + s->lam[C3(i, j, k - 1)]
+                                  + s->lam[C3(i - 1, j, k)] + s->lam[C3(i, j, k)]);
+                s->txzn[e] = s->Txz[e] / (D + lv);
+                dtm = fmax(dtm, fabs(s->txzn[e] - s->txz[e]));
+            }
+#pragma omp parallel for reduction(max : dtm)
+    for (int k = 0; k <= nz; ++k)
+        for (int j = 0; j <= ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                long e = YZ3(i, j, k);
+                if (j == 0 || j == ny || k == 0 || k == nz) { s->tyzn[e] = 0.0; continue; }
+                double lv = 0.25 * (s->lam[C3(i, j - 1, k - 1)] + s->lam[C3(i, j, k - 1)]
+                                  + s->lam[C3(i, j - 1, k)] + s->lam[C3(i, j, k)]);
+                s->tyzn[e] = s->Tyz[e] / (D + lv);
+                dtm = fmax(dtm, fabs(s->tyzn[e] - s->tyz[e]));
+            }
+    /* 5. momentum residual and velocity update */
+    double rmax = 0.0, vmax = 0.0;
+    long nbad = 0;
+#pragma omp parallel for reduction(max : rmax, vmax) reduction(+ : nbad)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 1; i < nx; ++i) {
+                double sR = s->txxn[C3(i, j, k)] - s->pn[C3(i, j, k)];
+                double sL = s->txxn[C3(i - 1, j, k)] - s->pn[C3(i - 1, j, k)];
+                double R = (sR - sL) / dx
+                         + (s->txyn[XY3(i, j + 1, k)] - s->txyn[XY3(i, j, k)]) / dy
+                         + (s->txzn[XZ3(i, j, k + 1)] - s->txzn[XZ3(i, j, k)]) / dz;
+                double vn = s->vx[VX3(i, j, k)] + s->dtrho * R;
+                s->vxn[VX3(i, j, k)] = vn;
+                rmax = fmax(rmax, fabs(R));
+            if (!(fabs(R) <= DBL_MAX)) nbad++;
+                vmax = fmax(vmax, fabs(vn));
+            }
+#pragma omp parallel for reduction(max : rmax, vmax) reduction(+ : nbad)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 1; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                double sT = s->tyyn[C3(i, j, k)] - s->pn[C3(i, j, k)];
+                double sB = s->tyyn[C3(i, j - 1, k)] - s->pn[C3(i, j - 1, k)];
+                double R = (s->txyn[XY3(i + 1, j, k)] - s->txyn[XY3(i, j, k)]) / dx
+                         + (sT - sB) / dy
+                         + (s->tyzn[YZ3(i, j, k + 1)] - s->tyzn[YZ3(i, j, k)]) / dz;
+                double vn = s->vy[VY3(i, j, k)] + s->dtrho * R;
+                s->vyn[VY3(i, j, k)] = vn;
+                rmax = fmax(rmax, fabs(R));
+            if (!(fabs(R) <= DBL_MAX)) nbad++;
+                vmax = fmax(vmax, fabs(vn));
+            }
+#pragma omp parallel for reduction(max : rmax, vmax) reduction(+ : nbad)
+    for (int k = 1; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                double sU = s->tzzn[C3(i, j, k)] - s->pn[C3(i, j, k)];
+                double sD = s->tzzn[C3(i, j, k - 1)] - s->pn[C3(i, j, k - 1)];
+                double R = (s->txzn[XZ3(i + 1, j, k)] - s->txzn[XZ3(i, j, k)]) / dx
+                         + (s->tyzn[YZ3(i, j + 1, k)] - s->tyzn[YZ3(i, j, k)]) / dy
+                         + (sU - sD) / dz;
+                double vn = s->vz[VZ3(i, j, k)] + s->dtrho * R;
+                s->vzn[VZ3(i, j, k)] = vn;
+                rmax = fmax(rmax, fabs(R));
+            if (!(fabs(R) <= DBL_MAX)) nbad++;
+                vmax = fmax(vmax, fabs(vn));
+            }
+    s->vmax = vmax;
+    if (nbad) rmax = NAN;
+    if (physical) return rmax;
+    rmax = fmax(rmax, fmax(dpm * s->prm.bulk * s->prm.dt / s->kdtau, dtm * s->eta / s->gdtau) / s->L);
+    if (nbad) rmax = NAN;
+    for (int k = 0; k < nz; ++k) for (int j = 0; j < ny; ++j) for (int i = 1; i < nx; ++i)
+        s->vx[VX3(i, j, k)] = s->vxn[VX3(i, j, k)];
+    for (int k = 0; k < nz; ++k) for (int j = 1; j < ny; ++j) for (int i = 0; i < nx; ++i)
+        s->vy[VY3(i, j, k)] = s->vyn[VY3(i, j, k)];
+    for (int k = 1; k < nz; ++k) for (int j = 0; j < ny; ++j) for (int i = 0; i < nx; ++i)
+        s->vz[VZ3(i, j, k)] = s->vzn[VZ3(i, j, k)];
+    long nc = n_cells(s);
+    memcpy(s->p, s->pn, (size_t)nc * sizeof(double));
+    memcpy(s->txx, s->txxn, (size_t)nc * sizeof(double));
+    memcpy(s->tyy, s->tyyn, (size_t)nc * sizeof(double));
+    memcpy(s->tzz, s->tzzn, (size_t)nc * sizeof(double));
+    memcpy(s->txy, s->txyn, (size_t)n_xy(s) * sizeof(double));
+    memcpy(s->txz, s->txzn, (size_t)n_xz(s) * sizeof(double));
+    memcpy(s->tyz, s->tyzn, (size_t)n_yz(s) * sizeof(double));
+    return rmax;
+}
+
+double orc_sweep(orc_state* s, int physical)
+{
+    return s->ndim == 2 ? sweep2d(s, physical) : sweep3d(s, physical);
+}
+
+/* ------------------------------------------------------------ increment */
+static void copy_n(double* dst, const double* src, long n) { if (n > 0) memcpy(dst, src, (size_t)n * sizeof(double)); }
+
+static void save_start(orc_state* s)
+{
+    long nc = n_cells(s);
+    copy_n(s->p_old, s->p, nc);
+    copy_n(s->txx_old, s->txx, nc);
+    copy_n(s->tyy_old, s->tyy, nc);
+    copy_n(s->tzz_old, s->tzz, s->ndim == 3 ? nc : 0);
+    copy_n(s->txy_old, s->txy, n_xy(s));
+    copy_n(s->txz_old, s->txz, n_xz(s));
+    copy_n(s->tyz_old, s->tyz, n_yz(s));
+    copy_n(s->vx0, s->vx, n_vx(s));
+    copy_n(s->vy0, s->vy, n_vy(s));
+    copy_n(s->vz0, s->vz, n_vz(s));
+}
+
+static void roll_back(orc_state* s)
+{
+    long nc = n_cells(s);
+    copy_n(s->p, s->p_old, nc);
+    copy_n(s->txx, s->txx_old, nc);
+    copy_n(s->tyy, s->tyy_old, nc);
+    copy_n(s->tzz, s->tzz_old, s->ndim == 3 ? nc : 0);
+    copy_n(s->txy, s->txy_old, n_xy(s));
+    copy_n(s->txz, s->txz_old, n_xz(s));
+    copy_n(s->tyz, s->tyz_old, n_yz(s));
+    copy_n(s->vx, s->vx0, n_vx(s));
+    copy_n(s->vy, s->vy0, n_vy(s));
+    copy_n(s->vz, s->vz0, n_vz(s));
+}
+
+/* Accumulated displacement, strain and plastic strain; per-increment
+ * diagnostics (integrated sigma_xx over columns, yield statistics). */
+static void epilogue(orc_state* s, orc_stats* st)
+{
+    const int nx = s->nx, ny = s->ny, nz = s->nz;
+    const double dt = s->prm.dt, dx = s->dx, dy = s->dy, dz = s->dz;
+    for (long q = 0; q < n_vx(s); ++q) s->ux[q] += dt * s->vx[q];
+    for (long q = 0; q < n_vy(s); ++q) s->uy[q] += dt * s->vy[q];
+    for (long q = 0; q < n_vz(s); ++q) s->uz[q] += dt * s->vz[q];
+    double vio = -INFINITY;
+    if (s->ndim == 2) {
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                long c = C2(i, j);
+                s->exx[c] += dt * (s->vx[VX2(i + 1, j)] - s->vx[VX2(i, j)]) / dx;
+                s->eyy[c] += dt * (s->vy[VY2(i, j + 1)] - s->vy[VY2(i, j)]) / dy;
+                s->eps_p[c] += dt * 0.5 * s->lamdot[c];
+                double tb = 0.25 * (s->txy[XY2(i, j)] + s->txy[XY2(i + 1, j)]
+                                  + s->txy[XY2(i, j + 1)] + s->txy[XY2(i + 1, j + 1)]);
+                double tII = sqrt(0.5 * (s->txx[c] * s->txx[c] + s->tyy[c] * s->tyy[c]) + tb * tb);
+                vio = fmax(vio, tII - s->yld[c]);
+            }
+        for (int j = 1; j < ny; ++j)
+            for (int i = 1; i < nx; ++i)
+                s->exy[XY2(i, j)] += dt * 0.5 * ((s->vx[VX2(i, j)] - s->vx[VX2(i, j - 1)]) / dy
+                                               + (s->vy[VY2(i, j)] - s->vy[VY2(i - 1, j)]) / dx);
+        double sc = 0, sl = 0, sr = 0;
+        for (int j = 0; j < ny; ++j) {
+            sc += (s->txx[C2(nx / 2, j)] - s->p[C2(nx / 2, j)]) * dy;
+            sl += (s->txx[C2(0, j)] - s->p[C2(0, j)]) * dy;
+            sr += (s->txx[C2(nx - 1, j)] - s->p[C2(nx - 1, j)]) * dy;
+        }
+        st->sxx_centre = sc; st->sxx_left = sl; st->sxx_right = sr;
+    } else {
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    long c = C3(i, j, k);
+                    s->exx[c] += dt * (s->vx[VX3(i + 1, j, k)] - s->vx[VX3(i, j, k)]) / dx;
+                    s->eyy[c] += dt * (s->vy[VY3(i, j + 1, k)] - s->vy[VY3(i, j, k)]) / dy;
+                    s->ezz[c] += dt * (s->vz[VZ3(i, j, k + 1)] - s->vz[VZ3(i, j, k)]) / dz;
+                    s->eps_p[c] += dt * 0.5 * s->lamdot[c];
+                    double bxy = 0.25 * (s->txy[XY3(i, j, k)] + s->txy[XY3(i + 1, j, k)]
+                                       + s->txy[XY3(i, j + 1, k)] + s->txy[XY3(i + 1, j + 1, k)]);
+                    double bxz = 0.25 * (s->txz[XZ3(i, j, k)] + s->txz[XZ3(i + 1, j, k)]
+                                       + s->txz[XZ3(i, j, k + 1)] + s->txz[XZ3(i + 1, j, k + 1)]);
+                    double byz = 0.25 * (s->tyz[YZ3(i, j, k)] + s->tyz[YZ3(i, j + 1, k)]
+                                       + s->tyz[YZ3(i, j, k + 1)] + s->tyz[YZ3(i, j + 1, k + 1)]);
+                    double tII = sqrt(0.5 * (s->txx[c] * s->txx[c] + s->tyy[c] * s->tyy[c]
+                                             + s->tzz[c] * s->tzz[c])
+                                      + bxy * bxy + bxz * bxz + byz * byz);
+                    vio = fmax(vio, tII - s->yld[c]);
+                }
+        for (int k = 0; k < nz; ++k)
+            for (int j = 1; j < ny; ++j)
+                for (int i = 1; i < nx; ++i)
+                    s->exy[XY3(i, j, k)] += dt * 0.5 * ((s->vx[VX3(i, j, k)] - s->vx[VX3(i, j - 1, k)]) / dy
+                                                      + (s->vy[VY3(i, j, k)] - s->vy[VY3(i - 1, j, k)]) / dx);
+        for (int k = 1; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 1; i < nx; ++i)
+                    s->exz[XZ3(i, j, k)] += dt * 0.5 * ((s->vx[VX3(i, j, k)] - s->vx[VX3(i, j, k - 1)]) / dz
+                                                      + (s->vz[VZ3(i, j, k)] - s->vz[VZ3(i - 1, j, k)]) / dx);
+        for (int k = 1; k < nz; ++k)
+            for (int j = 1; j < ny; ++j)
+                for (int i = 0; i < nx; ++i)
+                    s->eyz[YZ3(i, j, k)] += dt * 0.5 * ((s->vy[VY3(i, j, k)] - s->vy[VY3(i, j, k - 1)]) / dz
+                                                      + (s->vz[VZ3(i, j, k)] - s->vz[VZ3(i, j - 1, k)]) / dy);
+        double sc = 0, sl = 0, sr = 0;
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j) {
+                sc += (s->txx[C3(nx / 2, j, k)] - s->p[C3(nx / 2, j, k)]) * dy * dz;
+                sl += (s->txx[C3(0, j, k)] - s->p[C3(0, j, k)]) * dy * dz;
+                sr += (s->txx[C3(nx - 1, j, k)] - s->p[C3(nx - 1, j, k)]) * dy * dz;
+            }
+        st->sxx_centre = sc; st->sxx_left = sl; st->sxx_right = sr;
+    }
+    st->n_yield = s->n_yield;
+    st->max_violation = vio;
+}
+
+int orc_load_step(orc_state* s, orc_stats* st)
+{
+    orc_stats dummy;
+    if (!st) st = &dummy;
+    memset(st, 0, sizeof(*st));
+    s->hist_len = 0;
+    save_start(s);
+    set_wall_velocities(s);
+
+    /* normalisation: physical residual of the plain guess, floored by the
+     * stress increment of the background loading over the domain size */
+    double emax = fmax(fabs(s->prm.erate[0]), fmax(fabs(s->prm.erate[1]), fabs(s->prm.erate[2])));
+    double dsig = 2.0 * s->prm.shear * emax * s->prm.dt;
+    st->r_ref = orc_sweep(s, 1);
+    st->ref = fmax(st->r_ref, dsig / s->L);
+
+    const int nchk = s->prm.n_check;
+    int status = -4;
+    double res = NAN;
+    int it;
+    for (it = 1; it <= s->prm.max_iter; ++it) {
+        res = orc_sweep(s, 0);
+        if (it % nchk == 0) {
+            if (s->hist && s->hist_len < s->hist_cap) s->hist[s->hist_len++] = res;
+            if (!(res == res) || isinf(res) || res > 1e8 * st->ref) { status = -5; break; }
+            if (res <= s->prm.tol * st->ref) { status = 0; break; }
+        }
+    }
+    st->iters = it > s->prm.max_iter ? s->prm.max_iter : it;
+    st->resid = res;
+    st->eps_rel = s->vmax > 0 ? s->dtrho * res / s->vmax : 0.0;
+    st->status = status;
+    if (status != 0) { roll_back(s); return status; }
+    epilogue(s, st);
+    return 0;
+}
