@@ -324,8 +324,9 @@ static double centre_lambda(double J2, double D, double p, double c, double A, d
 }
 
 /* ------------------------------------------------------------------ 2D */
-static double sweep2d(orc_state* s, int physical)
+static double sweep2d(orc_state* s, int mode)
 {
+    const int physical = mode == 1;
     const int nx = s->nx, ny = s->ny;
     const double dx = s->dx, dy = s->dy;
     const double igt = physical ? 0.0 : 1.0 / s->gdtau;
@@ -423,6 +424,7 @@ static double sweep2d(orc_state* s, int physical)
     if (physical) return rmax;
     rmax = fmax(rmax, fmax(dpm * s->prm.bulk * s->prm.dt / s->kdtau, dtm * s->eta / s->gdtau) / s->L);
     if (nbad) rmax = NAN;
+    if (mode == 2) return rmax;
     /* commit (Jacobi: every update above read only old values) */
     for (int j = 0; j < ny; ++j) for (int i = 1; i < nx; ++i) s->vx[VX2(i, j)] = s->vxn[VX2(i, j)];
     for (int j = 1; j < ny; ++j) for (int i = 0; i < nx; ++i) s->vy[VY2(i, j)] = s->vyn[VY2(i, j)];
@@ -434,8 +436,9 @@ static double sweep2d(orc_state* s, int physical)
 }
 
 /* ------------------------------------------------------------------ 3D */
-static double sweep3d(orc_state* s, int physical)
+static double sweep3d(orc_state* s, int mode)
 {
+    const int physical = mode == 1;
     const int nx = s->nx, ny = s->ny, nz = s->nz;
     const double dx = s->dx, dy = s->dy, dz = s->dz;
     const double igt = physical ? 0.0 : 1.0 / s->gdtau;
@@ -613,6 +616,7 @@ static double sweep3d(orc_state* s, int physical)
     if (physical) return rmax;
     rmax = fmax(rmax, fmax(dpm * s->prm.bulk * s->prm.dt / s->kdtau, dtm * s->eta / s->gdtau) / s->L);
     if (nbad) rmax = NAN;
+    if (mode == 2) return rmax;
     for (int k = 0; k < nz; ++k) for (int j = 0; j < ny; ++j) for (int i = 1; i < nx; ++i)
         s->vx[VX3(i, j, k)] = s->vxn[VX3(i, j, k)];
     for (int k = 0; k < nz; ++k) for (int j = 1; j < ny; ++j) for (int i = 0; i < nx; ++i)
@@ -630,9 +634,9 @@ static double sweep3d(orc_state* s, int physical)
     return rmax;
 }
 
-double orc_sweep(orc_state* s, int physical)
+double orc_sweep(orc_state* s, int mode)
 {
-    return s->ndim == 2 ? sweep2d(s, physical) : sweep3d(s, physical);
+    return s->ndim == 2 ? sweep2d(s, mode) : sweep3d(s, mode);
 }
 
 /* ------------------------------------------------------------ increment */
@@ -672,7 +676,11 @@ static void roll_back(orc_state* s)
  * diagnostics (integrated sigma_xx over columns, yield statistics). */
 static void epilogue(orc_state* s, orc_stats* st)
 {
+    /* centre diagnostics (Lambda, plastic rate, returned tauII, bound) of the
+     * accepted state: one PT evaluation that commits nothing */
+    orc_sweep(s, 2);
     const int nx = s->nx, ny = s->ny, nz = s->nz;
+    const double A = s->A, B = s->B;
     const double dt = s->prm.dt, dx = s->dx, dy = s->dy, dz = s->dz;
     for (long q = 0; q < n_vx(s); ++q) s->ux[q] += dt * s->vx[q];
     for (long q = 0; q < n_vy(s); ++q) s->uy[q] += dt * s->vy[q];
@@ -688,7 +696,7 @@ static void epilogue(orc_state* s, orc_stats* st)
                 double tb = 0.25 * (s->txy[XY2(i, j)] + s->txy[XY2(i + 1, j)]
                                   + s->txy[XY2(i, j + 1)] + s->txy[XY2(i + 1, j + 1)]);
                 double tII = sqrt(0.5 * (s->txx[c] * s->txx[c] + s->tyy[c] * s->tyy[c]) + tb * tb);
-                vio = fmax(vio, tII - s->yld[c]);
+                vio = fmax(vio, tII - fmax(0.0, A * s->p[c] + B * s->coh[c]));
             }
         for (int j = 1; j < ny; ++j)
             for (int i = 1; i < nx; ++i)
@@ -719,7 +727,7 @@ static void epilogue(orc_state* s, orc_stats* st)
                     double tII = sqrt(0.5 * (s->txx[c] * s->txx[c] + s->tyy[c] * s->tyy[c]
                                              + s->tzz[c] * s->tzz[c])
                                       + bxy * bxy + bxz * bxz + byz * byz);
-                    vio = fmax(vio, tII - s->yld[c]);
+                    vio = fmax(vio, tII - fmax(0.0, A * s->p[c] + B * s->coh[c]));
                 }
         for (int k = 0; k < nz; ++k)
             for (int j = 1; j < ny; ++j)

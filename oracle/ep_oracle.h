@@ -44,8 +44,8 @@ typedef struct orc_stats {
     double sxx_centre;       /* integral of sigma_xx over the centre column */
     double sxx_left;         /* ... over the first column */
     double sxx_right;        /* ... over the last column */
-    long long n_yield;       /* cells returned to the yield surface in the last iteration */
-    double max_violation;    /* max over cells of tauII(stored stresses) - Y */
+    long long n_yield;       /* cells on the yield surface in a PT evaluation of the accepted state */
+    double max_violation;    /* max over cells of tauII(stored stresses) - max(0, A p + B c) */
 } orc_stats;
 
 enum {
@@ -65,10 +65,12 @@ void   orc_free(orc_state* s);
 long   orc_field_size(const orc_state* s, int field);
 int    orc_get(const orc_state* s, int field, double* out);
 int    orc_set(orc_state* s, int field, const double* in);
-/* One pseudo-transient iteration.  physical != 0 evaluates the stresses of
- * the current velocities with the pseudo-time terms removed and returns their
- * momentum residual without changing the state.  Returns max |R|. */
-double orc_sweep(orc_state* s, int physical);
+/* One pseudo-transient iteration.  mode 0 updates the state; mode 1
+ * evaluates the stresses of the current velocities with the pseudo-time terms
+ * removed and returns their momentum residual; mode 2 evaluates one PT
+ * iteration (filling the centre diagnostics) without committing it.  Modes 1
+ * and 2 leave the state unchanged.  Returns the residual. */
+double orc_sweep(orc_state* s, int mode);
 int    orc_load_step(orc_state* s, orc_stats* st);
 /* PT scalars: [G~dtau, K~dtau, dtau/rho~, eta_ve, A, B, h, L] */
 void   orc_scalars(const orc_state* s, double out[8]);

@@ -145,6 +145,10 @@ class Oracle:
     def sweep(self, physical: bool = False) -> float:
         return lib().orc_sweep(self._h, 1 if physical else 0)
 
+    def evaluate(self) -> float:
+        """One PT evaluation of the current state without committing it."""
+        return lib().orc_sweep(self._h, 2)
+
     def load_step(self) -> dict:
         st = OrcStats()
         lib().orc_load_step(self._h, C.byref(st))
