@@ -1,0 +1,190 @@
+/*
+ * ep.h - C ABI of the MI355X elasto-plastic increment solver (libep.so).
+ *
+ * The library solves, one load increment at a time, the quasi-static momentum
+ * balance of a compressible (visco-)hypoelastic, perfectly plastic
+ * Drucker-Prager medium on a conservative staggered grid, by the accelerated
+ * pseudo-transient (PT) iteration (paper: "Summary of the governing
+ * equations", "Accelerated pseudo-transient method", "Return mapping
+ * algorithm for plasticity", "Convergence study").  Every PT iteration is a
+ * stencil sweep on the GPU: pressure and deviatoric stress from the velocity
+ * gradients, radial return onto the yield surface sqrt(J2) = A p + B c, and a
+ * velocity update from the stress divergence.
+ *
+ * Conventions shared by every call
+ *  - Return value: EP_OK (0) or a negative EP_E* code; no exception crosses
+ *    the ABI.  ep_last_error() describes the last failure of a handle.
+ *  - Host arrays are FP64, x fastest, at the field's own staggered shape
+ *    (ep_field_shape).  The caller owns them; the library copies.
+ *  - Device memory: the caller allocates ONE workspace of
+ *    ep_workspace_size() bytes (any allocator; 256-byte alignment) and keeps
+ *    it alive, unmodified, until ep_destroy.  The library allocates no device
+ *    memory of its own.
+ *  - Streams: all device work of a handle is queued on the stream given to
+ *    ep_init (a hipStream_t passed as void*; NULL = default stream).  Calls
+ *    that return host data synchronise that stream.  A handle is not
+ *    thread-safe; use one handle per stream.
+ *  - Units are those of the caller; the workloads use the paper's
+ *    nondimensionalisation (L_x = 1, G_0 = 1, background strain rate a = 1).
+ */
+#ifndef EP_H
+#define EP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EP_ABI_VERSION 1
+
+/* return codes */
+#define EP_OK          0
+#define EP_EINVAL     -1   /* bad argument or parameter set */
+#define EP_ENOMEM     -2   /* workspace too small */
+#define EP_EDEVICE    -3   /* a HIP call failed (message in ep_last_error) */
+#define EP_ENOTCONV   -4   /* max_iter reached: state rolled back to the increment start */
+#define EP_EDIVERGED  -5   /* NaN/Inf or residual > 1e8 * reference: rolled back */
+
+/* precision of the PT iteration fields */
+#define EP_FP64        0   /* everything FP64 (the paper's precision) */
+#define EP_FP32_FIELDS 1   /* v, p, tau iterate in FP32; accumulated stress,
+                              displacement, strain and all norms FP64; the
+                              increment finishes in FP64 sweeps when FP32
+                              stalls above the tolerance */
+
+/* sweep implementation */
+#define EP_SWEEP_AUTO     0
+#define EP_SWEEP_FUSED    1   /* one kernel per PT iteration (LDS halo tiles) */
+#define EP_SWEEP_UNFUSED  2   /* three kernels per iteration (centres, shear, velocity) */
+
+typedef struct ep_params {
+    int    ndim;             /* 2 or 3 */
+    int    nx, ny, nz;       /* cells per direction, each >= 3 (nz ignored in 2D) */
+    double lx, ly, lz;       /* domain extents; the domain is centred at the origin */
+    double bulk;             /* K > 0 */
+    double shear;            /* G > 0 (uniform) */
+    double visc;             /* mu_s > 0; +INFINITY gives the elasto-plastic limit */
+    double phi_deg;          /* friction angle */
+    double psi_deg;          /* dilation angle; must be 0 (non-dilatant flow) */
+    double dt;               /* physical time increment per load step */
+    double erate[3];         /* background strain rate (diagonal); pure shear = (1,-1,0) */
+    double tol;              /* normalised residual tolerance (> 0) */
+    int    max_iter;         /* PT iteration cap per increment (> 0) */
+    int    n_check;          /* residual checked every n_check iterations (0: 10 in 3D, 100 in 2D) */
+    double re;               /* PT numerical Reynolds number (0: 3 sqrt(10) pi / 2) */
+    double r;                /* PT ratio K~/G~ (0: 1/2) */
+    double cfl;              /* PT Courant number V~ dtau / h (0: 0.9/sqrt(ndim); must be < 1/sqrt(ndim)) */
+    int    precision;        /* EP_FP64 or EP_FP32_FIELDS */
+    int    sweep;            /* EP_SWEEP_* */
+    double fp32_switch;      /* FP32 mode: leave FP32 when the normalised residual
+                                is below this (0: 10 * tol) or stops improving */
+} ep_params;
+
+typedef struct ep_step_stats {
+    int    status;           /* EP_OK, EP_ENOTCONV or EP_EDIVERGED */
+    int    iters;            /* PT iterations of the increment (all precisions) */
+    int    iters_fp32;       /* of which FP32 sweeps */
+    double r_ref;            /* momentum residual of the physical stresses of the plain guess */
+    double ref;              /* max(r_ref, 2 G max|erate| dt / L): residual normaliser */
+    double resid;            /* final residual (absolute; normalised = resid / ref) */
+    double eps_rel;          /* dtau/rho~ * resid / max|v| (relative velocity change per iteration) */
+    double sxx_centre;       /* integral of sigma_xx = tau_xx - p over the centre column (plane in 3D) */
+    double sxx_left;         /* ... over the first column */
+    double sxx_right;        /* ... over the last column */
+    long long n_yield;       /* cells on the yield surface in the accepted state */
+    double max_violation;    /* max over cells of tauII(stored stresses) - (A p + B c) */
+    double seconds;          /* wall time of the call */
+} ep_step_stats;
+
+typedef struct ep_residual_info {
+    double resid;            /* combined residual of one PT evaluation of the current state */
+    double momentum;         /* L-inf momentum residual of the current stresses (eq. for eps_abs) */
+    double physical;         /* momentum residual of the physical stresses of the current v */
+    double vmax;             /* max |v| */
+} ep_residual_info;
+
+/* field ids for ep_fields / ep_field_shape */
+enum {
+    EP_F_VX = 0, EP_F_VY, EP_F_VZ,
+    EP_F_P, EP_F_TXX, EP_F_TYY, EP_F_TZZ, EP_F_TXY, EP_F_TXZ, EP_F_TYZ,
+    EP_F_P_OLD, EP_F_TXX_OLD, EP_F_TYY_OLD, EP_F_TZZ_OLD, EP_F_TXY_OLD, EP_F_TXZ_OLD, EP_F_TYZ_OLD,
+    EP_F_UX, EP_F_UY, EP_F_UZ,
+    EP_F_EXX, EP_F_EYY, EP_F_EZZ, EP_F_EXY, EP_F_EXZ, EP_F_EYZ,
+    EP_F_EPS_P, EP_F_COHESION, EP_F_LAMBDA_DOT, EP_F_TAU_II, EP_F_YIELD,
+    EP_F_COUNT
+};
+#define EP_GET 0
+#define EP_SET 1
+
+typedef struct ep_handle ep_handle;
+
+/* Library version (EP_ABI_VERSION of the build). */
+int ep_abi_version(void);
+
+/* Bytes of device workspace needed for *p.  Pure function; EP_EINVAL for an
+ * invalid parameter set. */
+int ep_workspace_size(const ep_params* p, size_t* bytes);
+
+/* Create a solver in a caller-owned workspace.
+ *  cohesion: n_cells FP64 values (x fastest) or NULL for 0; copied.
+ *  d_workspace/ws_bytes: device memory from the caller, >= ep_workspace_size.
+ *  stream: hipStream_t (as void*) used for all work of the handle.
+ * Initial state (model configuration section): p = tau = 0 and velocities
+ * equal to the background pure-shear field v = erate * x (domain centred).
+ * Errors: EP_EINVAL (psi != 0, cfl >= 1/sqrt(ndim), a size < 3, K, G, dt,
+ * tol or visc not > 0, NULL out), EP_ENOMEM (workspace too small),
+ * EP_EDEVICE. */
+int ep_init(const ep_params* p, const double* cohesion, void* d_workspace, size_t ws_bytes,
+            void* stream, ep_handle** out);
+
+/* Solve one load increment: save the increment's starting stresses (p^,
+ * tau^), iterate PT sweeps from the previous velocities until the residual
+ * (momentum L-inf combined with the pressure and deviator pseudo-rates, see
+ * the paper's convergence section) is at most tol * ref, then add v dt to
+ * the displacement and the strain-rate increments to the accumulated
+ * strains.  On EP_ENOTCONV / EP_EDIVERGED the state is rolled back to the
+ * increment start and st is still filled.  st may be NULL. */
+int ep_load_step(ep_handle* h, ep_step_stats* st);
+
+/* Run n PT sweeps on the current state without the increment prologue or
+ * epilogue (the previous-increment stresses are whatever ep_fields set or
+ * the last increment left).  *resid (may be NULL) gets the combined residual
+ * of the last sweep.  For single-sweep parity checks. */
+int ep_sweep(ep_handle* h, int n, double* resid);
+
+/* FP64 norms of the current state (no state change).  Synchronous. */
+int ep_residual(ep_handle* h, ep_residual_info* r);
+
+/* Copy one field between the device state and a host FP64 array of exactly
+ * ep_field_shape() elements.  dir = EP_GET or EP_SET.  EP_SET of TZZ(_OLD) is
+ * rejected in 3D (the deviator is stored trace-free: tzz = -(txx + tyy));
+ * accumulators, cohesion and the old stresses may be set (checkpoint
+ * restore).  LAMBDA_DOT, TAU_II and YIELD describe the last accepted
+ * increment and are read-only.  EP_EINVAL on a bad id or count. */
+int ep_fields(ep_handle* h, int field, int dir, double* host, size_t count);
+
+/* Shape (x, y, z extents; z = 1 in 2D) of a field; 0 extents if the field
+ * does not exist for this ndim.  Returns the element count or EP_EINVAL. */
+long ep_field_shape(const ep_handle* h, int field, int shape[3]);
+
+/* Release the handle (not the workspace). */
+void ep_destroy(ep_handle* h);
+
+/* Last error message of a handle (static string for a NULL handle). */
+const char* ep_last_error(const ep_handle* h);
+
+/* Timing of the PT sweeps (the dominant kernels).  When enabled, every batch
+ * of back-to-back sweeps between two residual checks is bracketed by HIP
+ * events on the handle's stream; ep_sweep_timing returns, for the given
+ * precision (EP_FP64 / EP_FP32_FIELDS), the accumulated event time divided
+ * by the number of sweeps since timing was (re-)enabled, i.e. the average
+ * duration of one PT iteration (all of its kernels).  Enabling resets. */
+int ep_enable_timing(ep_handle* h, int on);
+int ep_sweep_timing(const ep_handle* h, int precision, double* avg_ms, long* sweeps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EP_H */

@@ -1,0 +1,726 @@
+// Host runtime of libep.so: parameter checks, workspace carving, the
+// per-increment driver (prologue, PT loop with residual checks, precision
+// switch, epilogue) and field I/O.  Everything that runs per point runs in
+// the kernels of ep_sweep_*.hip and ep_aux.hip.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ep.h"
+#include "ep_internal.h"
+
+using namespace ep;
+
+struct ep_handle {
+    ep_params prm;
+    hipStream_t st;
+    AuxGrid g;
+    int ndim, nx, ny, nz, sy;
+    long sz, nelem;
+    double dx, dy, dz, eta, gdtau, kdtau, dtrho, A, B, L, h, inv_mus, dsig_ref;
+    int n_check;
+    bool fp32, fused;
+    double* it64[2][F_NIT];
+    int cur64;
+    double* old64[O_N];
+    double *coh64, *lam64;
+    double* vstart64[3];
+    double* u64[3];
+    double* e64[6];
+    double *epsp64, *lamdot64, *tii64, *yld64, *cols64;
+    float* it32[2][F_NIT];
+    int cur32;
+    float* old32[O_N];
+    float *coh32, *lam32;
+    unsigned long long* red;
+    bool it32_valid, old32_valid, it64_valid;
+    bool timing;
+    hipEvent_t ev0, ev1;
+    double t_ms[2];
+    long t_n[2];
+    char err[512];
+};
+
+namespace {
+
+const double PI = 3.14159265358979323846;
+
+int set_err(ep_handle* h, int code, const char* fmt, ...)
+{
+    if (h) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(h->err, sizeof(h->err), fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+#define HIPCHK(h, x)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (x);                                                                \
+        if (e_ != hipSuccess)                                                               \
+            return set_err((h), EP_EDEVICE, "%s failed: %s", #x, hipGetErrorString(e_));    \
+    } while (0)
+
+bool field_exists_it(int ndim, int f) { return ndim == 3 || (f != F_VZ && f != F_TXZ && f != F_TYZ); }
+bool field_exists_old(int ndim, int f) { return ndim == 3 || (f != O_TXZ && f != O_TYZ); }
+bool field_exists_e(int ndim, int f) { return ndim == 3 || f == 0 || f == 1 || f == 3; }
+
+int validate(const ep_params* p)
+{
+    if (!p) return EP_EINVAL;
+    if (p->ndim != 2 && p->ndim != 3) return EP_EINVAL;
+    if (p->nx < 3 || p->ny < 3 || (p->ndim == 3 && p->nz < 3)) return EP_EINVAL;
+    if (!(p->lx > 0) || !(p->ly > 0) || (p->ndim == 3 && !(p->lz > 0))) return EP_EINVAL;
+    if (!(p->bulk > 0) || !(p->shear > 0) || !(p->visc > 0) || !(p->dt > 0) || !(p->tol > 0)) return EP_EINVAL;
+    if (p->psi_deg != 0.0) return EP_EINVAL;
+    if (p->max_iter <= 0 || p->n_check < 0) return EP_EINVAL;
+    if (p->cfl < 0 || p->re < 0 || p->r < 0) return EP_EINVAL;
+    if (p->cfl > 0 && p->cfl >= 1.0 / std::sqrt((double)p->ndim)) return EP_EINVAL;
+    if (p->precision != EP_FP64 && p->precision != EP_FP32_FIELDS) return EP_EINVAL;
+    if (p->sweep < EP_SWEEP_AUTO || p->sweep > EP_SWEEP_UNFUSED) return EP_EINVAL;
+    return EP_OK;
+}
+
+// Walk the workspace layout; with h != nullptr assign the pointers.
+size_t carve(const ep_params* p, ep_handle* h, char* base)
+{
+    const int nx = p->nx, ny = p->ny, nz = p->ndim == 3 ? p->nz : 0;
+    const long sy = ((nx + 1) + 31) / 32 * 32;
+    const long sz = sy * (ny + 1);
+    const long nelem = sz * (p->ndim == 3 ? nz + 1 : 1);
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        off = (off + 255) / 256 * 256;
+        char* r = base ? base + off : nullptr;
+        off += bytes;
+        return r;
+    };
+    const size_t b64 = nelem * sizeof(double), b32 = nelem * sizeof(float);
+    const bool fp32 = p->precision == EP_FP32_FIELDS;
+    for (int b = 0; b < 2; ++b)
+        for (int f = 0; f < F_NIT; ++f) {
+            char* q = field_exists_it(p->ndim, f) ? take(b64) : nullptr;
+            if (h) h->it64[b][f] = (double*)q;
+        }
+    for (int f = 0; f < O_N; ++f) {
+        char* q = field_exists_old(p->ndim, f) ? take(b64) : nullptr;
+        if (h) h->old64[f] = (double*)q;
+    }
+    char* q;
+    q = take(b64); if (h) h->coh64 = (double*)q;
+    q = take(b64); if (h) h->lam64 = (double*)q;
+    for (int d = 0; d < 3; ++d) {
+        char* a = d < p->ndim ? take(b64) : nullptr;
+        char* u = d < p->ndim ? take(b64) : nullptr;
+        if (h) { h->vstart64[d] = (double*)a; h->u64[d] = (double*)u; }
+    }
+    for (int f = 0; f < 6; ++f) {
+        q = field_exists_e(p->ndim, f) ? take(b64) : nullptr;
+        if (h) h->e64[f] = (double*)q;
+    }
+    q = take(b64); if (h) h->epsp64 = (double*)q;
+    q = take(b64); if (h) h->lamdot64 = (double*)q;
+    q = take(b64); if (h) h->tii64 = (double*)q;
+    q = take(b64); if (h) h->yld64 = (double*)q;
+    q = take(4 * sizeof(double)); if (h) h->cols64 = (double*)q;
+    q = take(RED_N * sizeof(unsigned long long)); if (h) h->red = (unsigned long long*)q;
+    for (int b = 0; b < 2; ++b)
+        for (int f = 0; f < F_NIT; ++f) {
+            q = fp32 && field_exists_it(p->ndim, f) ? take(b32) : nullptr;
+            if (h) h->it32[b][f] = (float*)q;
+        }
+    for (int f = 0; f < O_N; ++f) {
+        q = fp32 && field_exists_old(p->ndim, f) ? take(b32) : nullptr;
+        if (h) h->old32[f] = (float*)q;
+    }
+    q = fp32 ? take(b32) : nullptr; if (h) h->coh32 = (float*)q;
+    q = fp32 ? take(b32) : nullptr; if (h) h->lam32 = (float*)q;
+    if (h) {
+        h->sy = (int)sy;
+        h->sz = sz;
+        h->nelem = nelem;
+    }
+    return (off + 255) / 256 * 256;
+}
+
+void derive(ep_handle* h)
+{
+    const ep_params& p = h->prm;
+    h->ndim = p.ndim;
+    h->nx = p.nx;
+    h->ny = p.ny;
+    h->nz = p.ndim == 3 ? p.nz : 0;
+    h->dx = p.lx / p.nx;
+    h->dy = p.ly / p.ny;
+    h->dz = p.ndim == 3 ? p.lz / p.nz : 1.0;
+    h->inv_mus = std::isinf(p.visc) ? 0.0 : 1.0 / p.visc;
+    const double ph = p.phi_deg * PI / 180.0;
+    if (p.ndim == 2) {
+        h->A = std::sin(ph);
+        h->B = std::cos(ph);
+    } else {
+        const double den = std::sqrt(3.0) * (3.0 - std::sin(ph));
+        h->A = 6.0 * std::sin(ph) / den;
+        h->B = 6.0 * std::cos(ph) / den;
+    }
+    const double re = p.re > 0 ? p.re : 3.0 * std::sqrt(10.0) * PI / 2.0;
+    const double cfl = p.cfl > 0 ? p.cfl : 0.9 / std::sqrt((double)p.ndim);
+    const double r = p.r > 0 ? p.r : 0.5;
+    h->eta = 1.0 / (1.0 / (p.shear * p.dt) + h->inv_mus);
+    h->h = std::fmin(h->dx, h->dy);
+    h->L = std::fmax(p.lx, p.ly);
+    if (p.ndim == 3) {
+        h->h = std::fmin(h->h, h->dz);
+        h->L = std::fmax(h->L, p.lz);
+    }
+    // Vtilde dtau = cfl h; rho~ = Re eta / (V~ L); G~ = rho~ V~^2 / (r + 4/3); K~ = r G~
+    h->gdtau = re * h->eta * cfl * h->h / (h->L * (r + 4.0 / 3.0));
+    h->kdtau = r * h->gdtau;
+    h->dtrho = cfl * h->h * h->L / (re * h->eta);
+    const double emax = std::fmax(std::fabs(p.erate[0]), std::fmax(std::fabs(p.erate[1]), std::fabs(p.erate[2])));
+    h->dsig_ref = 2.0 * p.shear * emax * p.dt;
+    h->n_check = p.n_check > 0 ? p.n_check : (p.ndim == 3 ? 10 : 100);
+    h->fp32 = p.precision == EP_FP32_FIELDS;
+    h->g.ndim = p.ndim;
+    h->g.nx = h->nx;
+    h->g.ny = h->ny;
+    h->g.nz = h->nz;
+}
+
+template <typename R>
+SweepArgs<R> make_args(const ep_handle* h, R* const* from, R* const* to, R* const* old, const R* coh, R* lam,
+                       bool physical)
+{
+    SweepArgs<R> a;
+    for (int f = 0; f < F_NIT; ++f) {
+        a.it[f] = from[f];
+        a.nx_[f] = to[f];
+    }
+    for (int f = 0; f < O_N; ++f) a.old[f] = old[f];
+    a.coh = coh;
+    a.lam = lam;
+    a.red = h->red;
+    a.nx = h->nx;
+    a.ny = h->ny;
+    a.nz = h->nz;
+    a.sy = h->sy;
+    a.sz = h->sz;
+    a.idx = (R)(1.0 / h->dx);
+    a.idy = (R)(1.0 / h->dy);
+    a.idz = (R)(1.0 / h->dz);
+    const double igt = physical ? 0.0 : 1.0 / h->gdtau;
+    const double ikt = physical ? 0.0 : 1.0 / h->kdtau;
+    const double igd = 1.0 / (h->prm.shear * h->prm.dt);
+    const double ikd = 1.0 / (h->prm.bulk * h->prm.dt);
+    a.igt = (R)igt;
+    a.ikt = (R)ikt;
+    a.igd = (R)igd;
+    a.ikd = (R)ikd;
+    a.D = (R)(igt + igd + h->inv_mus);
+    a.dtrho = (R)h->dtrho;
+    a.A = (R)h->A;
+    a.B = (R)h->B;
+    a.rK = (R)(h->prm.bulk * h->prm.dt / (h->kdtau * h->L));
+    a.rG = (R)(h->eta / (h->gdtau * h->L));
+    return a;
+}
+
+SweepArgs<double> args64(const ep_handle* h, bool physical, int from)
+{
+    return make_args<double>(h, h->it64[from], h->it64[1 - from], h->old64, h->coh64, h->lam64, physical);
+}
+SweepArgs<float> args32(const ep_handle* h, int from)
+{
+    return make_args<float>(h, h->it32[from], h->it32[1 - from], h->old32, h->coh32, h->lam32, false);
+}
+
+template <typename R>
+void launch_sweep(const ep_handle* h, const SweepArgs<R>& a, int mode)
+{
+    if (h->ndim == 2) {
+        if (h->fused) launch_sweep_fused_2d<R>(a, mode, h->st);
+        else launch_sweep_unfused_2d<R>(a, mode, h->st);
+    } else {
+        if (h->fused) launch_sweep_fused_3d<R>(a, mode, h->st);
+        else launch_sweep_unfused_3d<R>(a, mode, h->st);
+    }
+}
+
+int read_red(ep_handle* h, double out[RED_N])
+{
+    unsigned long long raw[RED_N];
+    HIPCHK(h, hipMemcpyAsync(raw, h->red, sizeof(raw), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    HIPCHK(h, hipGetLastError());
+    for (int q = 0; q < RED_N; ++q) {
+        double d;
+        std::memcpy(&d, &raw[q], sizeof(d));
+        out[q] = d;
+    }
+    out[RED_NYIELD] = (double)raw[RED_NYIELD];
+    return EP_OK;
+}
+
+void copy_it64(ep_handle* h, double* const* dst, double* const* src)
+{
+    for (int f = 0; f < F_NIT; ++f)
+        if (dst[f]) launch_copy(dst[f], src[f], h->nelem, h->st);
+}
+
+// Make it64[cur64] current after FP32 sweeps (stresses in increment form).
+void ensure_it64(ep_handle* h)
+{
+    if (h->it64_valid) return;
+    for (int f = 0; f < F_NIT; ++f) {
+        if (!h->it64[h->cur64][f]) continue;
+        int o = f == F_P ? O_P : f == F_TXX ? O_TXX : f == F_TYY ? O_TYY : f == F_TXY ? O_TXY
+              : f == F_TXZ ? O_TXZ : f == F_TYZ ? O_TYZ : -1;
+        if (o >= 0)
+            launch_incr_to_f64(h->it64[h->cur64][f], h->old64[o], h->it32[h->cur32][f], h->old32[o], h->nelem, h->st);
+        else
+            launch_to_f64(h->it64[h->cur64][f], h->it32[h->cur32][f], h->nelem, h->st);
+    }
+    h->it64_valid = true;
+}
+
+void ensure_it32(ep_handle* h)
+{
+    if (!h->fp32) return;
+    if (!h->old32_valid) {
+        for (int o = 0; o < O_N; ++o)
+            if (h->old64[o]) launch_to_f32(h->old32[o], h->old64[o], h->nelem, h->st);
+        launch_to_f32(h->coh32, h->coh64, h->nelem, h->st);
+        h->old32_valid = true;
+    }
+    if (!h->it32_valid) {
+        for (int f = 0; f < F_NIT; ++f)
+            if (h->it64[h->cur64][f]) launch_to_f32(h->it32[h->cur32][f], h->it64[h->cur64][f], h->nelem, h->st);
+        h->it32_valid = true;
+    }
+}
+
+// Run nb sweeps in one precision; the last one reduces the residual.
+int run_batch(ep_handle* h, bool use32, int nb, bool check_last)
+{
+    if (h->timing) HIPCHK(h, hipEventRecord(h->ev0, h->st));
+    launch_reset_red(h->red, h->st);
+    for (int b = 0; b < nb; ++b) {
+        int mode = (check_last && b == nb - 1) ? MODE_CHECK : MODE_UPDATE;
+        if (use32) {
+            launch_sweep<float>(h, args32(h, h->cur32), mode);
+            h->cur32 = 1 - h->cur32;
+        } else {
+            launch_sweep<double>(h, args64(h, false, h->cur64), mode);
+            h->cur64 = 1 - h->cur64;
+        }
+    }
+    if (use32) h->it64_valid = false;
+    else h->it32_valid = false;
+    if (h->timing) HIPCHK(h, hipEventRecord(h->ev1, h->st));
+    HIPCHK(h, hipGetLastError());
+    return EP_OK;
+}
+
+void add_timing(ep_handle* h, bool use32, int nb)
+{
+    if (!h->timing) return;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) {
+        h->t_ms[use32 ? 1 : 0] += ms;
+        h->t_n[use32 ? 1 : 0] += nb;
+    }
+}
+
+void roll_back(ep_handle* h)
+{
+    double** it = h->it64[h->cur64];
+    for (int d = 0; d < h->ndim; ++d) launch_copy(it[F_VX + d], h->vstart64[d], h->nelem, h->st);
+    const int map[O_N] = {F_P, F_TXX, F_TYY, F_TXY, F_TXZ, F_TYZ};
+    for (int o = 0; o < O_N; ++o)
+        if (h->old64[o]) launch_copy(it[map[o]], h->old64[o], h->nelem, h->st);
+    h->it64_valid = true;
+    h->it32_valid = false;
+}
+
+struct FieldRef {
+    double* dev;     // padded device array (nullptr for derived fields)
+    int ext[3];      // staggered extents
+    bool writable;
+};
+
+FieldRef field_ref(ep_handle* h, int f)
+{
+    const int nx = h->nx, ny = h->ny, nz = h->ndim == 3 ? h->nz : 1;
+    const bool d3 = h->ndim == 3;
+    FieldRef r{nullptr, {0, 0, 0}, false};
+    auto set = [&](double* d, int a, int b, int c, bool w) { r.dev = d; r.ext[0] = a; r.ext[1] = b; r.ext[2] = c; r.writable = w; };
+    double** it = h->it64[h->cur64];
+    switch (f) {
+    case EP_F_VX: set(it[F_VX], nx + 1, ny, nz, true); break;
+    case EP_F_VY: set(it[F_VY], nx, ny + 1, nz, true); break;
+    case EP_F_VZ: if (d3) set(it[F_VZ], nx, ny, nz + 1, true); break;
+    case EP_F_P: set(it[F_P], nx, ny, nz, true); break;
+    case EP_F_TXX: set(it[F_TXX], nx, ny, nz, true); break;
+    case EP_F_TYY: set(it[F_TYY], nx, ny, nz, true); break;
+    case EP_F_TZZ: if (d3) set(nullptr, nx, ny, nz, false); break;
+    case EP_F_TXY: set(it[F_TXY], nx + 1, ny + 1, nz, true); break;
+    case EP_F_TXZ: if (d3) set(it[F_TXZ], nx + 1, ny, nz + 1, true); break;
+    case EP_F_TYZ: if (d3) set(it[F_TYZ], nx, ny + 1, nz + 1, true); break;
+    case EP_F_P_OLD: set(h->old64[O_P], nx, ny, nz, true); break;
+    case EP_F_TXX_OLD: set(h->old64[O_TXX], nx, ny, nz, true); break;
+    case EP_F_TYY_OLD: set(h->old64[O_TYY], nx, ny, nz, true); break;
+    case EP_F_TZZ_OLD: if (d3) set(nullptr, nx, ny, nz, false); break;
+    case EP_F_TXY_OLD: set(h->old64[O_TXY], nx + 1, ny + 1, nz, true); break;
+    case EP_F_TXZ_OLD: if (d3) set(h->old64[O_TXZ], nx + 1, ny, nz + 1, true); break;
+    case EP_F_TYZ_OLD: if (d3) set(h->old64[O_TYZ], nx, ny + 1, nz + 1, true); break;
+    case EP_F_UX: set(h->u64[0], nx + 1, ny, nz, true); break;
+    case EP_F_UY: set(h->u64[1], nx, ny + 1, nz, true); break;
+    case EP_F_UZ: if (d3) set(h->u64[2], nx, ny, nz + 1, true); break;
+    case EP_F_EXX: set(h->e64[0], nx, ny, nz, true); break;
+    case EP_F_EYY: set(h->e64[1], nx, ny, nz, true); break;
+    case EP_F_EZZ: if (d3) set(h->e64[2], nx, ny, nz, true); break;
+    case EP_F_EXY: set(h->e64[3], nx + 1, ny + 1, nz, true); break;
+    case EP_F_EXZ: if (d3) set(h->e64[4], nx + 1, ny, nz + 1, true); break;
+    case EP_F_EYZ: if (d3) set(h->e64[5], nx, ny + 1, nz + 1, true); break;
+    case EP_F_EPS_P: set(h->epsp64, nx, ny, nz, true); break;
+    case EP_F_COHESION: set(h->coh64, nx, ny, nz, true); break;
+    case EP_F_LAMBDA_DOT: set(h->lamdot64, nx, ny, nz, false); break;
+    case EP_F_TAU_II: set(h->tii64, nx, ny, nz, false); break;
+    case EP_F_YIELD: set(h->yld64, nx, ny, nz, false); break;
+    default: break;
+    }
+    return r;
+}
+
+int get_padded(ep_handle* h, const double* dev, std::vector<double>& buf)
+{
+    buf.resize(h->nelem);
+    HIPCHK(h, hipMemcpyAsync(buf.data(), dev, h->nelem * sizeof(double), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return EP_OK;
+}
+
+void gather(const ep_handle* h, const std::vector<double>& pad, const int ext[3], double* out)
+{
+    long q = 0;
+    for (int k = 0; k < ext[2]; ++k)
+        for (int j = 0; j < ext[1]; ++j)
+            for (int i = 0; i < ext[0]; ++i) out[q++] = pad[i + (long)h->sy * j + h->sz * k];
+}
+
+void scatter(const ep_handle* h, const double* in, const int ext[3], std::vector<double>& pad)
+{
+    long q = 0;
+    for (int k = 0; k < ext[2]; ++k)
+        for (int j = 0; j < ext[1]; ++j)
+            for (int i = 0; i < ext[0]; ++i) pad[i + (long)h->sy * j + h->sz * k] = in[q++];
+}
+
+int upload(ep_handle* h, double* dev, const double* in, const int ext[3])
+{
+    std::vector<double> pad;
+    int rc = get_padded(h, dev, pad);
+    if (rc) return rc;
+    scatter(h, in, ext, pad);
+    HIPCHK(h, hipMemcpyAsync(dev, pad.data(), h->nelem * sizeof(double), hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return EP_OK;
+}
+
+}  // namespace
+
+// =========================================================================
+extern "C" {
+
+int ep_abi_version(void) { return EP_ABI_VERSION; }
+
+int ep_workspace_size(const ep_params* p, size_t* bytes)
+{
+    if (!bytes || validate(p) != EP_OK) return EP_EINVAL;
+    *bytes = carve(p, nullptr, nullptr);
+    return EP_OK;
+}
+
+int ep_init(const ep_params* p, const double* cohesion, void* d_workspace, size_t ws_bytes, void* stream,
+            ep_handle** out)
+{
+    if (!out) return EP_EINVAL;
+    *out = nullptr;
+    int rc = validate(p);
+    if (rc) return rc;
+    size_t need = carve(p, nullptr, nullptr);
+    if (!d_workspace || ws_bytes < need) return EP_ENOMEM;
+    if (((uintptr_t)d_workspace & 255) != 0) return EP_EINVAL;
+    ep_handle* h = new (std::nothrow) ep_handle();
+    if (!h) return EP_ENOMEM;
+    h->prm = *p;
+    h->st = (hipStream_t)stream;
+    derive(h);
+    carve(p, h, (char*)d_workspace);
+    h->g.sy = h->sy;
+    h->g.sz = h->sz;
+    h->g.nelem = h->nelem;
+    h->fused = p->sweep != EP_SWEEP_UNFUSED && fused_available(p->ndim, h->fp32);
+    if (p->sweep == EP_SWEEP_FUSED && !h->fused) {
+        delete h;
+        return EP_EINVAL;
+    }
+    h->cur64 = 0;
+    h->cur32 = 0;
+    auto fail = [&](int code) { delete h; return code; };
+    if (hipMemsetAsync(d_workspace, 0, need, h->st) != hipSuccess) return fail(EP_EDEVICE);
+    if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) return fail(EP_EDEVICE);
+    // cohesion and the background velocity field
+    std::vector<double> pad(h->nelem, 0.0);
+    const int nz1 = h->ndim == 3 ? h->nz : 1;
+    if (cohesion) {
+        int ext[3] = {h->nx, h->ny, nz1};
+        scatter(h, cohesion, ext, pad);
+        if (hipMemcpyAsync(h->coh64, pad.data(), h->nelem * sizeof(double), hipMemcpyHostToDevice, h->st) != hipSuccess)
+            return fail(EP_EDEVICE);
+        if (hipStreamSynchronize(h->st) != hipSuccess) return fail(EP_EDEVICE);
+    }
+    for (int d = 0; d < h->ndim; ++d) {
+        std::fill(pad.begin(), pad.end(), 0.0);
+        const int ex[3] = {h->nx + (d == 0), h->ny + (d == 1), nz1 + (d == 2)};
+        const double len = d == 0 ? p->lx : d == 1 ? p->ly : p->lz;
+        const double sp = d == 0 ? h->dx : d == 1 ? h->dy : h->dz;
+        for (int k = 0; k < ex[2]; ++k)
+            for (int j = 0; j < ex[1]; ++j)
+                for (int i = 0; i < ex[0]; ++i) {
+                    const int n = d == 0 ? i : d == 1 ? j : k;
+                    pad[i + (long)h->sy * j + h->sz * k] = p->erate[d] * (-0.5 * len + n * sp);
+                }
+        if (hipMemcpyAsync(h->it64[0][F_VX + d], pad.data(), h->nelem * sizeof(double), hipMemcpyHostToDevice, h->st) !=
+            hipSuccess)
+            return fail(EP_EDEVICE);
+        if (hipStreamSynchronize(h->st) != hipSuccess) return fail(EP_EDEVICE);
+    }
+    h->it64_valid = true;
+    h->it32_valid = false;
+    h->old32_valid = false;
+    if (hipGetLastError() != hipSuccess) return fail(EP_EDEVICE);
+    *out = h;
+    return EP_OK;
+}
+
+void ep_destroy(ep_handle* h)
+{
+    if (!h) return;
+    (void)hipEventDestroy(h->ev0);
+    (void)hipEventDestroy(h->ev1);
+    delete h;
+}
+
+const char* ep_last_error(const ep_handle* h) { return h ? h->err : "no handle"; }
+
+int ep_enable_timing(ep_handle* h, int on)
+{
+    if (!h) return EP_EINVAL;
+    h->timing = on != 0;
+    h->t_ms[0] = h->t_ms[1] = 0;
+    h->t_n[0] = h->t_n[1] = 0;
+    return EP_OK;
+}
+
+int ep_sweep_timing(const ep_handle* h, int precision, double* avg_ms, long* sweeps)
+{
+    if (!h || (precision != EP_FP64 && precision != EP_FP32_FIELDS)) return EP_EINVAL;
+    const int q = precision == EP_FP32_FIELDS ? 1 : 0;
+    if (avg_ms) *avg_ms = h->t_n[q] ? h->t_ms[q] / h->t_n[q] : 0.0;
+    if (sweeps) *sweeps = h->t_n[q];
+    return EP_OK;
+}
+
+int ep_sweep(ep_handle* h, int n, double* resid)
+{
+    if (!h || n <= 0) return EP_EINVAL;
+    int rc;
+    if (h->fp32) {
+        ensure_it32(h);
+        rc = run_batch(h, true, n, true);
+    } else {
+        rc = run_batch(h, false, n, true);
+    }
+    if (rc) return rc;
+    double red[RED_N];
+    if ((rc = read_red(h, red))) return rc;
+    add_timing(h, h->fp32, n);
+    if (resid) *resid = red[RED_RESID];
+    return EP_OK;
+}
+
+int ep_residual(ep_handle* h, ep_residual_info* r)
+{
+    if (!h || !r) return EP_EINVAL;
+    ensure_it64(h);
+    double red[RED_N];
+    int rc;
+    // one PT evaluation into the scratch buffer (state untouched)
+    launch_reset_red(h->red, h->st);
+    launch_sweep<double>(h, args64(h, false, h->cur64), MODE_CHECK);
+    if ((rc = read_red(h, red))) return rc;
+    r->resid = red[RED_RESID];
+    r->momentum = red[RED_MOM];
+    r->vmax = red[RED_VMAX];
+    launch_reset_red(h->red, h->st);
+    launch_sweep<double>(h, args64(h, true, h->cur64), MODE_PHYS);
+    if ((rc = read_red(h, red))) return rc;
+    r->physical = red[RED_MOM];
+    return EP_OK;
+}
+
+int ep_load_step(ep_handle* h, ep_step_stats* st)
+{
+    if (!h) return EP_EINVAL;
+    ep_step_stats dummy;
+    if (!st) st = &dummy;
+    std::memset(st, 0, sizeof(*st));
+    const auto t0 = std::chrono::steady_clock::now();
+    int rc;
+    double red[RED_N];
+
+    // ---- prologue: increment start state, wall velocities ----------------
+    ensure_it64(h);
+    double** it = h->it64[h->cur64];
+    const int map[O_N] = {F_P, F_TXX, F_TYY, F_TXY, F_TXZ, F_TYZ};
+    for (int o = 0; o < O_N; ++o)
+        if (h->old64[o]) launch_copy(h->old64[o], it[map[o]], h->nelem, h->st);
+    launch_set_walls(h->g, it[F_VX], it[F_VY], it[F_VZ], h->prm.erate, h->prm.lx, h->prm.ly, h->prm.lz, h->st);
+    for (int d = 0; d < h->ndim; ++d) launch_copy(h->vstart64[d], it[F_VX + d], h->nelem, h->st);
+    h->it32_valid = false;
+    h->old32_valid = false;
+
+    // ---- normaliser: physical residual of the plain guess ----------------
+    launch_reset_red(h->red, h->st);
+    launch_sweep<double>(h, args64(h, true, h->cur64), MODE_PHYS);
+    if ((rc = read_red(h, red))) return rc;
+    st->r_ref = red[RED_MOM];
+    st->ref = std::fmax(st->r_ref, h->dsig_ref / h->L);
+
+    // ---- PT iterations ------------------------------------------------------
+    const double tol_abs = h->prm.tol * st->ref;
+    const double sw = (h->prm.fp32_switch > 0 ? h->prm.fp32_switch : 10.0 * h->prm.tol) * st->ref;
+    bool use32 = h->fp32;
+    if (use32) ensure_it32(h);
+    const int nmax = std::max(h->nx, std::max(h->ny, h->nz));
+    const int stall_checks = std::max(8, 16 * nmax / h->n_check);
+    double best = INFINITY;
+    int since_best = 0;
+    int iters = 0, iters32 = 0;
+    int status = EP_ENOTCONV;
+    double resid = NAN, vmax = 0;
+    while (iters < h->prm.max_iter) {
+        const int nb = std::min(h->n_check, h->prm.max_iter - iters);
+        if ((rc = run_batch(h, use32, nb, true))) return rc;
+        if ((rc = read_red(h, red))) return rc;
+        add_timing(h, use32, nb);
+        iters += nb;
+        if (use32) iters32 += nb;
+        resid = red[RED_RESID];
+        vmax = red[RED_VMAX];
+        if (!(resid <= 1e8 * st->ref)) {
+            status = EP_EDIVERGED;
+            break;
+        }
+        if (use32) {
+            if (resid < 0.5 * best) {
+                best = resid;
+                since_best = 0;
+            } else {
+                ++since_best;
+            }
+            if (resid <= sw || since_best >= stall_checks) {
+                ensure_it64(h);      // continue from the FP32 state in FP64
+                use32 = false;
+            }
+            continue;
+        }
+        if (resid <= tol_abs) {
+            status = EP_OK;
+            break;
+        }
+    }
+    st->iters = iters;
+    st->iters_fp32 = iters32;
+    st->resid = resid;
+    st->eps_rel = vmax > 0 ? h->dtrho * resid / vmax : 0.0;
+    st->status = status;
+    if (status != EP_OK) {
+        ensure_it64(h);
+        roll_back(h);
+        st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return status;
+    }
+
+    // ---- epilogue: diagnostics of the accepted state, FP64 accumulators ----
+    launch_reset_red(h->red, h->st);
+    launch_diagnostics<double>(args64(h, false, h->cur64), h->lamdot64, h->tii64, h->yld64, h->st);
+    it = h->it64[h->cur64];
+    const double* v[3] = {it[F_VX], it[F_VY], it[F_VZ]};
+    launch_accumulate(h->g, h->prm.dt, 1.0 / h->dx, 1.0 / h->dy, 1.0 / h->dz, v, h->u64, h->e64, h->epsp64,
+                      h->lamdot64, h->st);
+    launch_column_integrals(h->g, it[F_P], it[F_TXX], h->dy, h->dz, h->cols64, h->st);
+    double cols[4];
+    HIPCHK(h, hipMemcpyAsync(cols, h->cols64, sizeof(cols), hipMemcpyDeviceToHost, h->st));
+    if ((rc = read_red(h, red))) return rc;
+    st->sxx_left = cols[0];
+    st->sxx_centre = cols[1];
+    st->sxx_right = cols[2];
+    st->n_yield = (long long)red[RED_NYIELD];
+    st->max_violation = red[RED_VIOL] - 1.0;
+    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return EP_OK;
+}
+
+long ep_field_shape(const ep_handle* h, int field, int shape[3])
+{
+    if (!h || field < 0 || field >= EP_F_COUNT) return EP_EINVAL;
+    FieldRef r = field_ref(const_cast<ep_handle*>(h), field);
+    if (shape) {
+        shape[0] = r.ext[0];
+        shape[1] = r.ext[1];
+        shape[2] = r.ext[2];
+    }
+    return (long)r.ext[0] * r.ext[1] * r.ext[2];
+}
+
+int ep_fields(ep_handle* h, int field, int dir, double* host, size_t count)
+{
+    if (!h || !host || field < 0 || field >= EP_F_COUNT || (dir != EP_GET && dir != EP_SET)) return EP_EINVAL;
+    ensure_it64(h);
+    FieldRef r = field_ref(h, field);
+    const size_t n = (size_t)r.ext[0] * r.ext[1] * r.ext[2];
+    if (n == 0 || count != n) return set_err(h, EP_EINVAL, "field %d: count %zu, expected %zu", field, count, n);
+    int rc;
+    if (dir == EP_GET) {
+        std::vector<double> pad;
+        if (field == EP_F_TZZ || field == EP_F_TZZ_OLD) {
+            std::vector<double> a, b;
+            const double* px = field == EP_F_TZZ ? h->it64[h->cur64][F_TXX] : h->old64[O_TXX];
+            const double* py = field == EP_F_TZZ ? h->it64[h->cur64][F_TYY] : h->old64[O_TYY];
+            if ((rc = get_padded(h, px, a)) || (rc = get_padded(h, py, b))) return rc;
+            for (long q = 0; q < h->nelem; ++q) a[q] = -(a[q] + b[q]);
+            gather(h, a, r.ext, host);
+            return EP_OK;
+        }
+        if ((rc = get_padded(h, r.dev, pad))) return rc;
+        gather(h, pad, r.ext, host);
+        return EP_OK;
+    }
+    if (!r.writable) return set_err(h, EP_EINVAL, "field %d is read-only", field);
+    if ((rc = upload(h, r.dev, host, r.ext))) return rc;
+    if (field <= EP_F_TYZ) h->it32_valid = false;
+    else h->old32_valid = false;    // old stresses, cohesion (and harmlessly for accumulators)
+    return EP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,252 @@
+// Per-increment kernels around the PT loop: copies and precision
+// conversions, wall velocities, FP64 accumulators (displacement, strain,
+// plastic strain), diagnostics of the accepted state and column integrals of
+// sigma_xx.  All run once per increment (or per precision switch), so they
+// are simple grid-stride / one-thread-per-point kernels.
+#include "ep_device.h"
+
+namespace ep {
+
+namespace {
+
+constexpr int NT1 = 256;
+
+inline int blocks_for(long n) { long b = (n + NT1 - 1) / NT1; return (int)(b > 65535L * 8 ? 65535L * 8 : b); }
+
+__global__ void k_fill(double* p, double v, long n)
+{
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) p[q] = v;
+}
+__global__ void k_copy(double* d, const double* s, long n)
+{
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) d[q] = s[q];
+}
+__global__ void k_to_f32(float* d, const double* s, long n)
+{
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) d[q] = (float)s[q];
+}
+__global__ void k_to_f64(double* d, const float* s, long n)
+{
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) d[q] = (double)s[q];
+}
+__global__ void k_incr_to_f64(double* d, const double* b64, const float* x, const float* b32, long n)
+{
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x)
+        d[q] = b64[q] + ((double)x[q] - (double)b32[q]);
+}
+__global__ void k_reset(unsigned long long* r)
+{
+    if (threadIdx.x < RED_N) r[threadIdx.x] = 0ull;
+}
+
+__global__ void k_walls(AuxGrid g, double* vx, double* vy, double* vz, double ex, double ey, double ez,
+                        double lx, double ly, double lz)
+{
+    // thread (a, b) over the largest wall face; each writes the matching
+    // points of the walls it covers
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    const int nz = g.ndim == 3 ? g.nz : 1;
+    // x-walls: (j, k) = (a, b)
+    if (a < g.ny && b < nz) {
+        long e = (long)g.sy * a + g.sz * b;
+        vx[e] = -0.5 * lx * ex;
+        vx[e + g.nx] = 0.5 * lx * ex;
+    }
+    // y-walls: (i, k) = (a, b)
+    if (a < g.nx && b < nz) {
+        long e = a + g.sz * b;
+        vy[e] = -0.5 * ly * ey;
+        vy[e + (long)g.sy * g.ny] = 0.5 * ly * ey;
+    }
+    // z-walls: (i, j) = (a % nx, ...): handled by a second launch dimension
+    if (g.ndim == 3 && a < g.nx && b < g.ny) {
+        long e = a + (long)g.sy * b;
+        vz[e] = -0.5 * lz * ez;
+        vz[e + g.sz * g.nz] = 0.5 * lz * ez;
+    }
+}
+
+__global__ void k_accumulate(AuxGrid g, double dt, double idx, double idy, double idz,
+                             const double* vx, const double* vy, const double* vz,
+                             double* ux, double* uy, double* uz,
+                             double* exx, double* eyy, double* ezz, double* exy, double* exz, double* eyz,
+                             double* epsp, const double* lamdot)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    const int k = blockIdx.z;
+    if (i > g.nx || j > g.ny) return;
+    const bool d3 = g.ndim == 3;
+    if (!d3 && k > 0) return;
+    const long sy = g.sy, sz = g.sz;
+    const long e = i + sy * j + sz * k;
+    const int nz = d3 ? g.nz : 1;
+    // displacements at faces
+    if (j < g.ny && k < nz) ux[e] += dt * vx[e];
+    if (i < g.nx && k < nz) uy[e] += dt * vy[e];
+    if (d3 && i < g.nx && j < g.ny) uz[e] += dt * vz[e];
+    // centres
+    if (i < g.nx && j < g.ny && k < nz) {
+        exx[e] += dt * (vx[e + 1] - vx[e]) * idx;
+        eyy[e] += dt * (vy[e + sy] - vy[e]) * idy;
+        if (d3) ezz[e] += dt * (vz[e + sz] - vz[e]) * idz;
+        epsp[e] += dt * 0.5 * lamdot[e];
+    }
+    // interior shear points
+    if (i > 0 && i < g.nx && j > 0 && j < g.ny && k < nz)
+        exy[e] += dt * 0.5 * ((vx[e] - vx[e - sy]) * idy + (vy[e] - vy[e - 1]) * idx);
+    if (d3 && i > 0 && i < g.nx && j < g.ny && k > 0 && k < g.nz)
+        exz[e] += dt * 0.5 * ((vx[e] - vx[e - sz]) * idz + (vz[e] - vz[e - 1]) * idx);
+    if (d3 && i < g.nx && j > 0 && j < g.ny && k > 0 && k < g.nz)
+        eyz[e] += dt * 0.5 * ((vy[e] - vy[e - sz]) * idz + (vz[e] - vz[e - sy]) * idy);
+}
+
+// Centre diagnostics: one PT evaluation of the accepted state without writes
+// of the state.  Mirrors the centre computation of the sweep.
+template <typename R>
+__device__ R shear_T(const SweepArgs<R>& a, int f, int of, long e, long s1, long s2, R i1, R i2,
+                     const R* v1, const R* v2)
+{
+    R e2 = (v1[e] - v1[e - s1]) * i1 + (v2[e] - v2[e - s2]) * i2;
+    return a.it[f][e] * a.igt + a.old[of][e] * a.igd + e2;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_diag(SweepArgs<R> a, double* lamdot, double* tii_out, double* yld)
+{
+    __shared__ double sh[4];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    const int k = blockIdx.z;
+    const bool d3 = a.nz > 0;
+    double cnt = 0.0, viol = -INFINITY;
+    if (i < a.nx && j < a.ny) {
+        const long sy = a.sy, sz = a.sz;
+        const long c = i + sy * j + sz * k;
+        const R* vx = a.it[F_VX];
+        const R* vy = a.it[F_VY];
+        R dvx = (vx[c + 1] - vx[c]) * a.idx;
+        R dvy = (vy[c + sy] - vy[c]) * a.idy;
+        R dvz = d3 ? (a.it[F_VZ][c + sz] - a.it[F_VZ][c]) * a.idz : R(0);
+        R div = dvx + dvy + dvz;
+        R pn = (a.it[F_P][c] * a.ikt + a.old[O_P][c] * a.ikd - div) / (a.ikt + a.ikd);
+        R Txx = a.it[F_TXX][c] * a.igt + a.old[O_TXX][c] * a.igd + R(2) * (dvx - div / R(3));
+        R Tyy = a.it[F_TYY][c] * a.igt + a.old[O_TYY][c] * a.igd + R(2) * (dvy - div / R(3));
+        auto Txy = [&](long e, int ii, int jj) -> R {
+            if (ii <= 0 || ii >= a.nx || jj <= 0 || jj >= a.ny) return R(0);
+            return shear_T(a, F_TXY, O_TXY, e, sy, 1, a.idy, a.idx, vx, vy);
+        };
+        R Tb = R(0.25) * (Txy(c, i, j) + Txy(c + 1, i + 1, j) + Txy(c + sy, i, j + 1) + Txy(c + sy + 1, i + 1, j + 1));
+        R J2;
+        // stored-stress tauII at the centre (shear averaged from the shear points)
+        const R* sxy = a.it[F_TXY];
+        R bxy = R(0.25) * (sxy[c] + sxy[c + 1] + sxy[c + sy] + sxy[c + sy + 1]);
+        R txx_s = a.it[F_TXX][c], tyy_s = a.it[F_TYY][c];
+        R tii_s;
+        if (d3) {
+            const R* vz = a.it[F_VZ];
+            auto Txz = [&](long e, int ii, int kk) -> R {
+                if (ii <= 0 || ii >= a.nx || kk <= 0 || kk >= a.nz) return R(0);
+                return shear_T(a, F_TXZ, O_TXZ, e, sz, 1, a.idz, a.idx, vx, vz);
+            };
+            auto Tyz = [&](long e, int jj, int kk) -> R {
+                if (jj <= 0 || jj >= a.ny || kk <= 0 || kk >= a.nz) return R(0);
+                return shear_T(a, F_TYZ, O_TYZ, e, sz, sy, a.idz, a.idy, vy, vz);
+            };
+            R Tzz = -(Txx + Tyy);
+            R Txzb = R(0.25) * (Txz(c, i, k) + Txz(c + 1, i + 1, k) + Txz(c + sz, i, k + 1) + Txz(c + sz + 1, i + 1, k + 1));
+            R Tyzb = R(0.25) * (Tyz(c, j, k) + Tyz(c + sy, j + 1, k) + Tyz(c + sz, j, k + 1) + Tyz(c + sy + sz, j + 1, k + 1));
+            J2 = R(0.5) * (Txx * Txx + Tyy * Tyy + Tzz * Tzz) + Tb * Tb + Txzb * Txzb + Tyzb * Tyzb;
+            const R* sxz = a.it[F_TXZ];
+            const R* syz = a.it[F_TYZ];
+            R bxz = R(0.25) * (sxz[c] + sxz[c + 1] + sxz[c + sz] + sxz[c + sz + 1]);
+            R byz = R(0.25) * (syz[c] + syz[c + sy] + syz[c + sz] + syz[c + sy + sz]);
+            R tzz_s = -(txx_s + tyy_s);
+            tii_s = sqrt(R(0.5) * (txx_s * txx_s + tyy_s * tyy_s + tzz_s * tzz_s) + bxy * bxy + bxz * bxz + byz * byz);
+        } else {
+            J2 = R(0.5) * (Txx * Txx + Tyy * Tyy) + Tb * Tb;
+            tii_s = sqrt(R(0.5) * (txx_s * txx_s + tyy_s * tyy_s) + bxy * bxy);
+        }
+        R ld, tii, Y;
+        R lam = centre_lambda(J2, a.D, pn, a.coh[c], a.A, a.B, ld, tii, Y);
+        lamdot[c] = (double)ld;
+        tii_out[c] = (double)tii;
+        yld[c] = (double)Y;
+        cnt = lam > R(0) ? 1.0 : 0.0;
+        // violation of the stored state against its own bound
+        R Ys = a.A * a.it[F_P][c] + a.B * a.coh[c];
+        Ys = Ys > R(0) ? Ys : R(0);
+        viol = (double)(tii_s - Ys);
+    }
+    block_sum_to<256>(cnt, a.red + RED_NYIELD, sh);
+    // the violation can be negative: shift by a large constant so that the
+    // unsigned max of the bit patterns orders it correctly
+    block_max_to<256>(i < a.nx && j < a.ny ? viol + 1.0 : 0.0, a.red + RED_VIOL, sh);
+}
+
+__global__ void k_columns(AuxGrid g, const double* p, const double* txx, double w, double* out)
+{
+    // one block per column (0, nx/2, nx-1); threads stride over (j, k)
+    __shared__ double sh[4];
+    const int col = blockIdx.x == 0 ? 0 : (blockIdx.x == 1 ? g.nx / 2 : g.nx - 1);
+    const int nz = g.ndim == 3 ? g.nz : 1;
+    const long n = (long)g.ny * nz;
+    double s = 0.0;
+    for (long q = threadIdx.x; q < n; q += blockDim.x) {
+        long j = q % g.ny, k = q / g.ny;
+        long e = col + g.sy * j + g.sz * k;
+        s += (txx[e] - p[e]) * w;
+    }
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+}  // namespace
+
+void launch_fill(double* p, double v, long n, hipStream_t s) { k_fill<<<blocks_for(n), NT1, 0, s>>>(p, v, n); }
+void launch_copy(double* d, const double* src, long n, hipStream_t s) { k_copy<<<blocks_for(n), NT1, 0, s>>>(d, src, n); }
+void launch_to_f32(float* d, const double* src, long n, hipStream_t s) { k_to_f32<<<blocks_for(n), NT1, 0, s>>>(d, src, n); }
+void launch_to_f64(double* d, const float* src, long n, hipStream_t s) { k_to_f64<<<blocks_for(n), NT1, 0, s>>>(d, src, n); }
+void launch_incr_to_f64(double* d, const double* b64, const float* x, const float* b32, long n, hipStream_t s)
+{
+    k_incr_to_f64<<<blocks_for(n), NT1, 0, s>>>(d, b64, x, b32, n);
+}
+void launch_reset_red(unsigned long long* red, hipStream_t s) { k_reset<<<1, 64, 0, s>>>(red); }
+
+void launch_set_walls(const AuxGrid& g, double* vx, double* vy, double* vz, const double erate[3],
+                      double lx, double ly, double lz, hipStream_t s)
+{
+    int na = g.nx > g.ny ? g.nx : g.ny;
+    int nb = g.ndim == 3 ? (g.nz > g.ny ? g.nz : g.ny) : 1;
+    dim3 grid((na + 127) / 128, nb);
+    k_walls<<<grid, 128, 0, s>>>(g, vx, vy, vz, erate[0], erate[1], erate[2], lx, ly, lz);
+}
+
+void launch_accumulate(const AuxGrid& g, double dt, double idx, double idy, double idz,
+                       const double* const v[3], double* const u[3], double* const e[6],
+                       double* epsp, const double* lamdot, hipStream_t s)
+{
+    dim3 grid((g.nx + 1 + 127) / 128, g.ny + 1, g.ndim == 3 ? g.nz + 1 : 1);
+    k_accumulate<<<grid, 128, 0, s>>>(g, dt, idx, idy, idz, v[0], v[1], v[2], u[0], u[1], u[2],
+                                      e[0], e[1], e[2], e[3], e[4], e[5], epsp, lamdot);
+}
+
+template <typename R>
+void launch_diagnostics(const SweepArgs<R>& a, double* lamdot, double* tii, double* yld, hipStream_t s)
+{
+    dim3 grid((a.nx + 255) / 256, a.ny, a.nz > 0 ? a.nz : 1);
+    k_diag<R><<<grid, 256, 0, s>>>(a, lamdot, tii, yld);
+}
+template void launch_diagnostics<double>(const SweepArgs<double>&, double*, double*, double*, hipStream_t);
+template void launch_diagnostics<float>(const SweepArgs<float>&, double*, double*, double*, hipStream_t);
+
+void launch_column_integrals(const AuxGrid& g, const double* p, const double* txx, double dy, double dz,
+                             double* out3, hipStream_t s)
+{
+    k_columns<<<3, 256, 0, s>>>(g, p, txx, g.ndim == 3 ? dy * dz : dy, out3);
+}
+
+}  // namespace ep

@@ -1,0 +1,89 @@
+// Internal interface between the host runtime (ep_api.hip) and the kernels.
+//
+// Device layout: every field lives in its own array with one common padded
+// shape, x fastest: element (i, j, k) is at i + sy*j + sz*k with
+// sy = round_up(nx + 1, 32) and sz = sy * (ny + 1).  Cells use i < nx,
+// x-faces i <= nx, vertices / edges the corresponding "+1" extents, so the
+// neighbour offsets of every staggered field are the same +-1, +-sy, +-sz.
+// Padding entries are never read.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ep {
+
+// Index of the iteration fields in the field tables.
+enum { F_VX = 0, F_VY, F_VZ, F_P, F_TXX, F_TYY, F_TXY, F_TXZ, F_TYZ, F_NIT };
+// Index of the previous-increment stresses.
+enum { O_P = 0, O_TXX, O_TYY, O_TXY, O_TXZ, O_TYZ, O_N };
+
+// Reduction slots (uint64 bit patterns of non-negative doubles; max by
+// integer atomicMax; NaN is mapped to +inf before reduction).
+enum { RED_RESID = 0, RED_MOM, RED_VMAX, RED_NYIELD, RED_VIOL, RED_N = 8 };
+
+// Scalars of one PT sweep.  Kernel arguments by value.
+template <typename R>
+struct SweepArgs {
+    const R* it[F_NIT];    // iteration k (read)
+    R* nx_[F_NIT];         // iteration k+1 (written)
+    const R* old[O_N];     // stresses at the start of the increment
+    const R* coh;          // cohesion at cells
+    R* lam;                // unfused path: centre Lambda of this sweep
+    unsigned long long* red;
+    int nx, ny, nz;
+    int sy;
+    long sz;
+    R idx, idy, idz;       // inverse spacings
+    R igt, ikt;            // 1/(G~ dtau), 1/(K~ dtau); 0 for a physical evaluation
+    R igd, ikd;            // 1/(G dt), 1/(K dt)
+    R D;                   // igt + igd + 1/mu_s
+    R dtrho;               // dtau / rho~
+    R A, B;                // Drucker-Prager constants
+    R rK, rG;              // pseudo-rate -> residual factors: K dt/(K~dtau L), eta/(G~dtau L)
+};
+
+// Sweep modes.
+enum { MODE_UPDATE = 0,    // write iteration k+1
+       MODE_CHECK = 1,     // write k+1 and reduce the residual
+       MODE_PHYS = 2 };    // physical evaluation: reduce the momentum residual only, write nothing
+
+// ---- launchers (ep_sweep.hip) ---------------------------------------------
+template <typename R> void launch_sweep_unfused_2d(const SweepArgs<R>& a, int mode, hipStream_t s);
+template <typename R> void launch_sweep_unfused_3d(const SweepArgs<R>& a, int mode, hipStream_t s);
+template <typename R> void launch_sweep_fused_2d(const SweepArgs<R>& a, int mode, hipStream_t s);
+template <typename R> void launch_sweep_fused_3d(const SweepArgs<R>& a, int mode, hipStream_t s);
+bool fused_available(int ndim, bool fp32);
+
+// ---- auxiliary kernels (ep_aux.hip) ----------------------------------------
+struct AuxGrid {
+    int ndim, nx, ny, nz, sy;
+    long sz;
+    long nelem;            // elements per padded array
+};
+
+void launch_fill(double* p, double v, long n, hipStream_t s);
+void launch_copy(double* dst, const double* src, long n, hipStream_t s);
+void launch_to_f32(float* dst, const double* src, long n, hipStream_t s);
+void launch_to_f64(double* dst, const float* src, long n, hipStream_t s);
+// dst64 = base64 + (double)(x32 - base32)   (increment form)
+void launch_incr_to_f64(double* dst, const double* base64, const float* x32, const float* base32,
+                        long n, hipStream_t s);
+void launch_reset_red(unsigned long long* red, hipStream_t s);
+// Background velocities at the wall faces.
+void launch_set_walls(const AuxGrid& g, double* vx, double* vy, double* vz, const double erate[3],
+                      double lx, double ly, double lz, hipStream_t s);
+// Accumulators: u += v dt at faces; strains += grad v dt; eps_p += dt lamdot / 2.
+void launch_accumulate(const AuxGrid& g, double dt, double idx, double idy, double idz,
+                       const double* const v[3], double* const u[3], double* const e[6],
+                       double* epsp, const double* lamdot, hipStream_t s);
+// Centre diagnostics of the accepted state (one PT evaluation without writes):
+// lamdot = D (tauII_tr - Y) where yielding, tauII returned, Y; counts yielding
+// cells and the max violation tauII(stored) - Y into red.
+template <typename R>
+void launch_diagnostics(const SweepArgs<R>& a, double* lamdot, double* tii, double* yld,
+                        hipStream_t s);
+// Column integrals of sigma_xx at columns i = 0, nx/2, nx-1 (3 doubles).
+void launch_column_integrals(const AuxGrid& g, const double* p, const double* txx, double dy,
+                             double dz, double* out3, hipStream_t s);
+
+}  // namespace ep

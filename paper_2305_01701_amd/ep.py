@@ -1,0 +1,262 @@
+"""Python binding of libep.so (ctypes; argument marshalling only).
+
+Functions carry the C names (ep_init, ep_load_step, ep_sweep, ep_residual,
+ep_fields, ...).  `Solver` is a thin convenience wrapper: it asks the library
+for the workspace size, allocates that many bytes on the GPU with PyTorch,
+passes the current torch stream, and converts fields to numpy arrays.  Every
+step of the solve runs in the library's HIP kernels; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libep.so")
+
+EP_OK, EP_EINVAL, EP_ENOMEM, EP_EDEVICE, EP_ENOTCONV, EP_EDIVERGED = 0, -1, -2, -3, -4, -5
+EP_FP64, EP_FP32_FIELDS = 0, 1
+EP_SWEEP_AUTO, EP_SWEEP_FUSED, EP_SWEEP_UNFUSED = 0, 1, 2
+EP_GET, EP_SET = 0, 1
+
+FIELDS = [
+    "vx", "vy", "vz", "p", "txx", "tyy", "tzz", "txy", "txz", "tyz",
+    "p_old", "txx_old", "tyy_old", "tzz_old", "txy_old", "txz_old", "tyz_old",
+    "ux", "uy", "uz", "exx", "eyy", "ezz", "exy", "exz", "eyz",
+    "eps_p", "cohesion", "lambda_dot", "tau_ii", "yield",
+]
+FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
+
+# every symbol include/ep.h declares
+SYMBOLS = ["ep_abi_version", "ep_workspace_size", "ep_init", "ep_load_step", "ep_sweep",
+           "ep_residual", "ep_fields", "ep_field_shape", "ep_destroy", "ep_last_error",
+           "ep_enable_timing", "ep_sweep_timing"]
+
+
+class ep_params(C.Structure):
+    _fields_ = [
+        ("ndim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+        ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double),
+        ("bulk", C.c_double), ("shear", C.c_double), ("visc", C.c_double),
+        ("phi_deg", C.c_double), ("psi_deg", C.c_double), ("dt", C.c_double),
+        ("erate", C.c_double * 3), ("tol", C.c_double),
+        ("max_iter", C.c_int), ("n_check", C.c_int),
+        ("re", C.c_double), ("r", C.c_double), ("cfl", C.c_double),
+        ("precision", C.c_int), ("sweep", C.c_int), ("fp32_switch", C.c_double),
+    ]
+
+
+class ep_step_stats(C.Structure):
+    _fields_ = [
+        ("status", C.c_int), ("iters", C.c_int), ("iters_fp32", C.c_int),
+        ("r_ref", C.c_double), ("ref", C.c_double), ("resid", C.c_double), ("eps_rel", C.c_double),
+        ("sxx_centre", C.c_double), ("sxx_left", C.c_double), ("sxx_right", C.c_double),
+        ("n_yield", C.c_longlong), ("max_violation", C.c_double), ("seconds", C.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ep_residual_info(C.Structure):
+    _fields_ = [("resid", C.c_double), ("momentum", C.c_double), ("physical", C.c_double),
+                ("vmax", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libep.so; raises if it has not been built (no CPU fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2305_01701_amd.build` (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.ep_abi_version.restype = C.c_int
+        L.ep_workspace_size.argtypes = [C.POINTER(ep_params), C.POINTER(C.c_size_t)]
+        L.ep_init.argtypes = [C.POINTER(ep_params), C.POINTER(C.c_double), vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.ep_load_step.argtypes = [vp, C.POINTER(ep_step_stats)]
+        L.ep_sweep.argtypes = [vp, C.c_int, C.POINTER(C.c_double)]
+        L.ep_residual.argtypes = [vp, C.POINTER(ep_residual_info)]
+        L.ep_fields.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_double), C.c_size_t]
+        L.ep_field_shape.restype = C.c_long
+        L.ep_field_shape.argtypes = [vp, C.c_int, C.POINTER(C.c_int)]
+        L.ep_destroy.argtypes = [vp]
+        L.ep_destroy.restype = None
+        L.ep_last_error.restype = C.c_char_p
+        L.ep_last_error.argtypes = [vp]
+        L.ep_enable_timing.argtypes = [vp, C.c_int]
+        L.ep_sweep_timing.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_long)]
+        _lib = L
+    return _lib
+
+
+# ---- thin C-named wrappers ---------------------------------------------------
+def ep_abi_version() -> int:
+    return lib().ep_abi_version()
+
+
+def ep_workspace_size(p: ep_params) -> int:
+    n = C.c_size_t(0)
+    rc = lib().ep_workspace_size(C.byref(p), C.byref(n))
+    if rc != EP_OK:
+        raise ValueError(f"ep_workspace_size: {rc}")
+    return n.value
+
+
+def ep_init(p: ep_params, cohesion: Optional[np.ndarray], d_workspace: int, ws_bytes: int, stream: int):
+    h = C.c_void_p()
+    coh = None if cohesion is None else np.ascontiguousarray(cohesion, dtype=np.float64)
+    cp = None if coh is None else coh.ctypes.data_as(C.POINTER(C.c_double))
+    rc = lib().ep_init(C.byref(p), cp, C.c_void_p(d_workspace), ws_bytes, C.c_void_p(stream), C.byref(h))
+    return rc, h
+
+
+def ep_load_step(h) -> tuple:
+    st = ep_step_stats()
+    rc = lib().ep_load_step(h, C.byref(st))
+    return rc, st.as_dict()
+
+
+def ep_sweep(h, n: int) -> tuple:
+    r = C.c_double(0)
+    rc = lib().ep_sweep(h, n, C.byref(r))
+    return rc, r.value
+
+
+def ep_residual(h) -> tuple:
+    r = ep_residual_info()
+    rc = lib().ep_residual(h, C.byref(r))
+    return rc, {k: getattr(r, k) for k, _ in r._fields_}
+
+
+def ep_field_shape(h, field: int) -> tuple:
+    shp = (C.c_int * 3)()
+    n = lib().ep_field_shape(h, field, shp)
+    return n, tuple(shp)
+
+
+def ep_fields(h, field: int, direction: int, host: np.ndarray) -> int:
+    assert host.dtype == np.float64 and host.flags.c_contiguous
+    return lib().ep_fields(h, field, direction, host.ctypes.data_as(C.POINTER(C.c_double)), host.size)
+
+
+def ep_destroy(h) -> None:
+    lib().ep_destroy(h)
+
+
+def ep_last_error(h) -> str:
+    return lib().ep_last_error(h).decode()
+
+
+# ---- convenience -----------------------------------------------------------
+def params_from_model(m, precision: int = EP_FP64, sweep: int = EP_SWEEP_AUTO,
+                      fp32_switch: float = 0.0) -> ep_params:
+    p = ep_params()
+    p.ndim, p.nx, p.ny = m.ndim, m.nx, m.ny
+    p.nz = m.nz if m.ndim == 3 else 1
+    p.lx, p.ly, p.lz = m.lx, m.ly, m.lz
+    p.bulk, p.shear, p.visc = m.bulk, m.shear, m.visc
+    p.phi_deg, p.psi_deg, p.dt = m.phi_deg, m.psi_deg, m.dt
+    for q in range(3):
+        p.erate[q] = m.erate[q]
+    p.tol, p.max_iter, p.n_check = m.tol, m.max_iter, m.n_check
+    p.re, p.r, p.cfl = m.re, m.r, m.cfl
+    p.precision, p.sweep, p.fp32_switch = precision, sweep, fp32_switch
+    return p
+
+
+class EpError(RuntimeError):
+    pass
+
+
+class Solver:
+    """One model on the GPU (device memory from torch, work on its stream)."""
+
+    def __init__(self, model, cohesion: Optional[np.ndarray] = None, precision: int = EP_FP64,
+                 sweep: int = EP_SWEEP_AUTO, fp32_switch: float = 0.0, device: str = "cuda:0",
+                 stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise EpError("no GPU visible: the solver runs only on the device")
+        self.model = model
+        self.params = params_from_model(model, precision, sweep, fp32_switch)
+        self.ws_bytes = ep_workspace_size(self.params)
+        self.torch = torch
+        self.device = torch.device(device)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        base = (base + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        if cohesion is None:
+            from ep_workloads import cohesion_field
+            cohesion = cohesion_field(model)
+        with torch.cuda.device(self.device):
+            rc, h = ep_init(self.params, cohesion, base, self.ws_bytes, self.stream.cuda_stream)
+        if rc != EP_OK:
+            raise EpError(f"ep_init failed with {rc}")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            ep_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc not in (EP_OK,):
+            raise EpError(f"{what} failed with {rc}: {ep_last_error(self.h)}")
+
+    def load_step(self) -> dict:
+        rc, st = ep_load_step(self.h)
+        if rc not in (EP_OK, EP_ENOTCONV, EP_EDIVERGED):
+            self._check(rc, "ep_load_step")
+        return st
+
+    def sweep(self, n: int = 1) -> float:
+        rc, r = ep_sweep(self.h, n)
+        self._check(rc, "ep_sweep")
+        return r
+
+    def residual(self) -> dict:
+        rc, r = ep_residual(self.h)
+        self._check(rc, "ep_residual")
+        return r
+
+    def size(self, name: str) -> int:
+        return ep_field_shape(self.h, FIELD_ID[name])[0]
+
+    def get(self, name: str) -> np.ndarray:
+        n = self.size(name)
+        out = np.zeros(max(n, 0), dtype=np.float64)
+        if n > 0:
+            self._check(ep_fields(self.h, FIELD_ID[name], EP_GET, out), f"get {name}")
+        return out
+
+    def set(self, name: str, values) -> None:
+        a = np.ascontiguousarray(values, dtype=np.float64).ravel()
+        self._check(ep_fields(self.h, FIELD_ID[name], EP_SET, a), f"set {name}")
+
+    def fields(self, names=None) -> Dict[str, np.ndarray]:
+        names = names or [n for n in FIELDS if self.size(n) > 0]
+        return {n: self.get(n) for n in names}
+
+    def enable_timing(self, on: bool = True) -> None:
+        self._check(lib().ep_enable_timing(self.h, 1 if on else 0), "ep_enable_timing")
+
+    def sweep_timing(self, precision: int) -> tuple:
+        ms, n = C.c_double(0), C.c_long(0)
+        self._check(lib().ep_sweep_timing(self.h, precision, C.byref(ms), C.byref(n)), "ep_sweep_timing")
+        return ms.value, n.value
