@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Benchmark of the per-increment elasto-plastic PT solve on one MI355X.
+
+A step is one load increment: prologue, pseudo-transient sweeps until the
+normalised residual meets the tolerance (1e-6), epilogue (FP64 accumulators,
+diagnostics).  The default workload is the 3D 255^3 pure-shear model with a
+spherical weak inclusion (K = 2, G = 1, phi = 30, strain increment 5e-5 per
+step), FP32 iteration fields with FP64 accumulation and norms.  W warm-up
+increments run untimed (they also carry the model past the onset of yield),
+then K increments are timed.
+
+value    = effective GB/s: algorithmic bytes of all sweeps of the timed
+           increments / wall time (25 field accesses per cell per 3D sweep,
+           at the precision of each sweep)
+roofline = the sweep kernel alone: algorithmic bytes per sweep / average
+           sweep duration from HIP events on the solver's stream
+cpu_baseline = the FP64 oracle on the host cores, a bounded number of sweeps
+           of the same grid, in the same unit.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "effective GB/s per iteration sweep (% HBM peak); s and iters per load step @ res 1e-6"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from ep_workloads import c1_small_2d, c2_2d, c3_3d, c5_3d
+    if name == "3d-255":
+        return c3_3d(255), "3d-255^3 pure shear, spherical weak inclusion r=0.1L (c=0.5c0), K=2, G=1, phi=30, psi=0, strain increment 5e-5, tol 1e-6"
+    if name == "3d-255-K1e3":
+        return c3_3d(255, bulk=1e3), "3d-255^3 as above with K=1e3 (nearly incompressible)"
+    if name == "2d-1023":
+        return c2_2d(0), "2d-1023^2 pure shear, circular weak inclusion r=0.1L offset from seed 0, tol 1e-6"
+    if name == "3d-511":
+        return c5_3d(), "3d-511^3 pure shear, spherical weak inclusion, strain increment 5e-5, tol 1e-6"
+    if name.startswith("3d-"):
+        n = int(name[3:])
+        return c3_3d(n), f"3d-{n}^3 pure shear, spherical weak inclusion"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def bytes_per_cell(ndim, prec_bytes):
+    # updated fields read + written, previous-increment stresses and cohesion read
+    return (25 if ndim == 3 else 17) * prec_bytes
+
+
+def kernel_sources_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2305_01701_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_name, prec):
+    """HBM bytes per sweep from the committed rocprof counter summary, or None
+    when the kernels changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload_name}_{prec}.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_sources_sha256_16") != kernel_sources_hash():
+        return None
+    return d.get("hbm_bytes_per_sweep")
+
+
+def cpu_baseline(m, budget_s):
+    from oracle import build as ob
+    if not os.path.exists(ob.LIB):
+        ob.build()
+    from oracle.oracle import Oracle
+    o = Oracle(m)
+    o.sweep()                      # first touch of the arrays
+    n, t0 = 0, time.perf_counter()
+    while True:
+        o.sweep()
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or n >= 200:
+            break
+    o.close()
+    a_eff = bytes_per_cell(m.ndim, 8) * m.n_cells
+    return {"value": round(a_eff * n / el / 1e9, 3), "unit": "GB/s", "cores": Oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{n} PT sweeps of the {m.name} grid from its initial state, FP64 "
+                      f"({el / n * 1e3:.1f} ms per sweep)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed load increments")
+    ap.add_argument("--warmup", type=int, default=12, help="untimed load increments before timing")
+    ap.add_argument("--workload", default="3d-255")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--sweep", default="auto", choices=["auto", "fused", "unfused"])
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this solver has no multi-GPU path "
+              "(the domain-decomposition design is described but not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2305_01701_amd import ep as E
+
+    m, desc = workload(args.workload)
+    m = m.with_(max_iter=2_000_000)
+    prec = E.EP_FP32_FIELDS if args.precision == "fp32" else E.EP_FP64
+    sweep = {"auto": E.EP_SWEEP_AUTO, "fused": E.EP_SWEEP_FUSED, "unfused": E.EP_SWEEP_UNFUSED}[args.sweep]
+    log("workload", m.name, "cells", m.n_cells, "precision", args.precision, "sweep", args.sweep)
+    s = E.Solver(m, precision=prec, sweep=sweep)
+    log("workspace", f"{s.ws_bytes / 2**30:.2f} GiB")
+
+    for n in range(args.warmup):
+        st = s.load_step()
+        log(f"warmup {n + 1}/{args.warmup}: status {st['status']} iters {st['iters']} "
+            f"(fp32 {st['iters_fp32']}) yield {st['n_yield']} {st['seconds']:.3f}s")
+
+    s.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for n in range(args.steps):
+        st = s.load_step()
+        stats.append(st)
+        log(f"step {n + 1}/{args.steps}: status {st['status']} iters {st['iters']} "
+            f"(fp32 {st['iters_fp32']}) yield {st['n_yield']} resid/ref {st['resid'] / st['ref']:.2e} "
+            f"{st['seconds']:.3f}s")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    it32 = sum(st["iters_fp32"] for st in stats)
+    it64 = sum(st["iters"] - st["iters_fp32"] for st in stats)
+    a32 = bytes_per_cell(m.ndim, 4) * m.n_cells
+    a64 = bytes_per_cell(m.ndim, 8) * m.n_cells
+    value = (it32 * a32 + it64 * a64) / wall / 1e9 if wall > 0 else 0.0
+
+    # roofline of the dominant sweep
+    use32 = it32 >= it64
+    ms, nsw = s.sweep_timing(E.EP_FP32_FIELDS if use32 else E.EP_FP64)
+    a_dom = a32 if use32 else a64
+    achieved = a_dom / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    traffic = measured_traffic(args.workload, "fp32" if use32 else "fp64")
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": ("fp32" if use32 else "fp64") + " PT sweep", "sweeps_timed": nsw,
+            "avg_sweep_ms": round(ms, 4), "algorithmic_bytes_per_sweep": a_dom}
+    s.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(m, args.cpu_budget)
+        log("cpu baseline", cpu)
+
+    iters = it32 + it64
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall / max(args.steps, 1) * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == E.EP_FP32_FIELDS else "f64", "data": "synthetic",
+        "config": {"workload": desc, "cells": m.n_cells, "increments_timed": f"{args.warmup + 1}..{args.warmup + args.steps}",
+                   "precision": args.precision, "sweep": args.sweep},
+        "hbm_frac": round(value / HBM_PEAK_GBS, 4),
+        "s_per_step": round(wall / max(args.steps, 1), 4),
+        "iters_per_step": round(iters / max(args.steps, 1), 1),
+        "iters_fp32_per_step": round(it32 / max(args.steps, 1), 1),
+        "failed_steps": sum(1 for st in stats if st["status"] != 0),
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -79,7 +79,9 @@ typedef struct ep_params {
     int    precision;        /* EP_FP64 or EP_FP32_FIELDS */
     int    sweep;            /* EP_SWEEP_* */
     double fp32_switch;      /* FP32 mode: leave FP32 when the normalised residual
-                                is below this (0: 10 * tol) or stops improving */
+                                is below this (0: 10 * tol) ... */
+    int    fp32_stall;       /* ... or has not halved for this many checks
+                                (0: 16 max(nx,ny,nz) / n_check; < 0: never) */
 } ep_params;
 
 typedef struct ep_step_stats {
@@ -96,6 +98,7 @@ typedef struct ep_step_stats {
     long long n_yield;       /* cells on the yield surface in the accepted state */
     double max_violation;    /* max over cells of tauII(stored stresses) - (A p + B c) */
     double seconds;          /* wall time of the call */
+    double fp32_exit;        /* normalised residual when FP32 handed over (0 in FP64 mode) */
 } ep_step_stats;
 
 typedef struct ep_residual_info {
@@ -140,13 +143,21 @@ int ep_init(const ep_params* p, const double* cohesion, void* d_workspace, size_
             void* stream, ep_handle** out);
 
 /* Solve one load increment: save the increment's starting stresses (p^,
- * tau^), iterate PT sweeps from the previous velocities until the residual
+ * tau^); evaluate the physical stresses of the previous velocities (the plain
+ * guess) -- their momentum residual is R_ref and they are the pseudo-time
+ * starting point of p and tau; iterate PT sweeps until the residual
  * (momentum L-inf combined with the pressure and deviator pseudo-rates, see
- * the paper's convergence section) is at most tol * ref, then add v dt to
+ * the paper's convergence section) is at most tol * ref; then add v dt to
  * the displacement and the strain-rate increments to the accumulated
  * strains.  On EP_ENOTCONV / EP_EDIVERGED the state is rolled back to the
  * increment start and st is still filled.  st may be NULL. */
 int ep_load_step(ep_handle* h, ep_step_stats* st);
+
+/* Residual history of the last ep_load_step: for each check, the normalised
+ * residual (resid / ref) and the precision of the sweeps that produced it
+ * (EP_FP64 or EP_FP32_FIELDS).  Copies at most cap entries; returns the
+ * number of checks recorded (may exceed cap), or EP_EINVAL. */
+int ep_step_history(const ep_handle* h, double* resid, int* precision, int cap);
 
 /* Run n PT sweeps on the current state without the increment prologue or
  * epilogue (the previous-increment stresses are whatever ep_fields set or

@@ -33,6 +33,8 @@
  * is not taken as converged.  An increment stops when this is at most
  * tol * max(R_ref, 2 G max|erate| dt / L), R_ref being the momentum residual
  * of the physical stresses of the plain guess (pseudo-time terms removed).
+ * Those physical stresses are also the pseudo-time starting point of p and
+ * tau; velocities start from the previous increment's.
  *
  * PT parameters (equations for rho~, G~, K~, Vp and the optimal Re, r): the
  * viscosity in rho~ is the visco-elastic eta = 1/(1/(G dt) + 1/mu_s),
@@ -772,6 +774,20 @@ int orc_load_step(orc_state* s, orc_stats* st)
     double dsig = 2.0 * s->prm.shear * emax * s->prm.dt;
     st->r_ref = orc_sweep(s, 1);
     st->ref = fmax(st->r_ref, dsig / s->L);
+    /* the pseudo-time iteration starts from the physical stresses of the
+     * guessed velocities (the evaluation above), not from the previous
+     * increment's stresses: same fixed point, no pseudo-time relaxation of
+     * stresses that the guess already determines */
+    {
+        long nc = n_cells(s);
+        copy_n(s->p, s->pn, nc);
+        copy_n(s->txx, s->txxn, nc);
+        copy_n(s->tyy, s->tyyn, nc);
+        copy_n(s->tzz, s->tzzn, s->ndim == 3 ? nc : 0);
+        copy_n(s->txy, s->txyn, n_xy(s));
+        copy_n(s->txz, s->txzn, n_xz(s));
+        copy_n(s->tyz, s->tyzn, n_yz(s));
+    }
 
     const int nchk = s->prm.n_check;
     int status = -4;

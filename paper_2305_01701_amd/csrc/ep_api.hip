@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -44,6 +45,8 @@ struct ep_handle {
     hipEvent_t ev0, ev1;
     double t_ms[2];
     long t_n[2];
+    std::vector<double> hist_r;
+    std::vector<int> hist_p;
     char err[512];
 };
 
@@ -605,6 +608,13 @@ int ep_load_step(ep_handle* h, ep_step_stats* st)
     if ((rc = read_red(h, red))) return rc;
     st->r_ref = red[RED_MOM];
     st->ref = std::fmax(st->r_ref, h->dsig_ref / h->L);
+    // the physical stresses just written to the other buffer are the
+    // pseudo-time starting point; the velocities carry over unchanged
+    for (int d = 0; d < h->ndim; ++d)
+        launch_copy(h->it64[1 - h->cur64][F_VX + d], h->it64[h->cur64][F_VX + d], h->nelem, h->st);
+    h->cur64 = 1 - h->cur64;
+    h->hist_r.clear();
+    h->hist_p.clear();
 
     // ---- PT iterations ------------------------------------------------------
     const double tol_abs = h->prm.tol * st->ref;
@@ -612,7 +622,8 @@ int ep_load_step(ep_handle* h, ep_step_stats* st)
     bool use32 = h->fp32;
     if (use32) ensure_it32(h);
     const int nmax = std::max(h->nx, std::max(h->ny, h->nz));
-    const int stall_checks = std::max(8, 16 * nmax / h->n_check);
+    const int stall_checks = h->prm.fp32_stall > 0 ? h->prm.fp32_stall
+                           : h->prm.fp32_stall < 0 ? INT_MAX : std::max(8, 16 * nmax / h->n_check);
     double best = INFINITY;
     int since_best = 0;
     int iters = 0, iters32 = 0;
@@ -627,6 +638,8 @@ int ep_load_step(ep_handle* h, ep_step_stats* st)
         if (use32) iters32 += nb;
         resid = red[RED_RESID];
         vmax = red[RED_VMAX];
+        h->hist_r.push_back(resid / st->ref);
+        h->hist_p.push_back(use32 ? EP_FP32_FIELDS : EP_FP64);
         if (!(resid <= 1e8 * st->ref)) {
             status = EP_EDIVERGED;
             break;
@@ -641,6 +654,7 @@ int ep_load_step(ep_handle* h, ep_step_stats* st)
             if (resid <= sw || since_best >= stall_checks) {
                 ensure_it64(h);      // continue from the FP32 state in FP64
                 use32 = false;
+                st->fp32_exit = resid / st->ref;
             }
             continue;
         }
@@ -679,6 +693,17 @@ int ep_load_step(ep_handle* h, ep_step_stats* st)
     st->max_violation = red[RED_VIOL] - 1.0;
     st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return EP_OK;
+}
+
+int ep_step_history(const ep_handle* h, double* resid, int* precision, int cap)
+{
+    if (!h || cap < 0) return EP_EINVAL;
+    const int n = (int)h->hist_r.size();
+    for (int q = 0; q < n && q < cap; ++q) {
+        if (resid) resid[q] = h->hist_r[q];
+        if (precision) precision[q] = h->hist_p[q];
+    }
+    return n;
 }
 
 long ep_field_shape(const ep_handle* h, int field, int shape[3])

@@ -34,7 +34,7 @@ FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
 # every symbol include/ep.h declares
 SYMBOLS = ["ep_abi_version", "ep_workspace_size", "ep_init", "ep_load_step", "ep_sweep",
            "ep_residual", "ep_fields", "ep_field_shape", "ep_destroy", "ep_last_error",
-           "ep_enable_timing", "ep_sweep_timing"]
+           "ep_enable_timing", "ep_sweep_timing", "ep_step_history"]
 
 
 class ep_params(C.Structure):
@@ -47,6 +47,7 @@ class ep_params(C.Structure):
         ("max_iter", C.c_int), ("n_check", C.c_int),
         ("re", C.c_double), ("r", C.c_double), ("cfl", C.c_double),
         ("precision", C.c_int), ("sweep", C.c_int), ("fp32_switch", C.c_double),
+        ("fp32_stall", C.c_int),
     ]
 
 
@@ -56,6 +57,7 @@ class ep_step_stats(C.Structure):
         ("r_ref", C.c_double), ("ref", C.c_double), ("resid", C.c_double), ("eps_rel", C.c_double),
         ("sxx_centre", C.c_double), ("sxx_left", C.c_double), ("sxx_right", C.c_double),
         ("n_yield", C.c_longlong), ("max_violation", C.c_double), ("seconds", C.c_double),
+        ("fp32_exit", C.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -94,6 +96,7 @@ def lib():
         L.ep_last_error.argtypes = [vp]
         L.ep_enable_timing.argtypes = [vp, C.c_int]
         L.ep_sweep_timing.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_long)]
+        L.ep_step_history.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_int]
         _lib = L
     return _lib
 
@@ -157,8 +160,17 @@ def ep_last_error(h) -> str:
 
 
 # ---- convenience -----------------------------------------------------------
+def ep_step_history(h, cap: int = 1 << 20) -> tuple:
+    r = np.zeros(cap, dtype=np.float64)
+    pr = np.zeros(cap, dtype=np.int32)
+    n = lib().ep_step_history(h, r.ctypes.data_as(C.POINTER(C.c_double)),
+                              pr.ctypes.data_as(C.POINTER(C.c_int)), cap)
+    n = min(n, cap)
+    return r[:n].copy(), pr[:n].copy()
+
+
 def params_from_model(m, precision: int = EP_FP64, sweep: int = EP_SWEEP_AUTO,
-                      fp32_switch: float = 0.0) -> ep_params:
+                      fp32_switch: float = 0.0, fp32_stall: int = 0) -> ep_params:
     p = ep_params()
     p.ndim, p.nx, p.ny = m.ndim, m.nx, m.ny
     p.nz = m.nz if m.ndim == 3 else 1
@@ -169,7 +181,7 @@ def params_from_model(m, precision: int = EP_FP64, sweep: int = EP_SWEEP_AUTO,
         p.erate[q] = m.erate[q]
     p.tol, p.max_iter, p.n_check = m.tol, m.max_iter, m.n_check
     p.re, p.r, p.cfl = m.re, m.r, m.cfl
-    p.precision, p.sweep, p.fp32_switch = precision, sweep, fp32_switch
+    p.precision, p.sweep, p.fp32_switch, p.fp32_stall = precision, sweep, fp32_switch, fp32_stall
     return p
 
 
@@ -181,13 +193,13 @@ class Solver:
     """One model on the GPU (device memory from torch, work on its stream)."""
 
     def __init__(self, model, cohesion: Optional[np.ndarray] = None, precision: int = EP_FP64,
-                 sweep: int = EP_SWEEP_AUTO, fp32_switch: float = 0.0, device: str = "cuda:0",
-                 stream=None):
+                 sweep: int = EP_SWEEP_AUTO, fp32_switch: float = 0.0, fp32_stall: int = 0,
+                 device: str = "cuda:0", stream=None):
         import torch
         if not torch.cuda.is_available():
             raise EpError("no GPU visible: the solver runs only on the device")
         self.model = model
-        self.params = params_from_model(model, precision, sweep, fp32_switch)
+        self.params = params_from_model(model, precision, sweep, fp32_switch, fp32_stall)
         self.ws_bytes = ep_workspace_size(self.params)
         self.torch = torch
         self.device = torch.device(device)
@@ -229,6 +241,10 @@ class Solver:
         rc, r = ep_sweep(self.h, n)
         self._check(rc, "ep_sweep")
         return r
+
+    def history(self) -> tuple:
+        """(normalised residual, precision) at each check of the last increment."""
+        return ep_step_history(self.h)
 
     def residual(self) -> dict:
         rc, r = ep_residual(self.h)
