@@ -774,6 +774,11 @@ int orc_load_step(orc_state* s, orc_stats* st)
     double dsig = 2.0 * s->prm.shear * emax * s->prm.dt;
     st->r_ref = orc_sweep(s, 1);
     st->ref = fmax(st->r_ref, dsig / s->L);
+    if (!(st->r_ref <= DBL_MAX)) {           /* NaN / Inf in the starting state */
+        st->status = -5;
+        roll_back(s);
+        return -5;
+    }
     /* the pseudo-time iteration starts from the physical stresses of the
      * guessed velocities (the evaluation above), not from the previous
      * increment's stresses: same fixed point, no pseudo-time relaxation of

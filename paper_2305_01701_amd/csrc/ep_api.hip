@@ -26,7 +26,7 @@ struct ep_handle {
     long sz, nelem;
     double dx, dy, dz, eta, gdtau, kdtau, dtrho, A, B, L, h, inv_mus, dsig_ref;
     int n_check;
-    bool fp32, fused;
+    bool fp32, fused32, fused64;
     double* it64[2][F_NIT];
     int cur64;
     double* old64[O_N];
@@ -228,6 +228,8 @@ SweepArgs<R> make_args(const ep_handle* h, R* const* from, R* const* to, R* cons
     a.igd = (R)igd;
     a.ikd = (R)ikd;
     a.D = (R)(igt + igd + h->inv_mus);
+    a.invD = (R)(1.0 / (igt + igd + h->inv_mus));
+    a.ikk = (R)(1.0 / (ikt + ikd));
     a.dtrho = (R)h->dtrho;
     a.A = (R)h->A;
     a.B = (R)h->B;
@@ -248,11 +250,12 @@ SweepArgs<float> args32(const ep_handle* h, int from)
 template <typename R>
 void launch_sweep(const ep_handle* h, const SweepArgs<R>& a, int mode)
 {
+    const bool fused = sizeof(R) == 4 ? h->fused32 : h->fused64;
     if (h->ndim == 2) {
-        if (h->fused) launch_sweep_fused_2d<R>(a, mode, h->st);
+        if (fused) launch_sweep_fused_2d<R>(a, mode, h->st);
         else launch_sweep_unfused_2d<R>(a, mode, h->st);
     } else {
-        if (h->fused) launch_sweep_fused_3d<R>(a, mode, h->st);
+        if (fused) launch_sweep_fused_3d<R>(a, mode, h->st);
         else launch_sweep_unfused_3d<R>(a, mode, h->st);
     }
 }
@@ -471,11 +474,10 @@ int ep_init(const ep_params* p, const double* cohesion, void* d_workspace, size_
     h->g.sy = h->sy;
     h->g.sz = h->sz;
     h->g.nelem = h->nelem;
-    h->fused = p->sweep != EP_SWEEP_UNFUSED && fused_available(p->ndim, h->fp32);
-    if (p->sweep == EP_SWEEP_FUSED && !h->fused) {
-        delete h;
-        return EP_EINVAL;
-    }
+    // EP_SWEEP_AUTO takes, per precision, the faster implementation measured on
+    // MI355X; FUSED / UNFUSED force one for both precisions
+    h->fused32 = p->sweep == EP_SWEEP_FUSED || (p->sweep == EP_SWEEP_AUTO && fused_preferred(p->ndim, true));
+    h->fused64 = p->sweep == EP_SWEEP_FUSED || (p->sweep == EP_SWEEP_AUTO && fused_preferred(p->ndim, false));
     h->cur64 = 0;
     h->cur32 = 0;
     auto fail = [&](int code) { delete h; return code; };
@@ -608,6 +610,12 @@ int ep_load_step(ep_handle* h, ep_step_stats* st)
     if ((rc = read_red(h, red))) return rc;
     st->r_ref = red[RED_MOM];
     st->ref = std::fmax(st->r_ref, h->dsig_ref / h->L);
+    if (!(st->r_ref <= 1e300)) {            // NaN / Inf in the starting state
+        st->status = EP_EDIVERGED;
+        roll_back(h);
+        st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return EP_EDIVERGED;
+    }
     // the physical stresses just written to the other buffer are the
     // pseudo-time starting point; the velocities carry over unchanged
     for (int d = 0; d < h->ndim; ++d)

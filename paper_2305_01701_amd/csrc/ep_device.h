@@ -10,6 +10,11 @@ namespace ep {
 
 __device__ __forceinline__ double nan_to_inf(double v) { return (v <= DBL_MAX) ? v : INFINITY; }
 
+// Running maximum that keeps a NaN once it has seen one (fmax drops NaN
+// arguments, which would hide a diverging state from the residual check).
+template <typename T>
+__device__ __forceinline__ T nmax(T acc, T x) { return (x > acc || x != x) ? x : acc; }
+
 // Max over a wave64 (all lanes get the result).
 __device__ __forceinline__ double wave_max(double v)
 {
@@ -75,6 +80,33 @@ __device__ __forceinline__ R centre_lambda(R J2, R D, R p, R c, R A, R B, R& lam
         tii = Y;
     }
     return lam;
+}
+
+// Reciprocal and square root of the fused sweeps: the hardware
+// approximations (about 1 ulp) in FP32, IEEE operations in FP64.
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fast_sqrt(double x) { return sqrt(x); }
+
+// Radial return in scale form.  With tauII_tr = sqrt(J2)/D and the bound
+// Y = max(0, A p + B c): elastic (tauII_tr <= Y) gives Lambda = 0 and the
+// factor 1/(D + Lambda) = 1/D; yielding gives Lambda = sqrt(J2)/Y - D and
+// 1/(D + Lambda) = Y/sqrt(J2), so the returned deviator T Y/sqrt(J2) lies on
+// the yield surface.  Same quantities as centre_lambda, one root and one
+// reciprocal.
+template <typename R>
+__device__ __forceinline__ R return_scale(R J2, R D, R invD, R p, R c, R A, R B, R& lam)
+{
+    R Y = A * p + B * c;
+    Y = Y > R(0) ? Y : R(0);
+    const R sq = fast_sqrt(J2);
+    if (sq * invD > Y) {
+        lam = sq * fast_rcp(Y) - D;
+        return Y * fast_rcp(sq);
+    }
+    lam = R(0);
+    return invD;
 }
 
 }  // namespace ep

@@ -37,6 +37,8 @@ struct SweepArgs {
     R igt, ikt;            // 1/(G~ dtau), 1/(K~ dtau); 0 for a physical evaluation
     R igd, ikd;            // 1/(G dt), 1/(K dt)
     R D;                   // igt + igd + 1/mu_s
+    R invD;                // 1 / D
+    R ikk;                 // 1 / (ikt + ikd)
     R dtrho;               // dtau / rho~
     R A, B;                // Drucker-Prager constants
     R rK, rG;              // pseudo-rate -> residual factors: K dt/(K~dtau L), eta/(G~dtau L)
@@ -52,7 +54,8 @@ template <typename R> void launch_sweep_unfused_2d(const SweepArgs<R>& a, int mo
 template <typename R> void launch_sweep_unfused_3d(const SweepArgs<R>& a, int mode, hipStream_t s);
 template <typename R> void launch_sweep_fused_2d(const SweepArgs<R>& a, int mode, hipStream_t s);
 template <typename R> void launch_sweep_fused_3d(const SweepArgs<R>& a, int mode, hipStream_t s);
-bool fused_available(int ndim, bool fp32);
+// Whether the automatic choice uses the fused sweep for this case.
+bool fused_preferred(int ndim, bool fp32);
 
 // ---- auxiliary kernels (ep_aux.hip) ----------------------------------------
 struct AuxGrid {

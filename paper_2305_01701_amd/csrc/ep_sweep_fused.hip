@@ -1,19 +1,620 @@
-// Fused PT sweep (one kernel per iteration).  Not yet available: the
-// runtime falls back to the unfused sweep.
+// Fused PT sweep: one kernel per pseudo-transient iteration.
+//
+// One iteration couples points up to two cells apart (v -> shear trial at
+// edges -> 4-point mean at centres -> Lambda at centres -> mean back to
+// edges -> velocity), so a workgroup that owns a tile recomputes a halo:
+//
+//   3D: a workgroup owns a TX x TY column of cells over a chunk of ZC
+//   z-planes and marches up the chunk.  Every quantity lives in LDS as 2D
+//   planes of (TX+4) x (TY+4) points (a 2-point x-y halo) in small ring
+//   buffers over z.  Step f of the march loads the velocity planes at z = f,
+//   forms the shear trials on the z-level f (xz, yz edges) and the plane
+//   f-1 (xy edges), the centre update of plane f-1 (pressure, deviator,
+//   return mapping), the new edge stresses of plane/level f-1, and the new
+//   velocities of plane f-2 (vx, vy) and level f-1 (vz).  Each field is read
+//   from and written to HBM once per sweep; the halo reads of neighbouring
+//   tiles are served by L2 (blocks are remapped so that spatial neighbours
+//   run on the same XCD).
+//   2D: the same stages on a single TX x TY tile.
+//
+// The arithmetic of every point is that of the unfused sweep (same formulas,
+// same Jacobi order: all reads are of iteration k, all writes iteration k+1).
 #include "ep_device.h"
 
 namespace ep {
 
-bool fused_available(int, bool) { return false; }
+namespace {
 
-template <typename R> void launch_sweep_fused_2d(const SweepArgs<R>& a, int mode, hipStream_t s)
+__device__ __forceinline__ int mod3(int f) { int r = f % 3; return r < 0 ? r + 3 : r; }
+__device__ __forceinline__ int mod2(int f) { return f & 1; }
+
+// Block index -> logical tile so that consecutive logical tiles run on the
+// same XCD (dispatch is round-robin over the 8 XCDs).  Bijective for any nb.
+__device__ __forceinline__ int xcd_remap(int b, int nb)
 {
-    launch_sweep_unfused_2d<R>(a, mode, s);
+    const int q = nb / 8, r = nb % 8;
+    const int x = b % 8, s = b / 8;
+    return x < r ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
 }
-template <typename R> void launch_sweep_fused_3d(const SweepArgs<R>& a, int mode, hipStream_t s)
+
+// ----------------------------------------------------------------------- 3D
+// Global data a march step needs is prefetched into registers one step
+// ahead (velocities of plane f+1, edge stresses of level f+1 and plane f,
+// centre data of plane f), so that HBM latency overlaps the LDS work of the
+// current step.  Each thread owns the same plane positions in every step.
+template <typename R, int TX, int TY, int ZC, int MODE>
+__global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, int nbx, int nby, int nbz)
 {
-    launch_sweep_unfused_3d<R>(a, mode, s);
+    constexpr int W = TX + 4, H = TY + 4, N = W * H, NT = TX * TY;
+    constexpr int NQ = (N + NT - 1) / NT;                  // plane positions per thread
+    constexpr int CW = TX + 2, CN = (TX + 2) * (TY + 2);   // centre region (1-cell halo)
+    constexpr int NR = (CN + NT - 1) / NT;
+    __shared__ R s_vx[3][N], s_vy[3][N], s_vz[2][N];
+    __shared__ R s_Txy[N], s_Txz[2][N], s_Tyz[2][N];
+    __shared__ R s_lam[2][N], s_p[2][N], s_sxx[2][N], s_syy[2][N];
+    __shared__ R s_nxy[2][N], s_nxz[2][N], s_nyz[2][N];
+    __shared__ double s_red[NT / 64 > 0 ? NT / 64 : 1];
+
+    const int lb = xcd_remap(blockIdx.x, nbx * nby * nbz);
+    const int bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
+    const int i0 = bx * TX, j0 = by * TY;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int k0 = bz * ZC, k1 = min(k0 + ZC, nz);
+    const long sy = a.sy, sz = a.sz;
+    const int tid = threadIdx.x;
+    const int hx = (i0 + TX == nx) ? 1 : 0;     // owns the x = nx row when nx % TX == 0
+    const int hy = (j0 + TY == ny) ? 1 : 0;
+    const bool last_z = (k1 == nz);
+
+    const R *vx = a.it[F_VX], *vy = a.it[F_VY], *vz = a.it[F_VZ];
+    const R *txz_k = a.it[F_TXZ], *tyz_k = a.it[F_TYZ], *txy_k = a.it[F_TXY];
+    const R *txz_o = a.old[O_TXZ], *tyz_o = a.old[O_TYZ], *txy_o = a.old[O_TXY];
+    const R *p_k = a.it[F_P], *txx_k = a.it[F_TXX], *tyy_k = a.it[F_TYY];
+    const R *p_o = a.old[O_P], *txx_o = a.old[O_TXX], *tyy_o = a.old[O_TYY], *coh = a.coh;
+    const R idx = a.idx, idy = a.idy, idz = a.idz, igt = a.igt, igd = a.igd, ikt = a.ikt, ikd = a.ikd;
+    const R D = a.D;
+
+    // per-thread positions: plane points q (S1, S2) and centre points r (S3)
+    int qi[NQ], qj[NQ];
+    bool qok[NQ];
+    for (int u = 0; u < NQ; ++u) {
+        const int q = tid + NT * u;
+        qok[u] = q < N;
+        qi[u] = i0 - 2 + q % W;
+        qj[u] = j0 - 2 + q / W;
+    }
+    int ri[NR], rj[NR];
+    bool rok[NR];
+    for (int u = 0; u < NR; ++u) {
+        const int r = tid + NT * u;
+        rok[u] = r < CN;
+        ri[u] = i0 - 1 + r % CW;
+        rj[u] = j0 - 1 + r / CW;
+    }
+
+    // prefetch registers (step g)
+    R fvx[NQ], fvy[NQ], fvz[NQ], fxz[NQ], fxzo[NQ], fyz[NQ], fyzo[NQ], fxy[NQ], fxyo[NQ];
+    R fp[NR], fpo[NR], fsx[NR], fsxo[NR], fsy[NR], fsyo[NR], fc[NR];
+    auto prefetch = [&](int g) {
+        const bool pl = g >= 0 && g < nz, lv = g >= 0 && g <= nz, inner = g >= 1 && g <= nz - 1;
+        const bool pm = g - 1 >= 0 && g - 1 < nz;
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {
+            const int i = qi[u], j = qj[u];
+            const long e = i + sy * j + sz * g;
+            const bool ok = qok[u];
+            fvx[u] = (ok && pl && i >= 0 && i <= nx && j >= 0 && j < ny) ? vx[e] : R(0);
+            fvy[u] = (ok && pl && i >= 0 && i < nx && j >= 0 && j <= ny) ? vy[e] : R(0);
+            fvz[u] = (ok && lv && i >= 0 && i < nx && j >= 0 && j < ny) ? vz[e] : R(0);
+            const bool exz = ok && inner && i >= 1 && i <= nx - 1 && j >= 0 && j < ny;
+            const bool eyz = ok && inner && j >= 1 && j <= ny - 1 && i >= 0 && i < nx;
+            fxz[u] = exz ? txz_k[e] : R(0);
+            fxzo[u] = exz ? txz_o[e] : R(0);
+            fyz[u] = eyz ? tyz_k[e] : R(0);
+            fyzo[u] = eyz ? tyz_o[e] : R(0);
+            const bool exy = ok && pm && i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1;
+            fxy[u] = exy ? txy_k[e - sz] : R(0);
+            fxyo[u] = exy ? txy_o[e - sz] : R(0);
+        }
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            const int i = ri[u], j = rj[u];
+            const long e = i + sy * j + sz * (g - 1);
+            const bool ok = rok[u] && pm && i >= 0 && i < nx && j >= 0 && j < ny;
+            fp[u] = ok ? p_k[e] : R(0);
+            fpo[u] = ok ? p_o[e] : R(0);
+            fsx[u] = ok ? txx_k[e] : R(0);
+            fsxo[u] = ok ? txx_o[e] : R(0);
+            fsy[u] = ok ? tyy_k[e] : R(0);
+            fsyo[u] = ok ? tyy_o[e] : R(0);
+            fc[u] = ok ? coh[e] : R(0);
+        }
+    };
+
+    double rmax = 0.0, mmax = 0.0, vmax = 0.0;   // combined, momentum-only, |v|
+
+    prefetch(k0 - 2);
+    for (int f = k0 - 2; f <= k1 + 1; ++f) {
+        // take over the data of step f, start loading step f+1
+        R cvx[NQ], cvy[NQ], cvz[NQ], cxz[NQ], cxzo[NQ], cyz[NQ], cyzo[NQ], cxy[NQ], cxyo[NQ];
+        R cp[NR], cpo[NR], csx[NR], csxo[NR], csy[NR], csyo[NR], cc[NR];
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {
+            cvx[u] = fvx[u]; cvy[u] = fvy[u]; cvz[u] = fvz[u];
+            cxz[u] = fxz[u]; cxzo[u] = fxzo[u]; cyz[u] = fyz[u]; cyzo[u] = fyzo[u];
+            cxy[u] = fxy[u]; cxyo[u] = fxyo[u];
+        }
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            cp[u] = fp[u]; cpo[u] = fpo[u]; csx[u] = fsx[u]; csxo[u] = fsxo[u];
+            csy[u] = fsy[u]; csyo[u] = fsyo[u]; cc[u] = fc[u];
+        }
+        if (f + 1 <= k1 + 1) prefetch(f + 1);
+
+        // ---- S1: velocities of plane f (vx, vy) and level f (vz) -------------
+        {
+            const bool ld_xy = f >= 0 && f < nz;
+            const bool ld_z = f >= 0 && f <= nz;
+            const int s3 = mod3(f), s2 = mod2(f);
+#pragma unroll
+            for (int u = 0; u < NQ; ++u) {
+                if (!qok[u]) continue;
+                const int q = tid + NT * u;
+                if (ld_xy) {
+                    s_vx[s3][q] = cvx[u];
+                    s_vy[s3][q] = cvy[u];
+                }
+                if (ld_z) s_vz[s2][q] = cvz[u];
+            }
+        }
+        __syncthreads();
+        // ---- S2: shear trials: xz, yz at level f; xy at plane f-1 ----------
+        {
+            const bool do_l = f >= k0 - 1 && f >= 0 && f <= nz;
+            const bool do_p = f - 1 >= k0 - 1 && f - 1 >= 0 && f - 1 < nz;
+            const int l = f, sl = mod2(l), cm = mod3(l), cp3 = mod3(l - 1), pm = mod3(f - 1);
+            const bool inner_l = l >= 1 && l <= nz - 1;
+#pragma unroll
+            for (int u = 0; u < NQ; ++u) {
+                const int q = tid + NT * u;
+                if (!qok[u] || q % W < 1 || q / W < 1) continue;
+                const int i = qi[u], j = qj[u];
+                if (do_l) {
+                    R txz = R(0), tyz = R(0);
+                    if (inner_l && i >= 1 && i <= nx - 1 && j >= 0 && j < ny) {
+                        R e2 = (s_vx[cm][q] - s_vx[cp3][q]) * idz + (s_vz[sl][q] - s_vz[sl][q - 1]) * idx;
+                        txz = cxz[u] * igt + cxzo[u] * igd + e2;
+                    }
+                    if (inner_l && j >= 1 && j <= ny - 1 && i >= 0 && i < nx) {
+                        R e2 = (s_vy[cm][q] - s_vy[cp3][q]) * idz + (s_vz[sl][q] - s_vz[sl][q - W]) * idy;
+                        tyz = cyz[u] * igt + cyzo[u] * igd + e2;
+                    }
+                    s_Txz[sl][q] = txz;
+                    s_Tyz[sl][q] = tyz;
+                }
+                if (do_p) {
+                    R t = R(0);
+                    if (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1) {
+                        R e2 = (s_vx[pm][q] - s_vx[pm][q - W]) * idy + (s_vy[pm][q] - s_vy[pm][q - 1]) * idx;
+                        t = cxy[u] * igt + cxyo[u] * igd + e2;
+                    }
+                    s_Txy[q] = t;
+                }
+            }
+        }
+        __syncthreads();
+        // ---- S3: centres of plane c = f-1 -----------------------------------
+        const int c = f - 1;
+        if (c >= k0 - 1 && c >= 0 && c < nz && c <= k1) {
+            const int cm = mod3(c), sc = mod2(c), sc1 = mod2(c + 1);
+#pragma unroll
+            for (int u = 0; u < NR; ++u) {
+                if (!rok[u]) continue;
+                const int r = tid + NT * u;
+                const int la = 1 + r % CW, lbb = 1 + r / CW;
+                const int q = la + W * lbb;
+                const int i = ri[u], j = rj[u];
+                if (!(i >= 0 && i < nx && j >= 0 && j < ny)) {
+                    s_lam[sc][q] = R(0);
+                    s_p[sc][q] = R(0);
+                    s_sxx[sc][q] = R(0);
+                    s_syy[sc][q] = R(0);
+                    continue;
+                }
+                R dvx = (s_vx[cm][q + 1] - s_vx[cm][q]) * idx;
+                R dvy = (s_vy[cm][q + W] - s_vy[cm][q]) * idy;
+                R dvz = (s_vz[sc1][q] - s_vz[sc][q]) * idz;
+                R div = dvx + dvy + dvz;
+                const R pk = cp[u], txk = csx[u], tyk = csy[u];
+                R pn = (pk * ikt + cpo[u] * ikd - div) * a.ikk;
+                R Txx = txk * igt + csxo[u] * igd + R(2) * (dvx - div / R(3));
+                R Tyy = tyk * igt + csyo[u] * igd + R(2) * (dvy - div / R(3));
+                R Tzz = -(Txx + Tyy);
+                R Txyb = R(0.25) * (s_Txy[q] + s_Txy[q + 1] + s_Txy[q + W] + s_Txy[q + W + 1]);
+                R Txzb = R(0.25) * (s_Txz[sc][q] + s_Txz[sc][q + 1] + s_Txz[sc1][q] + s_Txz[sc1][q + 1]);
+                R Tyzb = R(0.25) * (s_Tyz[sc][q] + s_Tyz[sc][q + W] + s_Tyz[sc1][q] + s_Tyz[sc1][q + W]);
+                R J2 = R(0.5) * (Txx * Txx + Tyy * Tyy + Tzz * Tzz) + Txyb * Txyb + Txzb * Txzb + Tyzb * Tyzb;
+                R lam;
+                const R sc_ = return_scale(J2, D, a.invD, pn, cc[u], a.A, a.B, lam);
+                R txx = Txx * sc_, tyy = Tyy * sc_;
+                s_lam[sc][q] = lam;
+                s_p[sc][q] = pn;
+                s_sxx[sc][q] = txx;
+                s_syy[sc][q] = tyy;
+                const bool own = la >= 2 && la < TX + 2 && lbb >= 2 && lbb < TY + 2 && c >= k0 && c < k1;
+                if (own) {
+                    const long e = i + sy * j + sz * c;
+                    a.nx_[F_P][e] = pn;
+                    a.nx_[F_TXX][e] = txx;
+                    a.nx_[F_TYY][e] = tyy;
+                    if (MODE == MODE_CHECK) {
+                        R dp = fabs(pn - pk) * a.rK;
+                        R dtx = fabs(txx - txk), dty = fabs(tyy - tyk), dtz = fabs((txx + tyy) - (txk + tyk));
+                        rmax = nmax(rmax, nmax((double)dp, (double)(nmax(nmax(dtx, dty), dtz) * a.rG)));
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // ---- S4: new edge stresses: xy at plane f-1, xz / yz at level f-1 ---
+        {
+            const int p = f - 1;
+            if (p >= k0 && p < k1) {
+                const int sp = mod2(p);
+                constexpr int EW = TX + 1, EN = (TX + 1) * (TY + 1);
+                for (int r = tid; r < EN; r += NT) {
+                    const int la = 2 + r % EW, lbb = 2 + r / EW;
+                    const int q = la + W * lbb;
+                    const int i = i0 - 2 + la, j = j0 - 2 + lbb;
+                    R t = R(0);
+                    if (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1) {
+                        R lv = R(0.25) * (s_lam[sp][q - W - 1] + s_lam[sp][q - W] + s_lam[sp][q - 1] + s_lam[sp][q]);
+                        t = s_Txy[q] * fast_rcp(D + lv);
+                    }
+                    s_nxy[sp][q] = t;
+                    if (la < TX + 2 + hx && lbb < TY + 2 + hy && i <= nx && j <= ny) {
+                        const long e = i + sy * j + sz * p;
+                        a.nx_[F_TXY][e] = t;
+                        if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)(fabs(t - a.it[F_TXY][e]) * a.rG));
+                    }
+                }
+            }
+            const int l = f - 1;
+            if (l >= k0 && l <= k1 && l >= 0 && l <= nz) {
+                const int sl = mod2(l), sm = mod2(l - 1);
+                const bool inner_l = l >= 1 && l <= nz - 1;
+                const bool own_l = l < k1 || (l == nz && last_z);
+                constexpr int EW = TX + 1, EN = (TX + 1) * (TY + 1);
+                for (int r = tid; r < EN; r += NT) {
+                    const int la = 2 + r % EW, lbb = 2 + r / EW;
+                    const int q = la + W * lbb;
+                    const int i = i0 - 2 + la, j = j0 - 2 + lbb;
+                    const long e = i + sy * j + sz * l;
+                    // xz edge (i, j) at level l: x-extent nx+1, y-extent ny
+                    if (lbb < TY + 2) {
+                        R t = R(0);
+                        if (inner_l && i >= 1 && i <= nx - 1 && j < ny) {
+                            R lv = R(0.25) * (s_lam[sm][q - 1] + s_lam[sm][q] + s_lam[sl][q - 1] + s_lam[sl][q]);
+                            t = s_Txz[sl][q] * fast_rcp(D + lv);
+                        }
+                        s_nxz[sl][q] = t;
+                        if (own_l && la < TX + 2 + hx && i <= nx && j < ny) {
+                            a.nx_[F_TXZ][e] = t;
+                            if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)(fabs(t - a.it[F_TXZ][e]) * a.rG));
+                        }
+                    }
+                    // yz edge (i, j) at level l: x-extent nx, y-extent ny+1
+                    if (la < TX + 2) {
+                        R t = R(0);
+                        if (inner_l && j >= 1 && j <= ny - 1 && i < nx) {
+                            R lv = R(0.25) * (s_lam[sm][q - W] + s_lam[sm][q] + s_lam[sl][q - W] + s_lam[sl][q]);
+                            t = s_Tyz[sl][q] * fast_rcp(D + lv);
+                        }
+                        s_nyz[sl][q] = t;
+                        if (own_l && lbb < TY + 2 + hy && i < nx && j <= ny) {
+                            a.nx_[F_TYZ][e] = t;
+                            if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)(fabs(t - a.it[F_TYZ][e]) * a.rG));
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // ---- S5: velocities: vx, vy at plane f-2, vz at level f-1 -----------
+        {
+            const int p = f - 2;
+            if (p >= k0 && p < k1) {
+                const int cm = mod3(p), sp = mod2(p), sp1 = mod2(p + 1);
+                constexpr int FW = TX + 1, FN = (TX + 1) * (TY + 1);
+                for (int r = tid; r < FN; r += NT) {
+                    const int la = 2 + r % FW, lbb = 2 + r / FW;
+                    const int q = la + W * lbb;
+                    const int i = i0 - 2 + la, j = j0 - 2 + lbb;
+                    const long e = i + sy * j + sz * p;
+                    if (la < TX + 2 + hx && lbb < TY + 2 && i <= nx && j < ny) {      // x-face
+                        R v = s_vx[cm][q];
+                        if (i >= 1 && i <= nx - 1) {
+                            R Rx = ((s_sxx[sp][q] - s_p[sp][q]) - (s_sxx[sp][q - 1] - s_p[sp][q - 1])) * idx
+                                 + (s_nxy[sp][q + W] - s_nxy[sp][q]) * idy + (s_nxz[sp1][q] - s_nxz[sp][q]) * idz;
+                            v = v + a.dtrho * Rx;
+                            mmax = nmax(mmax, (double)fabs(Rx));
+                        }
+                        if (MODE != MODE_PHYS) a.nx_[F_VX][e] = v;
+                        vmax = nmax(vmax, (double)fabs(v));
+                    }
+                    if (la < TX + 2 && lbb < TY + 2 + hy && i < nx && j <= ny) {      // y-face
+                        R v = s_vy[cm][q];
+                        if (j >= 1 && j <= ny - 1) {
+                            R Ry = (s_nxy[sp][q + 1] - s_nxy[sp][q]) * idx
+                                 + ((s_syy[sp][q] - s_p[sp][q]) - (s_syy[sp][q - W] - s_p[sp][q - W])) * idy
+                                 + (s_nyz[sp1][q] - s_nyz[sp][q]) * idz;
+                            v = v + a.dtrho * Ry;
+                            mmax = nmax(mmax, (double)fabs(Ry));
+                        }
+                        if (MODE != MODE_PHYS) a.nx_[F_VY][e] = v;
+                        vmax = nmax(vmax, (double)fabs(v));
+                    }
+                }
+            }
+            const int l = f - 1;
+            if (l >= 0 && ((l >= k0 && l < k1) || (l == nz && last_z))) {
+                const int sl = mod2(l), sm = mod2(l - 1);
+                const bool inner_l = l >= 1 && l <= nz - 1;
+                for (int r = tid; r < NT; r += NT) {
+                    const int la = 2 + r % TX, lbb = 2 + r / TX;
+                    const int q = la + W * lbb;
+                    const int i = i0 - 2 + la, j = j0 - 2 + lbb;
+                    if (i >= nx || j >= ny) continue;
+                    const long e = i + sy * j + sz * l;
+                    R v = s_vz[sl][q];
+                    if (inner_l) {
+                        R szu = -(s_sxx[sl][q] + s_syy[sl][q]) - s_p[sl][q];
+                        R szd = -(s_sxx[sm][q] + s_syy[sm][q]) - s_p[sm][q];
+                        R Rz = (s_nxz[sl][q + 1] - s_nxz[sl][q]) * idx + (s_nyz[sl][q + W] - s_nyz[sl][q]) * idy
+                             + (szu - szd) * idz;
+                        v = v + a.dtrho * Rz;
+                        mmax = nmax(mmax, (double)fabs(Rz));
+                    }
+                    if (MODE != MODE_PHYS) a.nx_[F_VZ][e] = v;
+                    vmax = nmax(vmax, (double)fabs(v));
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (MODE != MODE_UPDATE) {
+        block_max_to<NT>(mmax, a.red + RED_MOM, s_red);
+        if (MODE == MODE_CHECK) {
+            block_max_to<NT>(fmax(rmax, mmax), a.red + RED_RESID, s_red);
+            block_max_to<NT>(vmax, a.red + RED_VMAX, s_red);
+        }
+    }
 }
+
+// ----------------------------------------------------------------------- 2D
+template <typename R, int TX, int TY, int MODE>
+__global__ __launch_bounds__(TX * TY) void k_fused_2d(SweepArgs<R> a, int nbx, int nby)
+{
+    constexpr int W = TX + 4, H = TY + 4, N = W * H, NT = TX * TY;
+    __shared__ R s_vx[N], s_vy[N], s_Txy[N], s_lam[N], s_p[N], s_sxx[N], s_syy[N], s_nxy[N];
+    __shared__ double s_red[NT / 64 > 0 ? NT / 64 : 1];
+
+    const int lb = xcd_remap(blockIdx.x, nbx * nby);
+    const int bx = lb % nbx, by = lb / nbx;
+    const int i0 = bx * TX, j0 = by * TY;
+    const int nx = a.nx, ny = a.ny;
+    const long sy = a.sy;
+    const int tid = threadIdx.x;
+    const int hx = (i0 + TX == nx) ? 1 : 0;
+    const int hy = (j0 + TY == ny) ? 1 : 0;
+    const R idx = a.idx, idy = a.idy, igt = a.igt, igd = a.igd, ikt = a.ikt, ikd = a.ikd, D = a.D;
+    double rmax = 0.0, mmax = 0.0, vmax = 0.0;   // combined, momentum-only, |v|
+
+    // issue every global load of the tile up front (velocities, shear stresses
+    // of iteration k and of the increment start, centre data), then the stages
+    constexpr int NQ = (N + NT - 1) / NT;
+    constexpr int CW = TX + 2, CN = (TX + 2) * (TY + 2), NR = (CN + NT - 1) / NT;
+    R gvx[NQ], gvy[NQ], gxy[NQ], gxyo[NQ];
+    R gp[NR], gpo[NR], gsx[NR], gsxo[NR], gsy[NR], gsyo[NR], gc[NR];
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+        const int q = tid + NT * u;
+        const int i = i0 - 2 + q % W, j = j0 - 2 + q / W;
+        const long e = i + sy * j;
+        const bool ok = q < N;
+        gvx[u] = (ok && i >= 0 && i <= nx && j >= 0 && j < ny) ? a.it[F_VX][e] : R(0);
+        gvy[u] = (ok && i >= 0 && i < nx && j >= 0 && j <= ny) ? a.it[F_VY][e] : R(0);
+        const bool exy = ok && i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1;
+        gxy[u] = exy ? a.it[F_TXY][e] : R(0);
+        gxyo[u] = exy ? a.old[O_TXY][e] : R(0);
+    }
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+        const int r = tid + NT * u;
+        const int i = i0 - 1 + r % CW, j = j0 - 1 + r / CW;
+        const long e = i + sy * j;
+        const bool ok = r < CN && i >= 0 && i < nx && j >= 0 && j < ny;
+        gp[u] = ok ? a.it[F_P][e] : R(0);
+        gpo[u] = ok ? a.old[O_P][e] : R(0);
+        gsx[u] = ok ? a.it[F_TXX][e] : R(0);
+        gsxo[u] = ok ? a.old[O_TXX][e] : R(0);
+        gsy[u] = ok ? a.it[F_TYY][e] : R(0);
+        gsyo[u] = ok ? a.old[O_TYY][e] : R(0);
+        gc[u] = ok ? a.coh[e] : R(0);
+    }
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+        const int q = tid + NT * u;
+        if (q < N) {
+            s_vx[q] = gvx[u];
+            s_vy[q] = gvy[u];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+        const int q = tid + NT * u;
+        if (q >= N) continue;
+        const int la = q % W, lbb = q / W;
+        if (la < 1 || lbb < 1) continue;
+        const int i = i0 - 2 + la, j = j0 - 2 + lbb;
+        R t = R(0);
+        if (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1) {
+            R e2 = (s_vx[q] - s_vx[q - W]) * idy + (s_vy[q] - s_vy[q - 1]) * idx;
+            t = gxy[u] * igt + gxyo[u] * igd + e2;
+        }
+        s_Txy[q] = t;
+    }
+    __syncthreads();
+    {
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            const int r = tid + NT * u;
+            if (r >= CN) continue;
+            const int la = 1 + r % CW, lbb = 1 + r / CW;
+            const int q = la + W * lbb;
+            const int i = i0 - 2 + la, j = j0 - 2 + lbb;
+            if (!(i >= 0 && i < nx && j >= 0 && j < ny)) {
+                s_lam[q] = R(0);
+                s_p[q] = R(0);
+                s_sxx[q] = R(0);
+                s_syy[q] = R(0);
+                continue;
+            }
+            const long e = i + sy * j;
+            R dvx = (s_vx[q + 1] - s_vx[q]) * idx;
+            R dvy = (s_vy[q + W] - s_vy[q]) * idy;
+            R div = dvx + dvy;
+            const R pk = gp[u], txk = gsx[u], tyk = gsy[u];
+            R pn = (pk * ikt + gpo[u] * ikd - div) * a.ikk;
+            R Txx = txk * igt + gsxo[u] * igd + R(2) * (dvx - div / R(3));
+            R Tyy = tyk * igt + gsyo[u] * igd + R(2) * (dvy - div / R(3));
+            R Tb = R(0.25) * (s_Txy[q] + s_Txy[q + 1] + s_Txy[q + W] + s_Txy[q + W + 1]);
+            R J2 = R(0.5) * (Txx * Txx + Tyy * Tyy) + Tb * Tb;
+            R lam;
+            const R sc_ = return_scale(J2, D, a.invD, pn, gc[u], a.A, a.B, lam);
+            R txx = Txx * sc_, tyy = Tyy * sc_;
+            s_lam[q] = lam;
+            s_p[q] = pn;
+            s_sxx[q] = txx;
+            s_syy[q] = tyy;
+            if (la >= 2 && la < TX + 2 && lbb >= 2 && lbb < TY + 2) {
+                a.nx_[F_P][e] = pn;
+                a.nx_[F_TXX][e] = txx;
+                a.nx_[F_TYY][e] = tyy;
+                if (MODE == MODE_CHECK) {
+                    R dp = fabs(pn - pk) * a.rK;
+                    R dt = nmax(fabs(txx - txk), fabs(tyy - tyk)) * a.rG;
+                    rmax = nmax(rmax, nmax((double)dp, (double)dt));
+                }
+            }
+        }
+    }
+    __syncthreads();
+    {
+        constexpr int EW = TX + 1, EN = (TX + 1) * (TY + 1);
+        for (int r = tid; r < EN; r += NT) {
+            const int la = 2 + r % EW, lbb = 2 + r / EW;
+            const int q = la + W * lbb;
+            const int i = i0 - 2 + la, j = j0 - 2 + lbb;
+            R t = R(0);
+            if (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1) {
+                R lv = R(0.25) * (s_lam[q - W - 1] + s_lam[q - W] + s_lam[q - 1] + s_lam[q]);
+                t = s_Txy[q] * fast_rcp(D + lv);
+            }
+            s_nxy[q] = t;
+            if (la < TX + 2 + hx && lbb < TY + 2 + hy && i <= nx && j <= ny) {
+                const long e = i + sy * j;
+                a.nx_[F_TXY][e] = t;
+                if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)(fabs(t - a.it[F_TXY][e]) * a.rG));
+            }
+        }
+    }
+    __syncthreads();
+    {
+        constexpr int FW = TX + 1, FN = (TX + 1) * (TY + 1);
+        for (int r = tid; r < FN; r += NT) {
+            const int la = 2 + r % FW, lbb = 2 + r / FW;
+            const int q = la + W * lbb;
+            const int i = i0 - 2 + la, j = j0 - 2 + lbb;
+            const long e = i + sy * j;
+            if (la < TX + 2 + hx && lbb < TY + 2 && i <= nx && j < ny) {
+                R v = s_vx[q];
+                if (i >= 1 && i <= nx - 1) {
+                    R Rx = ((s_sxx[q] - s_p[q]) - (s_sxx[q - 1] - s_p[q - 1])) * idx + (s_nxy[q + W] - s_nxy[q]) * idy;
+                    v = v + a.dtrho * Rx;
+                    mmax = nmax(mmax, (double)fabs(Rx));
+                }
+                if (MODE != MODE_PHYS) a.nx_[F_VX][e] = v;
+                vmax = nmax(vmax, (double)fabs(v));
+            }
+            if (la < TX + 2 && lbb < TY + 2 + hy && i < nx && j <= ny) {
+                R v = s_vy[q];
+                if (j >= 1 && j <= ny - 1) {
+                    R Ry = ((s_syy[q] - s_p[q]) - (s_syy[q - W] - s_p[q - W])) * idy + (s_nxy[q + 1] - s_nxy[q]) * idx;
+                    v = v + a.dtrho * Ry;
+                    mmax = nmax(mmax, (double)fabs(Ry));
+                }
+                if (MODE != MODE_PHYS) a.nx_[F_VY][e] = v;
+                vmax = nmax(vmax, (double)fabs(v));
+            }
+        }
+    }
+    if (MODE != MODE_UPDATE) {
+        block_max_to<NT>(mmax, a.red + RED_MOM, s_red);
+        if (MODE == MODE_CHECK) {
+            block_max_to<NT>(fmax(rmax, mmax), a.red + RED_RESID, s_red);
+            block_max_to<NT>(vmax, a.red + RED_VMAX, s_red);
+        }
+    }
+}
+
+// tile shapes
+constexpr int T3X = 32, T3Y = 16, T3Z = 32;         // FP32 3D
+constexpr int D3X = 32, D3Y = 4, D3Z = 32;          // FP64 3D (LDS-limited)
+constexpr int T2X = 64, T2Y = 8;                    // 2D
+
+template <typename R> struct Tile3;
+template <> struct Tile3<float> { static constexpr int X = T3X, Y = T3Y, Z = T3Z; };
+template <> struct Tile3<double> { static constexpr int X = D3X, Y = D3Y, Z = D3Z; };
+
+template <typename R, int MODE>
+void run_3d(const SweepArgs<R>& a, hipStream_t s)
+{
+    constexpr int TX = Tile3<R>::X, TY = Tile3<R>::Y, ZC = Tile3<R>::Z;
+    const int nbx = (a.nx + TX - 1) / TX, nby = (a.ny + TY - 1) / TY, nbz = (a.nz + ZC - 1) / ZC;
+    k_fused_3d<R, TX, TY, ZC, MODE><<<nbx * nby * nbz, TX * TY, 0, s>>>(a, nbx, nby, nbz);
+}
+
+template <typename R, int MODE>
+void run_2d(const SweepArgs<R>& a, hipStream_t s)
+{
+    const int nbx = (a.nx + T2X - 1) / T2X, nby = (a.ny + T2Y - 1) / T2Y;
+    k_fused_2d<R, T2X, T2Y, MODE><<<nbx * nby, T2X * T2Y, 0, s>>>(a, nbx, nby);
+}
+
+}  // namespace
+
+// 3D FP64: the LDS footprint of the marching tile (8-byte planes) leaves too
+// few waves per CU; the unfused kernels are faster there.
+bool fused_preferred(int ndim, bool fp32) { return ndim == 2 || fp32; }
+
+template <typename R>
+void launch_sweep_fused_3d(const SweepArgs<R>& a, int mode, hipStream_t s)
+{
+    if (mode == MODE_UPDATE) run_3d<R, MODE_UPDATE>(a, s);
+    else if (mode == MODE_CHECK) run_3d<R, MODE_CHECK>(a, s);
+    else run_3d<R, MODE_PHYS>(a, s);
+}
+
+template <typename R>
+void launch_sweep_fused_2d(const SweepArgs<R>& a, int mode, hipStream_t s)
+{
+    if (mode == MODE_UPDATE) run_2d<R, MODE_UPDATE>(a, s);
+    else if (mode == MODE_CHECK) run_2d<R, MODE_CHECK>(a, s);
+    else run_2d<R, MODE_PHYS>(a, s);
+}
+
 template void launch_sweep_fused_2d<double>(const SweepArgs<double>&, int, hipStream_t);
 template void launch_sweep_fused_2d<float>(const SweepArgs<float>&, int, hipStream_t);
 template void launch_sweep_fused_3d<double>(const SweepArgs<double>&, int, hipStream_t);

@@ -60,8 +60,8 @@ __global__ __launch_bounds__(NT) void k_centre_2d(SweepArgs<R> a)
         a.lam[c] = lam;
         if (MODE == MODE_CHECK) {
             R dp = fabs(pn - a.it[F_P][c]) * a.rK;
-            R dt = fmax(fabs(txx - a.it[F_TXX][c]), fabs(tyy - a.it[F_TYY][c])) * a.rG;
-            rmax = (double)fmax(dp, dt);
+            R dt = nmax(fabs(txx - a.it[F_TXX][c]), fabs(tyy - a.it[F_TYY][c])) * a.rG;
+            rmax = nmax((double)dp, (double)dt);
         }
     }
     if (MODE == MODE_CHECK) block_max_to<NT>(rmax, a.red + RED_RESID, sh);
@@ -105,20 +105,20 @@ __global__ __launch_bounds__(NT) void k_velocity_2d(SweepArgs<R> a)
         if (i > 0 && i < a.nx) {
             R Rx = ((txx[e] - p[e]) - (txx[e - 1] - p[e - 1])) * a.idx + (txy[e + a.sy] - txy[e]) * a.idy;
             v = v + a.dtrho * Rx;
-            rmax = fmax(rmax, (double)fabs(Rx));
+            rmax = nmax(rmax, (double)fabs(Rx));
         }
         if (MODE != MODE_PHYS) a.nx_[F_VX][e] = v;
-        vmax = fmax(vmax, (double)fabs(v));
+        vmax = nmax(vmax, (double)fabs(v));
     }
     if (i < a.nx && j <= a.ny) {                    // y-faces
         R v = a.it[F_VY][e];
         if (j > 0 && j < a.ny) {
             R Ry = ((tyy[e] - p[e]) - (tyy[e - a.sy] - p[e - a.sy])) * a.idy + (txy[e + 1] - txy[e]) * a.idx;
             v = v + a.dtrho * Ry;
-            rmax = fmax(rmax, (double)fabs(Ry));
+            rmax = nmax(rmax, (double)fabs(Ry));
         }
         if (MODE != MODE_PHYS) a.nx_[F_VY][e] = v;
-        vmax = fmax(vmax, (double)fabs(v));
+        vmax = nmax(vmax, (double)fabs(v));
     }
     if (MODE != MODE_UPDATE) {
         block_max_to<NT>(rmax, a.red + RED_MOM, sh);
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(NT) void k_centre_3d(SweepArgs<R> a)
             R dp = fabs(pn - a.it[F_P][c]) * a.rK;
             R dtx = fabs(txx - a.it[F_TXX][c]), dty = fabs(tyy - a.it[F_TYY][c]);
             R dtz = fabs((txx + tyy) - (a.it[F_TXX][c] + a.it[F_TYY][c]));
-            rmax = (double)fmax(dp, fmax(dtx, fmax(dty, dtz)) * a.rG);
+            rmax = nmax(nmax((double)dp, (double)(nmax(nmax(dtx, dty), dtz) * a.rG)), 0.0);
         }
     }
     if (MODE == MODE_CHECK) block_max_to<NT>(rmax, a.red + RED_RESID, sh);
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(NT) void k_edge_3d(SweepArgs<R> a)
                 t = T_xy(a, e, i, j) / (a.D + lv);
             }
             a.nx_[F_TXY][e] = t;
-            if (MODE == MODE_CHECK) rmax = fmax(rmax, (double)fabs(t - a.it[F_TXY][e]));
+            if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)fabs(t - a.it[F_TXY][e]));
         }
         if (j < a.ny) {                                   // xz edges
             R t = R(0);
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(NT) void k_edge_3d(SweepArgs<R> a)
                 t = T_xz(a, e, i, k) / (a.D + lv);
             }
             a.nx_[F_TXZ][e] = t;
-            if (MODE == MODE_CHECK) rmax = fmax(rmax, (double)fabs(t - a.it[F_TXZ][e]));
+            if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)fabs(t - a.it[F_TXZ][e]));
         }
         if (i < a.nx) {                                   // yz edges
             R t = R(0);
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(NT) void k_edge_3d(SweepArgs<R> a)
                 t = T_yz(a, e, j, k) / (a.D + lv);
             }
             a.nx_[F_TYZ][e] = t;
-            if (MODE == MODE_CHECK) rmax = fmax(rmax, (double)fabs(t - a.it[F_TYZ][e]));
+            if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)fabs(t - a.it[F_TYZ][e]));
         }
     }
     if (MODE == MODE_CHECK) block_max_to<NT>(rmax * (double)a.rG, a.red + RED_RESID, sh);
@@ -261,10 +261,10 @@ __global__ __launch_bounds__(NT) void k_velocity_3d(SweepArgs<R> a)
             R Rx = ((txx[e] - p[e]) - (txx[e - 1] - p[e - 1])) * a.idx
                  + (txy[e + sy] - txy[e]) * a.idy + (txz[e + sz] - txz[e]) * a.idz;
             v = v + a.dtrho * Rx;
-            rmax = fmax(rmax, (double)fabs(Rx));
+            rmax = nmax(rmax, (double)fabs(Rx));
         }
         if (MODE != MODE_PHYS) a.nx_[F_VX][e] = v;
-        vmax = fmax(vmax, (double)fabs(v));
+        vmax = nmax(vmax, (double)fabs(v));
     }
     if (i < a.nx && j <= a.ny && k < a.nz) {         // y-faces
         R v = a.it[F_VY][e];
@@ -272,10 +272,10 @@ __global__ __launch_bounds__(NT) void k_velocity_3d(SweepArgs<R> a)
             R Ry = (txy[e + 1] - txy[e]) * a.idx
                  + ((tyy[e] - p[e]) - (tyy[e - sy] - p[e - sy])) * a.idy + (tyz[e + sz] - tyz[e]) * a.idz;
             v = v + a.dtrho * Ry;
-            rmax = fmax(rmax, (double)fabs(Ry));
+            rmax = nmax(rmax, (double)fabs(Ry));
         }
         if (MODE != MODE_PHYS) a.nx_[F_VY][e] = v;
-        vmax = fmax(vmax, (double)fabs(v));
+        vmax = nmax(vmax, (double)fabs(v));
     }
     if (i < a.nx && j < a.ny && k <= a.nz) {         // z-faces
         R v = a.it[F_VZ][e];
@@ -284,10 +284,10 @@ __global__ __launch_bounds__(NT) void k_velocity_3d(SweepArgs<R> a)
             R szd = -(txx[e - sz] + tyy[e - sz]) - p[e - sz];
             R Rz = (txz[e + 1] - txz[e]) * a.idx + (tyz[e + sy] - tyz[e]) * a.idy + (szu - szd) * a.idz;
             v = v + a.dtrho * Rz;
-            rmax = fmax(rmax, (double)fabs(Rz));
+            rmax = nmax(rmax, (double)fabs(Rz));
         }
         if (MODE != MODE_PHYS) a.nx_[F_VZ][e] = v;
-        vmax = fmax(vmax, (double)fabs(v));
+        vmax = nmax(vmax, (double)fabs(v));
     }
     if (MODE != MODE_UPDATE) {
         block_max_to<NT>(rmax, a.red + RED_MOM, sh);

@@ -48,7 +48,7 @@ SWEEP_CASES = [
 
 @pytest.mark.parametrize("name,m", SWEEP_CASES, ids=[c[0] for c in SWEEP_CASES])
 @pytest.mark.parametrize("prec", [FP64, FP32], ids=["fp64", "fp32"])
-@pytest.mark.parametrize("sweep", [0, 2], ids=["auto", "unfused"])
+@pytest.mark.parametrize("sweep", [1, 2], ids=["fused", "unfused"])
 def test_single_sweep_matches_oracle(name, m, prec, sweep):
     """Random state (every field, walls included): 1 and 5 PT sweeps."""
     say("single sweep", name, "prec", prec, "sweep", sweep)
