@@ -104,7 +104,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3, help="timed load increments")
-    ap.add_argument("--warmup", type=int, default=12, help="untimed load increments before timing")
+    ap.add_argument("--warmup", type=int, default=10, help="untimed load increments before timing")
     ap.add_argument("--workload", default="3d-255")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--sweep", default="auto", choices=["auto", "fused", "unfused"])

@@ -78,10 +78,11 @@ typedef struct ep_params {
     double cfl;              /* PT Courant number V~ dtau / h (0: 0.9/sqrt(ndim); must be < 1/sqrt(ndim)) */
     int    precision;        /* EP_FP64 or EP_FP32_FIELDS */
     int    sweep;            /* EP_SWEEP_* */
-    double fp32_switch;      /* FP32 mode: leave FP32 when the normalised residual
-                                is below this (0: 10 * tol) ... */
-    int    fp32_stall;       /* ... or has not halved for this many checks
-                                (0: 16 max(nx,ny,nz) / n_check; < 0: never) */
+    double fp32_switch;      /* FP32 mode: leave FP32 when the normalised residual is
+                                below this (0: 10 * tol), or within 10x of the FP32
+                                rounding floor 8 u32 max|sigma| / h, ... */
+    int    fp32_stall;       /* ... or, within 20x of that floor, has not halved for
+                                this many checks (0: 16 max(nx,ny,nz) / n_check; < 0: never) */
 } ep_params;
 
 typedef struct ep_step_stats {

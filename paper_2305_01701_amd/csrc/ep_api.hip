@@ -235,8 +235,16 @@ SweepArgs<R> make_args(const ep_handle* h, R* const* from, R* const* to, R* cons
     a.B = (R)h->B;
     a.rK = (R)(h->prm.bulk * h->prm.dt / (h->kdtau * h->L));
     a.rG = (R)(h->eta / (h->gdtau * h->L));
+    // FP32 velocity fields store the deviation from the background field
+    const bool bg = sizeof(R) == 4;
+    a.ebx = (R)(bg ? h->prm.erate[0] : 0.0);
+    a.eby = (R)(bg ? h->prm.erate[1] : 0.0);
+    a.ebz = (R)(bg && h->ndim == 3 ? h->prm.erate[2] : 0.0);
     return a;
 }
+
+double face_len(const ep_handle* h, int d) { return d == 0 ? h->prm.lx : d == 1 ? h->prm.ly : h->prm.lz; }
+double face_sp(const ep_handle* h, int d) { return d == 0 ? h->dx : d == 1 ? h->dy : h->dz; }
 
 SweepArgs<double> args64(const ep_handle* h, bool physical, int from)
 {
@@ -291,8 +299,9 @@ void ensure_it64(ep_handle* h)
               : f == F_TXZ ? O_TXZ : f == F_TYZ ? O_TYZ : -1;
         if (o >= 0)
             launch_incr_to_f64(h->it64[h->cur64][f], h->old64[o], h->it32[h->cur32][f], h->old32[o], h->nelem, h->st);
-        else
-            launch_to_f64(h->it64[h->cur64][f], h->it32[h->cur32][f], h->nelem, h->st);
+        else                                    // velocity: add the background back
+            launch_vel_to_f64(h->g, f - F_VX, h->it64[h->cur64][f], h->it32[h->cur32][f], h->prm.erate[f - F_VX],
+                              face_len(h, f - F_VX), face_sp(h, f - F_VX), h->st);
     }
     h->it64_valid = true;
 }
@@ -307,8 +316,14 @@ void ensure_it32(ep_handle* h)
         h->old32_valid = true;
     }
     if (!h->it32_valid) {
-        for (int f = 0; f < F_NIT; ++f)
-            if (h->it64[h->cur64][f]) launch_to_f32(h->it32[h->cur32][f], h->it64[h->cur64][f], h->nelem, h->st);
+        for (int f = 0; f < F_NIT; ++f) {
+            if (!h->it64[h->cur64][f]) continue;
+            if (f <= F_VZ)                      // velocity: store the deviation from the background
+                launch_vel_to_f32(h->g, f, h->it32[h->cur32][f], h->it64[h->cur64][f], h->prm.erate[f],
+                                  face_len(h, f), face_sp(h, f), h->st);
+            else
+                launch_to_f32(h->it32[h->cur32][f], h->it64[h->cur64][f], h->nelem, h->st);
+        }
         h->it32_valid = true;
     }
 }
@@ -653,13 +668,20 @@ int ep_load_step(ep_handle* h, ep_step_stats* st)
             break;
         }
         if (use32) {
+            // FP32 rounding of the stresses bounds what an FP32 sweep can
+            // resolve: about 8 u32 max|sigma| / h in residual units (measured
+            // on a converged 3D plastic increment: 2-3 times that).  Above it
+            // FP32 keeps iterating, also through plateaus where the yielding
+            // zone reorganises; close to it, FP64 sweeps take over.
+            const double floor32 = 8.0 * 5.96e-8 * red[RED_SMAX] / h->h;
             if (resid < 0.5 * best) {
                 best = resid;
                 since_best = 0;
             } else {
                 ++since_best;
             }
-            if (resid <= sw || since_best >= stall_checks) {
+            const bool near_floor = resid <= 20.0 * floor32;
+            if (resid <= std::max(sw, 10.0 * floor32) || (near_floor && since_best >= stall_checks)) {
                 ensure_it64(h);      // continue from the FP32 state in FP64
                 use32 = false;
                 st->fp32_exit = resid / st->ref;

@@ -29,6 +29,22 @@ __global__ void k_to_f64(double* d, const float* s, long n)
 {
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) d[q] = (double)s[q];
 }
+__device__ __forceinline__ double face_bg(const AuxGrid& g, int d, long q, double erate, double len, double sp)
+{
+    const long i = q % g.sy, j = (q / g.sy) % (g.ny + 1), k = q / g.sz;
+    const long n = d == 0 ? i : d == 1 ? j : k;
+    return erate * (-0.5 * len + n * sp);
+}
+__global__ void k_vel_to_f32(AuxGrid g, int d, float* dst, const double* src, double er, double len, double sp)
+{
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < g.nelem; q += (long)gridDim.x * blockDim.x)
+        dst[q] = (float)(src[q] - face_bg(g, d, q, er, len, sp));
+}
+__global__ void k_vel_to_f64(AuxGrid g, int d, double* dst, const float* src, double er, double len, double sp)
+{
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < g.nelem; q += (long)gridDim.x * blockDim.x)
+        dst[q] = (double)src[q] + face_bg(g, d, q, er, len, sp);
+}
 __global__ void k_incr_to_f64(double* d, const double* b64, const float* x, const float* b32, long n)
 {
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x)
@@ -210,6 +226,16 @@ void launch_fill(double* p, double v, long n, hipStream_t s) { k_fill<<<blocks_f
 void launch_copy(double* d, const double* src, long n, hipStream_t s) { k_copy<<<blocks_for(n), NT1, 0, s>>>(d, src, n); }
 void launch_to_f32(float* d, const double* src, long n, hipStream_t s) { k_to_f32<<<blocks_for(n), NT1, 0, s>>>(d, src, n); }
 void launch_to_f64(double* d, const float* src, long n, hipStream_t s) { k_to_f64<<<blocks_for(n), NT1, 0, s>>>(d, src, n); }
+void launch_vel_to_f32(const AuxGrid& g, int d, float* dst, const double* src, double erate, double len,
+                       double spacing, hipStream_t s)
+{
+    k_vel_to_f32<<<blocks_for(g.nelem), NT1, 0, s>>>(g, d, dst, src, erate, len, spacing);
+}
+void launch_vel_to_f64(const AuxGrid& g, int d, double* dst, const float* src, double erate, double len,
+                       double spacing, hipStream_t s)
+{
+    k_vel_to_f64<<<blocks_for(g.nelem), NT1, 0, s>>>(g, d, dst, src, erate, len, spacing);
+}
 void launch_incr_to_f64(double* d, const double* b64, const float* x, const float* b32, long n, hipStream_t s)
 {
     k_incr_to_f64<<<blocks_for(n), NT1, 0, s>>>(d, b64, x, b32, n);

@@ -19,7 +19,7 @@ enum { O_P = 0, O_TXX, O_TYY, O_TXY, O_TXZ, O_TYZ, O_N };
 
 // Reduction slots (uint64 bit patterns of non-negative doubles; max by
 // integer atomicMax; NaN is mapped to +inf before reduction).
-enum { RED_RESID = 0, RED_MOM, RED_VMAX, RED_NYIELD, RED_VIOL, RED_N = 8 };
+enum { RED_RESID = 0, RED_MOM, RED_VMAX, RED_NYIELD, RED_VIOL, RED_SMAX, RED_N = 8 };
 
 // Scalars of one PT sweep.  Kernel arguments by value.
 template <typename R>
@@ -42,6 +42,8 @@ struct SweepArgs {
     R dtrho;               // dtau / rho~
     R A, B;                // Drucker-Prager constants
     R rK, rG;              // pseudo-rate -> residual factors: K dt/(K~dtau L), eta/(G~dtau L)
+    R ebx, eby, ebz;       // background strain rate subtracted from the stored velocities
+                           // (FP32 fields store v - erate * x; 0 when v is stored in full)
 };
 
 // Sweep modes.
@@ -68,6 +70,12 @@ void launch_fill(double* p, double v, long n, hipStream_t s);
 void launch_copy(double* dst, const double* src, long n, hipStream_t s);
 void launch_to_f32(float* dst, const double* src, long n, hipStream_t s);
 void launch_to_f64(double* dst, const float* src, long n, hipStream_t s);
+// Velocity component d (0 x, 1 y, 2 z) between the full FP64 field and the
+// FP32 field that stores v - erate_d * x_d (x_d the face coordinate).
+void launch_vel_to_f32(const AuxGrid& g, int d, float* dst, const double* src, double erate, double len,
+                       double spacing, hipStream_t s);
+void launch_vel_to_f64(const AuxGrid& g, int d, double* dst, const float* src, double erate, double len,
+                       double spacing, hipStream_t s);
 // dst64 = base64 + (double)(x32 - base32)   (increment form)
 void launch_incr_to_f64(double* dst, const double* base64, const float* x32, const float* base32,
                         long n, hipStream_t s);

@@ -131,7 +131,7 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, int nbx, i
         }
     };
 
-    double rmax = 0.0, mmax = 0.0, vmax = 0.0;   // combined, momentum-only, |v|
+    double rmax = 0.0, mmax = 0.0, vmax = 0.0, smax = 0.0;   // combined, momentum-only, |v|, |stress|
 
     prefetch(k0 - 2);
     for (int f = k0 - 2; f <= k1 + 1; ++f) {
@@ -221,9 +221,9 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, int nbx, i
                     s_syy[sc][q] = R(0);
                     continue;
                 }
-                R dvx = (s_vx[cm][q + 1] - s_vx[cm][q]) * idx;
-                R dvy = (s_vy[cm][q + W] - s_vy[cm][q]) * idy;
-                R dvz = (s_vz[sc1][q] - s_vz[sc][q]) * idz;
+                R dvx = (s_vx[cm][q + 1] - s_vx[cm][q]) * idx + a.ebx;
+                R dvy = (s_vy[cm][q + W] - s_vy[cm][q]) * idy + a.eby;
+                R dvz = (s_vz[sc1][q] - s_vz[sc][q]) * idz + a.ebz;
                 R div = dvx + dvy + dvz;
                 const R pk = cp[u], txk = csx[u], tyk = csy[u];
                 R pn = (pk * ikt + cpo[u] * ikd - div) * a.ikk;
@@ -251,6 +251,7 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, int nbx, i
                         R dp = fabs(pn - pk) * a.rK;
                         R dtx = fabs(txx - txk), dty = fabs(tyy - tyk), dtz = fabs((txx + tyy) - (txk + tyk));
                         rmax = nmax(rmax, nmax((double)dp, (double)(nmax(nmax(dtx, dty), dtz) * a.rG)));
+                        smax = nmax(smax, (double)nmax(nmax(fabs(pn), fabs(txx)), nmax(fabs(tyy), fabs(txx + tyy))));
                     }
                 }
             }
@@ -387,6 +388,7 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, int nbx, i
         if (MODE == MODE_CHECK) {
             block_max_to<NT>(fmax(rmax, mmax), a.red + RED_RESID, s_red);
             block_max_to<NT>(vmax, a.red + RED_VMAX, s_red);
+            block_max_to<NT>(smax, a.red + RED_SMAX, s_red);
         }
     }
 }
@@ -408,7 +410,7 @@ __global__ __launch_bounds__(TX * TY) void k_fused_2d(SweepArgs<R> a, int nbx, i
     const int hx = (i0 + TX == nx) ? 1 : 0;
     const int hy = (j0 + TY == ny) ? 1 : 0;
     const R idx = a.idx, idy = a.idy, igt = a.igt, igd = a.igd, ikt = a.ikt, ikd = a.ikd, D = a.D;
-    double rmax = 0.0, mmax = 0.0, vmax = 0.0;   // combined, momentum-only, |v|
+    double rmax = 0.0, mmax = 0.0, vmax = 0.0, smax = 0.0;   // combined, momentum-only, |v|, |stress|
 
     // issue every global load of the tile up front (velocities, shear stresses
     // of iteration k and of the increment start, centre data), then the stages
@@ -482,8 +484,8 @@ __global__ __launch_bounds__(TX * TY) void k_fused_2d(SweepArgs<R> a, int nbx, i
                 continue;
             }
             const long e = i + sy * j;
-            R dvx = (s_vx[q + 1] - s_vx[q]) * idx;
-            R dvy = (s_vy[q + W] - s_vy[q]) * idy;
+            R dvx = (s_vx[q + 1] - s_vx[q]) * idx + a.ebx;
+            R dvy = (s_vy[q + W] - s_vy[q]) * idy + a.eby;
             R div = dvx + dvy;
             const R pk = gp[u], txk = gsx[u], tyk = gsy[u];
             R pn = (pk * ikt + gpo[u] * ikd - div) * a.ikk;
@@ -506,6 +508,7 @@ __global__ __launch_bounds__(TX * TY) void k_fused_2d(SweepArgs<R> a, int nbx, i
                     R dp = fabs(pn - pk) * a.rK;
                     R dt = nmax(fabs(txx - txk), fabs(tyy - tyk)) * a.rG;
                     rmax = nmax(rmax, nmax((double)dp, (double)dt));
+                    smax = nmax(smax, (double)nmax(nmax(fabs(pn), fabs(txx)), fabs(tyy)));
                 }
             }
         }
@@ -565,6 +568,7 @@ __global__ __launch_bounds__(TX * TY) void k_fused_2d(SweepArgs<R> a, int nbx, i
         if (MODE == MODE_CHECK) {
             block_max_to<NT>(fmax(rmax, mmax), a.red + RED_RESID, s_red);
             block_max_to<NT>(vmax, a.red + RED_VMAX, s_red);
+            block_max_to<NT>(smax, a.red + RED_SMAX, s_red);
         }
     }
 }

@@ -37,13 +37,13 @@ __global__ __launch_bounds__(NT) void k_centre_2d(SweepArgs<R> a)
     __shared__ double sh[NT / 64];
     const int i = blockIdx.x * BX + threadIdx.x;
     const int j = blockIdx.y * BY + threadIdx.y;
-    double rmax = 0.0;
+    double rmax = 0.0, smax = 0.0;
     if (i < a.nx && j < a.ny) {
         const long c = i + (long)a.sy * j;
         const R* vx = a.it[F_VX];
         const R* vy = a.it[F_VY];
-        R dvx = (vx[c + 1] - vx[c]) * a.idx;
-        R dvy = (vy[c + a.sy] - vy[c]) * a.idy;
+        R dvx = (vx[c + 1] - vx[c]) * a.idx + a.ebx;
+        R dvy = (vy[c + a.sy] - vy[c]) * a.idy + a.eby;
         R div = dvx + dvy;
         R pn = (a.it[F_P][c] * a.ikt + a.old[O_P][c] * a.ikd - div) / (a.ikt + a.ikd);
         R Txx = a.it[F_TXX][c] * a.igt + a.old[O_TXX][c] * a.igd + R(2) * (dvx - div / R(3));
@@ -62,9 +62,13 @@ __global__ __launch_bounds__(NT) void k_centre_2d(SweepArgs<R> a)
             R dp = fabs(pn - a.it[F_P][c]) * a.rK;
             R dt = nmax(fabs(txx - a.it[F_TXX][c]), fabs(tyy - a.it[F_TYY][c])) * a.rG;
             rmax = nmax((double)dp, (double)dt);
+            smax = (double)nmax(nmax(fabs(pn), fabs(txx)), fabs(tyy));
         }
     }
-    if (MODE == MODE_CHECK) block_max_to<NT>(rmax, a.red + RED_RESID, sh);
+    if (MODE == MODE_CHECK) {
+        block_max_to<NT>(rmax, a.red + RED_RESID, sh);
+        block_max_to<NT>(smax, a.red + RED_SMAX, sh);
+    }
 }
 
 template <typename R, int MODE>
@@ -160,13 +164,13 @@ __global__ __launch_bounds__(NT) void k_centre_3d(SweepArgs<R> a)
     const int i = blockIdx.x * BX + threadIdx.x;
     const int j = blockIdx.y * BY + threadIdx.y;
     const int k = blockIdx.z;
-    double rmax = 0.0;
+    double rmax = 0.0, smax = 0.0;
     if (i < a.nx && j < a.ny) {
         const long c = i + (long)a.sy * j + a.sz * k;
         const long sy = a.sy, sz = a.sz;
-        R dvx = (a.it[F_VX][c + 1] - a.it[F_VX][c]) * a.idx;
-        R dvy = (a.it[F_VY][c + sy] - a.it[F_VY][c]) * a.idy;
-        R dvz = (a.it[F_VZ][c + sz] - a.it[F_VZ][c]) * a.idz;
+        R dvx = (a.it[F_VX][c + 1] - a.it[F_VX][c]) * a.idx + a.ebx;
+        R dvy = (a.it[F_VY][c + sy] - a.it[F_VY][c]) * a.idy + a.eby;
+        R dvz = (a.it[F_VZ][c + sz] - a.it[F_VZ][c]) * a.idz + a.ebz;
         R div = dvx + dvy + dvz;
         R pn = (a.it[F_P][c] * a.ikt + a.old[O_P][c] * a.ikd - div) / (a.ikt + a.ikd);
         R Txx = a.it[F_TXX][c] * a.igt + a.old[O_TXX][c] * a.igd + R(2) * (dvx - div / R(3));
@@ -191,9 +195,13 @@ __global__ __launch_bounds__(NT) void k_centre_3d(SweepArgs<R> a)
             R dtx = fabs(txx - a.it[F_TXX][c]), dty = fabs(tyy - a.it[F_TYY][c]);
             R dtz = fabs((txx + tyy) - (a.it[F_TXX][c] + a.it[F_TYY][c]));
             rmax = nmax(nmax((double)dp, (double)(nmax(nmax(dtx, dty), dtz) * a.rG)), 0.0);
+            smax = (double)nmax(nmax(fabs(pn), fabs(txx)), nmax(fabs(tyy), fabs(txx + tyy)));
         }
     }
-    if (MODE == MODE_CHECK) block_max_to<NT>(rmax, a.red + RED_RESID, sh);
+    if (MODE == MODE_CHECK) {
+        block_max_to<NT>(rmax, a.red + RED_RESID, sh);
+        block_max_to<NT>(smax, a.red + RED_SMAX, sh);
+    }
 }
 
 template <typename R, int MODE>
