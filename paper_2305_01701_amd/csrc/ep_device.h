@@ -42,7 +42,12 @@ __device__ __forceinline__ void block_max_to(double v, unsigned long long* dst, 
     if (tid < 64) {
         double w = tid < NT / 64 ? sh[tid] : 0.0;
         w = wave_max(w);
-        if (tid == 0 && w > 0.0) atomicMax(dst, (unsigned long long)__double_as_longlong(w));
+        if (tid == 0 && w > 0.0) {
+            // skip the atomic when the running maximum is already larger: a
+            // stale read only costs an unnecessary atomic, never a wrong max
+            const unsigned long long bits = (unsigned long long)__double_as_longlong(w);
+            if (bits > __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(dst, bits);
+        }
     }
     __syncthreads();
 }
