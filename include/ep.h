@@ -196,6 +196,63 @@ const char* ep_last_error(const ep_handle* h);
 int ep_enable_timing(ep_handle* h, int on);
 int ep_sweep_timing(const ep_handle* h, int precision, double* avg_ms, long* sweeps);
 
+/* ---- batches of 2D models ----------------------------------------------------
+ * A parameter sweep: n independent 2D models (each its own ep_params: size,
+ * material, cohesion field, tolerance) solved one load increment at a time
+ * together.  The PT sweeps of all models run as persistent launches that
+ * walk one tile list per precision and tile shape, n_check sweeps per
+ * replay of a captured HIP graph; after every replay each model is checked
+ * with the single-model convergence rule (ep_load_step) and retired from
+ * the lists when it has converged or failed, or moved to FP64 sweeps at its
+ * FP32 hand-over.  Per model, the iterates, iteration counts and statistics
+ * are those of ep_load_step on that model alone.
+ * Requirements: every model 2D, all with the same precision and the same
+ * (resolved) n_check, which must be even; at most 32767 tiles per direction.
+ * Memory: one caller-owned workspace of ep_batch_workspace_size() bytes
+ * (256-byte aligned), as for ep_init.  Stream: as for ep_init; graph
+ * replays are launched on it (a private stream is used only to record the
+ * graph). */
+typedef struct ep_batch ep_batch;
+
+/* Bytes of device workspace for n models with parameters p[0..n-1]. */
+int ep_batch_workspace_size(int n, const ep_params* p, size_t* bytes);
+
+/* Create a batch.  cohesion: NULL or n pointers, each NULL or n_cells FP64
+ * values of model i (copied).  Initial state of every model as in ep_init.
+ * Errors: EP_EINVAL (a model's parameters invalid, not 2D, mixed precision or
+ * n_check, odd n_check), EP_ENOMEM, EP_EDEVICE. */
+int ep_batch_init(int n, const ep_params* p, const double* const* cohesion, void* d_workspace, size_t ws_bytes,
+                  void* stream, ep_batch** out);
+
+/* Autotuner: picks the tile shape of each model size (models with equal
+ * nx, ny share one) by timing `reps` batched sweeps of all models per
+ * candidate, coordinate descent over the size classes.  The timed sweeps
+ * leave the state unchanged.  Optional; the default shape is 64 x 8. */
+int ep_batch_tune(ep_batch* b, int reps);
+
+/* Tile shape used for model i. */
+int ep_batch_tile_shape(const ep_batch* b, int i, int* tx, int* ty);
+
+/* One load increment of every model; st: n entries (required), filled as by
+ * ep_load_step.  Returns EP_OK when all models converged, else the status
+ * of the first model that did not (that model's state rolled back, the
+ * others advanced). */
+int ep_batch_load_step(ep_batch* b, ep_step_stats* st);
+
+/* The handle of model i, for ep_fields, ep_field_shape, ep_residual,
+ * ep_step_history and ep_sweep (owned by the batch: ep_destroy ignores it). */
+ep_handle* ep_batch_model(ep_batch* b, int i);
+
+/* Timing of the graph replays: when enabled, each replay is bracketed by
+ * HIP events; ep_batch_timing returns the accumulated milliseconds, the
+ * cell-sweeps done in FP32 and in FP64 (sum over models of cells x sweeps)
+ * and the number of replays since timing was (re-)enabled. */
+int ep_batch_enable_timing(ep_batch* b, int on);
+int ep_batch_timing(const ep_batch* b, double* ms, double* cell_sweeps32, double* cell_sweeps64, long* replays);
+
+void ep_batch_destroy(ep_batch* b);
+const char* ep_batch_last_error(const ep_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

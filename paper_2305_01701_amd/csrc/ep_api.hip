@@ -14,43 +14,13 @@
 #include <vector>
 
 #include "ep.h"
+#include "ep_handle.h"
 #include "ep_internal.h"
 
 using namespace ep;
 
-struct ep_handle {
-    ep_params prm;
-    hipStream_t st;
-    AuxGrid g;
-    int ndim, nx, ny, nz, sy;
-    long sz, nelem;
-    double dx, dy, dz, eta, gdtau, kdtau, dtrho, A, B, L, h, inv_mus, dsig_ref;
-    int n_check;
-    bool fp32, fused32, fused64;
-    double* it64[2][F_NIT];
-    int cur64;
-    double* old64[O_N];
-    double *coh64, *lam64;
-    double* vstart64[3];
-    double* u64[3];
-    double* e64[6];
-    double *epsp64, *lamdot64, *tii64, *yld64, *cols64;
-    float* it32[2][F_NIT];
-    int cur32;
-    float* old32[O_N];
-    float *coh32, *lam32;
-    unsigned long long* red;
-    bool it32_valid, old32_valid, it64_valid;
-    bool timing;
-    hipEvent_t ev0, ev1;
-    double t_ms[2];
-    long t_n[2];
-    std::vector<double> hist_r;
-    std::vector<int> hist_p;
-    char err[512];
-};
 
-namespace {
+namespace ep {
 
 const double PI = 3.14159265358979323846;
 
@@ -146,6 +116,15 @@ size_t carve(const ep_params* p, ep_handle* h, char* base)
     }
     q = fp32 ? take(b32) : nullptr; if (h) h->coh32 = (float*)q;
     q = fp32 ? take(b32) : nullptr; if (h) h->lam32 = (float*)q;
+    if (p->ndim == 2) {
+        const long nt = (long)((nx + kBatchTiles[0][0] - 1) / kBatchTiles[0][0]) *
+                        ((ny + kBatchTiles[0][1] - 1) / kBatchTiles[0][1]);
+        q = take(4 * sizeof(SweepArgs<double>)); if (h) h->tab64 = (SweepArgs<double>*)q;
+        q = take(2 * sizeof(SweepArgs<float>)); if (h) h->tab32 = (SweepArgs<float>*)q;
+        q = take(nt * sizeof(TileRef)); if (h) h->tiles = (TileRef*)q;
+        q = take(sizeof(int)); if (h) h->tcount = (int*)q;
+        if (h) h->ntiles = nt;
+    }
     if (h) {
         h->sy = (int)sy;
         h->sz = sz;
@@ -255,17 +234,57 @@ SweepArgs<float> args32(const ep_handle* h, int from)
     return make_args<float>(h, h->it32[from], h->it32[1 - from], h->old32, h->coh32, h->lam32, false);
 }
 
+// One PT sweep reading buffer `from` (physical: pseudo-time terms removed).
+// 2D fused sweeps run the batched tile kernel on this model's own one-entry
+// table and tile list, so that a model gives bitwise the same iterates alone
+// and inside a batch.
 template <typename R>
-void launch_sweep(const ep_handle* h, const SweepArgs<R>& a, int mode)
+void launch_sweep(const ep_handle* h, bool physical, int from, int mode)
 {
     const bool fused = sizeof(R) == 4 ? h->fused32 : h->fused64;
+    if (h->ndim == 2 && fused) {
+        const int q = sizeof(R) == 4 ? 1 : 0;
+        if (q == 1)
+            launch_sweep_batch_2d<float>(0, h->tab32 + from, h->tiles, h->tcount, mode, h->grid2[1], h->st);
+        else
+            launch_sweep_batch_2d<double>(0, h->tab64 + (physical ? 2 : 0) + from, h->tiles, h->tcount, mode,
+                                          h->grid2[0], h->st);
+        return;
+    }
+    SweepArgs<R> a;
+    if constexpr (sizeof(R) == 4) a = args32(h, from);
+    else a = args64(h, physical, from);
     if (h->ndim == 2) {
-        if (fused) launch_sweep_fused_2d<R>(a, mode, h->st);
-        else launch_sweep_unfused_2d<R>(a, mode, h->st);
+        launch_sweep_unfused_2d<R>(a, mode, h->st);
     } else {
         if (fused) launch_sweep_fused_3d<R>(a, mode, h->st);
         else launch_sweep_unfused_3d<R>(a, mode, h->st);
     }
+}
+
+// Device tables of the 2D tile kernel: FP64 [from 0, from 1, physical 0,
+// physical 1], FP32 [from 0, from 1], and the tile list (shape 0).
+int upload_tables(ep_handle* h)
+{
+    if (h->ndim != 2) return EP_OK;
+    SweepArgs<double> t64[4] = {args64(h, false, 0), args64(h, false, 1), args64(h, true, 0), args64(h, true, 1)};
+    HIPCHK(h, hipMemcpyAsync(h->tab64, t64, sizeof(t64), hipMemcpyHostToDevice, h->st));
+    if (h->fp32) {
+        SweepArgs<float> t32[2] = {args32(h, 0), args32(h, 1)};
+        HIPCHK(h, hipMemcpyAsync(h->tab32, t32, sizeof(t32), hipMemcpyHostToDevice, h->st));
+    }
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return EP_OK;
+}
+
+void decode_red(const unsigned long long raw[RED_N], double out[RED_N])
+{
+    for (int q = 0; q < RED_N; ++q) {
+        double d;
+        std::memcpy(&d, &raw[q], sizeof(d));
+        out[q] = d;
+    }
+    out[RED_NYIELD] = (double)raw[RED_NYIELD];
 }
 
 int read_red(ep_handle* h, double out[RED_N])
@@ -274,12 +293,7 @@ int read_red(ep_handle* h, double out[RED_N])
     HIPCHK(h, hipMemcpyAsync(raw, h->red, sizeof(raw), hipMemcpyDeviceToHost, h->st));
     HIPCHK(h, hipStreamSynchronize(h->st));
     HIPCHK(h, hipGetLastError());
-    for (int q = 0; q < RED_N; ++q) {
-        double d;
-        std::memcpy(&d, &raw[q], sizeof(d));
-        out[q] = d;
-    }
-    out[RED_NYIELD] = (double)raw[RED_NYIELD];
+    decode_red(raw, out);
     return EP_OK;
 }
 
@@ -336,10 +350,10 @@ int run_batch(ep_handle* h, bool use32, int nb, bool check_last)
     for (int b = 0; b < nb; ++b) {
         int mode = (check_last && b == nb - 1) ? MODE_CHECK : MODE_UPDATE;
         if (use32) {
-            launch_sweep<float>(h, args32(h, h->cur32), mode);
+            launch_sweep<float>(h, false, h->cur32, mode);
             h->cur32 = 1 - h->cur32;
         } else {
-            launch_sweep<double>(h, args64(h, false, h->cur64), mode);
+            launch_sweep<double>(h, false, h->cur64, mode);
             h->cur64 = 1 - h->cur64;
         }
     }
@@ -369,6 +383,150 @@ void roll_back(ep_handle* h)
         if (h->old64[o]) launch_copy(it[map[o]], h->old64[o], h->nelem, h->st);
     h->it64_valid = true;
     h->it32_valid = false;
+}
+
+double seconds_since(const StepCtl& c)
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - c.t0).count();
+}
+
+void step_begin(ep_handle* h, ep_step_stats* st)
+{
+    StepCtl& c = h->ctl;
+    c = StepCtl();
+    c.st = st;
+    c.t0 = std::chrono::steady_clock::now();
+    c.running = false;
+    c.status = EP_ENOTCONV;
+    c.resid = NAN;
+    c.vmax = 0;
+    std::memset(st, 0, sizeof(*st));
+
+    // increment start state and wall velocities
+    ensure_it64(h);
+    double** it = h->it64[h->cur64];
+    const int map[O_N] = {F_P, F_TXX, F_TYY, F_TXY, F_TXZ, F_TYZ};
+    for (int o = 0; o < O_N; ++o)
+        if (h->old64[o]) launch_copy(h->old64[o], it[map[o]], h->nelem, h->st);
+    launch_set_walls(h->g, it[F_VX], it[F_VY], it[F_VZ], h->prm.erate, h->prm.lx, h->prm.ly, h->prm.lz, h->st);
+    for (int d = 0; d < h->ndim; ++d) launch_copy(h->vstart64[d], it[F_VX + d], h->nelem, h->st);
+    h->it32_valid = false;
+    h->old32_valid = false;
+    // normaliser: physical residual of the plain guess
+    launch_reset_red(h->red, h->st);
+    launch_sweep<double>(h, true, h->cur64, MODE_PHYS);
+}
+
+int step_start(ep_handle* h, const double red[RED_N])
+{
+    StepCtl& c = h->ctl;
+    ep_step_stats* st = c.st;
+    st->r_ref = red[RED_MOM];
+    st->ref = std::fmax(st->r_ref, h->dsig_ref / h->L);
+    if (!(st->r_ref <= 1e300)) {            // NaN / Inf in the starting state
+        st->status = EP_EDIVERGED;
+        c.status = EP_EDIVERGED;
+        roll_back(h);
+        st->seconds = seconds_since(c);
+        return EP_EDIVERGED;
+    }
+    // the physical stresses just written to the other buffer are the
+    // pseudo-time starting point; the velocities carry over unchanged
+    for (int d = 0; d < h->ndim; ++d)
+        launch_copy(h->it64[1 - h->cur64][F_VX + d], h->it64[h->cur64][F_VX + d], h->nelem, h->st);
+    h->cur64 = 1 - h->cur64;
+    h->hist_r.clear();
+    h->hist_p.clear();
+
+    c.tol_abs = h->prm.tol * st->ref;
+    c.sw = (h->prm.fp32_switch > 0 ? h->prm.fp32_switch : 10.0 * h->prm.tol) * st->ref;
+    c.use32 = h->fp32;
+    if (c.use32) ensure_it32(h);
+    const int nmax = std::max(h->nx, std::max(h->ny, h->nz));
+    c.stall_checks = h->prm.fp32_stall > 0 ? h->prm.fp32_stall
+                   : h->prm.fp32_stall < 0 ? INT_MAX : std::max(8, 16 * nmax / h->n_check);
+    c.best = INFINITY;
+    c.since_best = 0;
+    c.running = true;
+    return EP_OK;
+}
+
+bool step_check(ep_handle* h, const double red[RED_N], int nb)
+{
+    StepCtl& c = h->ctl;
+    ep_step_stats* st = c.st;
+    st->iters += nb;
+    if (c.use32) st->iters_fp32 += nb;
+    c.resid = red[RED_RESID];
+    c.vmax = red[RED_VMAX];
+    h->hist_r.push_back(c.resid / st->ref);
+    h->hist_p.push_back(c.use32 ? EP_FP32_FIELDS : EP_FP64);
+    if (!(c.resid <= 1e8 * st->ref)) {
+        c.status = EP_EDIVERGED;
+        c.running = false;
+    } else if (c.use32) {
+        // FP32 rounding of the stresses bounds what an FP32 sweep can
+        // resolve: about 8 u32 max|sigma| / h in residual units (measured on
+        // a converged 3D plastic increment: 2-3 times that).  Above it FP32
+        // keeps iterating, also through plateaus where the yielding zone
+        // reorganises; close to it, FP64 sweeps take over.
+        const double floor32 = 8.0 * 5.96e-8 * red[RED_SMAX] / h->h;
+        if (c.resid < 0.5 * c.best) {
+            c.best = c.resid;
+            c.since_best = 0;
+        } else {
+            ++c.since_best;
+        }
+        const bool near_floor = c.resid <= 20.0 * floor32;
+        if (c.resid <= std::max(c.sw, 10.0 * floor32) || (near_floor && c.since_best >= c.stall_checks)) {
+            ensure_it64(h);          // continue from the FP32 state in FP64
+            c.use32 = false;
+            st->fp32_exit = c.resid / st->ref;
+        }
+    } else if (c.resid <= c.tol_abs) {
+        c.status = EP_OK;
+        c.running = false;
+    }
+    if (c.running && st->iters >= h->prm.max_iter) {
+        c.status = EP_ENOTCONV;
+        c.running = false;
+    }
+    return c.running;
+}
+
+int step_finish(ep_handle* h)
+{
+    StepCtl& c = h->ctl;
+    ep_step_stats* st = c.st;
+    st->resid = c.resid;
+    st->eps_rel = c.vmax > 0 ? h->dtrho * c.resid / c.vmax : 0.0;
+    st->status = c.status;
+    if (c.status != EP_OK) {
+        ensure_it64(h);
+        roll_back(h);
+        st->seconds = seconds_since(c);
+        return c.status;
+    }
+    // diagnostics of the accepted state, FP64 accumulators
+    launch_reset_red(h->red, h->st);
+    launch_diagnostics<double>(args64(h, false, h->cur64), h->lamdot64, h->tii64, h->yld64, h->st);
+    double** it = h->it64[h->cur64];
+    const double* v[3] = {it[F_VX], it[F_VY], it[F_VZ]};
+    launch_accumulate(h->g, h->prm.dt, 1.0 / h->dx, 1.0 / h->dy, 1.0 / h->dz, v, h->u64, h->e64, h->epsp64,
+                      h->lamdot64, h->st);
+    launch_column_integrals(h->g, it[F_P], it[F_TXX], h->dy, h->dz, h->cols64, h->st);
+    return EP_OK;
+}
+
+void step_report(ep_handle* h, const double red[RED_N], const double cols[4])
+{
+    ep_step_stats* st = h->ctl.st;
+    st->sxx_left = cols[0];
+    st->sxx_centre = cols[1];
+    st->sxx_right = cols[2];
+    st->n_yield = (long long)red[RED_NYIELD];
+    st->max_violation = red[RED_VIOL] - 1.0;
+    st->seconds = seconds_since(h->ctl);
 }
 
 struct FieldRef {
@@ -456,34 +614,15 @@ int upload(ep_handle* h, double* dev, const double* in, const int ext[3])
     return EP_OK;
 }
 
-}  // namespace
-
-// =========================================================================
-extern "C" {
-
-int ep_abi_version(void) { return EP_ABI_VERSION; }
-
-int ep_workspace_size(const ep_params* p, size_t* bytes)
+int handle_create(const ep_params* p, const double* cohesion, char* d_workspace, hipStream_t stream,
+                  ep_handle** out)
 {
-    if (!bytes || validate(p) != EP_OK) return EP_EINVAL;
-    *bytes = carve(p, nullptr, nullptr);
-    return EP_OK;
-}
-
-int ep_init(const ep_params* p, const double* cohesion, void* d_workspace, size_t ws_bytes, void* stream,
-            ep_handle** out)
-{
-    if (!out) return EP_EINVAL;
     *out = nullptr;
-    int rc = validate(p);
-    if (rc) return rc;
-    size_t need = carve(p, nullptr, nullptr);
-    if (!d_workspace || ws_bytes < need) return EP_ENOMEM;
-    if (((uintptr_t)d_workspace & 255) != 0) return EP_EINVAL;
+    const size_t need = carve(p, nullptr, nullptr);
     ep_handle* h = new (std::nothrow) ep_handle();
     if (!h) return EP_ENOMEM;
     h->prm = *p;
-    h->st = (hipStream_t)stream;
+    h->st = stream;
     derive(h);
     carve(p, h, (char*)d_workspace);
     h->g.sy = h->sy;
@@ -527,17 +666,66 @@ int ep_init(const ep_params* p, const double* cohesion, void* d_workspace, size_
     h->it64_valid = true;
     h->it32_valid = false;
     h->old32_valid = false;
+    if (h->ndim == 2) {
+        // tile list of the whole model and the persistent grid sizes
+        const int tx = kBatchTiles[0][0], ty = kBatchTiles[0][1];
+        const int nbx = (h->nx + tx - 1) / tx;
+        std::vector<TileRef> tl(h->ntiles);
+        for (long t = 0; t < h->ntiles; ++t) tl[t] = TileRef{0, (short)(t % nbx), (short)(t / nbx)};
+        const int cnt = (int)h->ntiles;
+        if (hipMemcpyAsync(h->tiles, tl.data(), tl.size() * sizeof(TileRef), hipMemcpyHostToDevice, h->st) !=
+                hipSuccess ||
+            hipMemcpyAsync(h->tcount, &cnt, sizeof(int), hipMemcpyHostToDevice, h->st) != hipSuccess ||
+            hipStreamSynchronize(h->st) != hipSuccess)
+            return fail(EP_EDEVICE);
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, 0) != hipSuccess || ncu <= 0) ncu = 256;
+        h->grid2[0] = (int)std::min<long>(h->ntiles, (long)ncu * std::min(8, batch_blocks_per_cu<double>(0)));
+        h->grid2[1] = (int)std::min<long>(h->ntiles, (long)ncu * std::min(8, batch_blocks_per_cu<float>(0)));
+        if (upload_tables(h) != EP_OK) return fail(EP_EDEVICE);
+    }
     if (hipGetLastError() != hipSuccess) return fail(EP_EDEVICE);
     *out = h;
     return EP_OK;
 }
 
-void ep_destroy(ep_handle* h)
+void handle_free(ep_handle* h)
 {
-    if (!h) return;
     (void)hipEventDestroy(h->ev0);
     (void)hipEventDestroy(h->ev1);
     delete h;
+}
+
+}  // namespace ep
+
+// =========================================================================
+extern "C" {
+
+int ep_abi_version(void) { return EP_ABI_VERSION; }
+
+int ep_workspace_size(const ep_params* p, size_t* bytes)
+{
+    if (!bytes || validate(p) != EP_OK) return EP_EINVAL;
+    *bytes = carve(p, nullptr, nullptr);
+    return EP_OK;
+}
+
+int ep_init(const ep_params* p, const double* cohesion, void* d_workspace, size_t ws_bytes, void* stream,
+            ep_handle** out)
+{
+    if (!out) return EP_EINVAL;
+    *out = nullptr;
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!d_workspace || ws_bytes < carve(p, nullptr, nullptr)) return EP_ENOMEM;
+    if (((uintptr_t)d_workspace & 255) != 0) return EP_EINVAL;
+    return handle_create(p, cohesion, (char*)d_workspace, (hipStream_t)stream, out);
+}
+
+void ep_destroy(ep_handle* h)
+{
+    if (!h || h->in_batch) return;     // models of a batch belong to the batch
+    handle_free(h);
 }
 
 const char* ep_last_error(const ep_handle* h) { return h ? h->err : "no handle"; }
@@ -586,13 +774,13 @@ int ep_residual(ep_handle* h, ep_residual_info* r)
     int rc;
     // one PT evaluation into the scratch buffer (state untouched)
     launch_reset_red(h->red, h->st);
-    launch_sweep<double>(h, args64(h, false, h->cur64), MODE_CHECK);
+    launch_sweep<double>(h, false, h->cur64, MODE_CHECK);
     if ((rc = read_red(h, red))) return rc;
     r->resid = red[RED_RESID];
     r->momentum = red[RED_MOM];
     r->vmax = red[RED_VMAX];
     launch_reset_red(h->red, h->st);
-    launch_sweep<double>(h, args64(h, true, h->cur64), MODE_PHYS);
+    launch_sweep<double>(h, true, h->cur64, MODE_PHYS);
     if ((rc = read_red(h, red))) return rc;
     r->physical = red[RED_MOM];
     return EP_OK;
@@ -603,125 +791,25 @@ int ep_load_step(ep_handle* h, ep_step_stats* st)
     if (!h) return EP_EINVAL;
     ep_step_stats dummy;
     if (!st) st = &dummy;
-    std::memset(st, 0, sizeof(*st));
-    const auto t0 = std::chrono::steady_clock::now();
     int rc;
     double red[RED_N];
-
-    // ---- prologue: increment start state, wall velocities ----------------
-    ensure_it64(h);
-    double** it = h->it64[h->cur64];
-    const int map[O_N] = {F_P, F_TXX, F_TYY, F_TXY, F_TXZ, F_TYZ};
-    for (int o = 0; o < O_N; ++o)
-        if (h->old64[o]) launch_copy(h->old64[o], it[map[o]], h->nelem, h->st);
-    launch_set_walls(h->g, it[F_VX], it[F_VY], it[F_VZ], h->prm.erate, h->prm.lx, h->prm.ly, h->prm.lz, h->st);
-    for (int d = 0; d < h->ndim; ++d) launch_copy(h->vstart64[d], it[F_VX + d], h->nelem, h->st);
-    h->it32_valid = false;
-    h->old32_valid = false;
-
-    // ---- normaliser: physical residual of the plain guess ----------------
-    launch_reset_red(h->red, h->st);
-    launch_sweep<double>(h, args64(h, true, h->cur64), MODE_PHYS);
+    step_begin(h, st);
     if ((rc = read_red(h, red))) return rc;
-    st->r_ref = red[RED_MOM];
-    st->ref = std::fmax(st->r_ref, h->dsig_ref / h->L);
-    if (!(st->r_ref <= 1e300)) {            // NaN / Inf in the starting state
-        st->status = EP_EDIVERGED;
-        roll_back(h);
-        st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        return EP_EDIVERGED;
-    }
-    // the physical stresses just written to the other buffer are the
-    // pseudo-time starting point; the velocities carry over unchanged
-    for (int d = 0; d < h->ndim; ++d)
-        launch_copy(h->it64[1 - h->cur64][F_VX + d], h->it64[h->cur64][F_VX + d], h->nelem, h->st);
-    h->cur64 = 1 - h->cur64;
-    h->hist_r.clear();
-    h->hist_p.clear();
-
-    // ---- PT iterations ------------------------------------------------------
-    const double tol_abs = h->prm.tol * st->ref;
-    const double sw = (h->prm.fp32_switch > 0 ? h->prm.fp32_switch : 10.0 * h->prm.tol) * st->ref;
-    bool use32 = h->fp32;
-    if (use32) ensure_it32(h);
-    const int nmax = std::max(h->nx, std::max(h->ny, h->nz));
-    const int stall_checks = h->prm.fp32_stall > 0 ? h->prm.fp32_stall
-                           : h->prm.fp32_stall < 0 ? INT_MAX : std::max(8, 16 * nmax / h->n_check);
-    double best = INFINITY;
-    int since_best = 0;
-    int iters = 0, iters32 = 0;
-    int status = EP_ENOTCONV;
-    double resid = NAN, vmax = 0;
-    while (iters < h->prm.max_iter) {
-        const int nb = std::min(h->n_check, h->prm.max_iter - iters);
+    if ((rc = step_start(h, red))) return rc;
+    const StepCtl& c = h->ctl;
+    while (c.running) {
+        const bool use32 = c.use32;
+        const int nb = std::min(h->n_check, h->prm.max_iter - st->iters);
         if ((rc = run_batch(h, use32, nb, true))) return rc;
         if ((rc = read_red(h, red))) return rc;
         add_timing(h, use32, nb);
-        iters += nb;
-        if (use32) iters32 += nb;
-        resid = red[RED_RESID];
-        vmax = red[RED_VMAX];
-        h->hist_r.push_back(resid / st->ref);
-        h->hist_p.push_back(use32 ? EP_FP32_FIELDS : EP_FP64);
-        if (!(resid <= 1e8 * st->ref)) {
-            status = EP_EDIVERGED;
-            break;
-        }
-        if (use32) {
-            // FP32 rounding of the stresses bounds what an FP32 sweep can
-            // resolve: about 8 u32 max|sigma| / h in residual units (measured
-            // on a converged 3D plastic increment: 2-3 times that).  Above it
-            // FP32 keeps iterating, also through plateaus where the yielding
-            // zone reorganises; close to it, FP64 sweeps take over.
-            const double floor32 = 8.0 * 5.96e-8 * red[RED_SMAX] / h->h;
-            if (resid < 0.5 * best) {
-                best = resid;
-                since_best = 0;
-            } else {
-                ++since_best;
-            }
-            const bool near_floor = resid <= 20.0 * floor32;
-            if (resid <= std::max(sw, 10.0 * floor32) || (near_floor && since_best >= stall_checks)) {
-                ensure_it64(h);      // continue from the FP32 state in FP64
-                use32 = false;
-                st->fp32_exit = resid / st->ref;
-            }
-            continue;
-        }
-        if (resid <= tol_abs) {
-            status = EP_OK;
-            break;
-        }
+        step_check(h, red, nb);
     }
-    st->iters = iters;
-    st->iters_fp32 = iters32;
-    st->resid = resid;
-    st->eps_rel = vmax > 0 ? h->dtrho * resid / vmax : 0.0;
-    st->status = status;
-    if (status != EP_OK) {
-        ensure_it64(h);
-        roll_back(h);
-        st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        return status;
-    }
-
-    // ---- epilogue: diagnostics of the accepted state, FP64 accumulators ----
-    launch_reset_red(h->red, h->st);
-    launch_diagnostics<double>(args64(h, false, h->cur64), h->lamdot64, h->tii64, h->yld64, h->st);
-    it = h->it64[h->cur64];
-    const double* v[3] = {it[F_VX], it[F_VY], it[F_VZ]};
-    launch_accumulate(h->g, h->prm.dt, 1.0 / h->dx, 1.0 / h->dy, 1.0 / h->dz, v, h->u64, h->e64, h->epsp64,
-                      h->lamdot64, h->st);
-    launch_column_integrals(h->g, it[F_P], it[F_TXX], h->dy, h->dz, h->cols64, h->st);
+    if ((rc = step_finish(h))) return rc;
     double cols[4];
     HIPCHK(h, hipMemcpyAsync(cols, h->cols64, sizeof(cols), hipMemcpyDeviceToHost, h->st));
     if ((rc = read_red(h, red))) return rc;
-    st->sxx_left = cols[0];
-    st->sxx_centre = cols[1];
-    st->sxx_right = cols[2];
-    st->n_yield = (long long)red[RED_NYIELD];
-    st->max_violation = red[RED_VIOL] - 1.0;
-    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    step_report(h, red, cols);
     return EP_OK;
 }
 

@@ -54,6 +54,11 @@ __global__ void k_reset(unsigned long long* r)
 {
     if (threadIdx.x < RED_N) r[threadIdx.x] = 0ull;
 }
+__global__ void k_reset_n(unsigned long long* r, int n)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) r[q] = 0ull;
+}
 
 __global__ void k_walls(AuxGrid g, double* vx, double* vy, double* vz, double ex, double ey, double ez,
                         double lx, double ly, double lz)
@@ -241,6 +246,11 @@ void launch_incr_to_f64(double* d, const double* b64, const float* x, const floa
     k_incr_to_f64<<<blocks_for(n), NT1, 0, s>>>(d, b64, x, b32, n);
 }
 void launch_reset_red(unsigned long long* red, hipStream_t s) { k_reset<<<1, 64, 0, s>>>(red); }
+void launch_reset_red_n(unsigned long long* red, int n_models, hipStream_t s)
+{
+    const int n = n_models * RED_N;
+    k_reset_n<<<(n + 255) / 256, 256, 0, s>>>(red, n);
+}
 
 void launch_set_walls(const AuxGrid& g, double* vx, double* vy, double* vz, const double erate[3],
                       double lx, double ly, double lz, hipStream_t s)

@@ -8,6 +8,15 @@
 
 namespace ep {
 
+// Block index -> logical tile so that consecutive logical tiles run on the
+// same XCD (dispatch is round-robin over the 8 XCDs).  Bijective for any nb.
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int q = nb / 8, r = nb % 8;
+    const int x = b % 8, s = b / 8;
+    return x < r ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
+}
+
 __device__ __forceinline__ double nan_to_inf(double v) { return (v <= DBL_MAX) ? v : INFINITY; }
 
 // Running maximum that keeps a NaN once it has seen one (fmax drops NaN
@@ -73,6 +82,7 @@ __device__ __forceinline__ void block_sum_to(double v, unsigned long long* dst, 
 template <typename R>
 __device__ __forceinline__ R centre_lambda(R J2, R D, R p, R c, R A, R B, R& lamdot, R& tii, R& Y)
 {
+#pragma clang fp contract(on)
     R tii_tr = sqrt(J2) / D;
     Y = A * p + B * c;
     Y = Y > R(0) ? Y : R(0);
@@ -103,6 +113,7 @@ __device__ __forceinline__ double fast_sqrt(double x) { return sqrt(x); }
 template <typename R>
 __device__ __forceinline__ R return_scale(R J2, R D, R invD, R p, R c, R A, R B, R& lam)
 {
+#pragma clang fp contract(on)   // same rounding in every kernel that inlines it
     R Y = A * p + B * c;
     Y = Y > R(0) ? Y : R(0);
     const R sq = fast_sqrt(J2);

@@ -51,13 +51,28 @@ enum { MODE_UPDATE = 0,    // write iteration k+1
        MODE_CHECK = 1,     // write k+1 and reduce the residual
        MODE_PHYS = 2 };    // physical evaluation: reduce the momentum residual only, write nothing
 
-// ---- launchers (ep_sweep.hip) ---------------------------------------------
+// ---- launchers (ep_sweep_unfused.hip, ep_sweep_fused.hip) -------------------
 template <typename R> void launch_sweep_unfused_2d(const SweepArgs<R>& a, int mode, hipStream_t s);
 template <typename R> void launch_sweep_unfused_3d(const SweepArgs<R>& a, int mode, hipStream_t s);
-template <typename R> void launch_sweep_fused_2d(const SweepArgs<R>& a, int mode, hipStream_t s);
 template <typename R> void launch_sweep_fused_3d(const SweepArgs<R>& a, int mode, hipStream_t s);
 // Whether the automatic choice uses the fused sweep for this case.
 bool fused_preferred(int ndim, bool fp32);
+
+// ---- batched 2D sweep (ep_sweep_batch.hip) ---------------------------------
+struct TileRef {
+    int model;             // index into the model table
+    short bx, by;          // tile coordinates in the model's grid
+};
+constexpr int BATCH_SHAPES = 6;
+extern const int kBatchTiles[BATCH_SHAPES][2];   // (TX, TY) of each tile shape
+// One sweep of every tile in list[0 .. *count) with the tile shape `shape`;
+// table[model] holds the model's arguments (reads of iteration k, writes of
+// k+1).  `grid` workgroups walk the list (persistent grid).
+template <typename R>
+void launch_sweep_batch_2d(int shape, const SweepArgs<R>* table, const TileRef* list, const int* count, int mode,
+                           int grid, hipStream_t s);
+// Resident workgroups per CU of the batched kernel with this tile shape.
+template <typename R> int batch_blocks_per_cu(int shape);
 
 // ---- auxiliary kernels (ep_aux.hip) ----------------------------------------
 struct AuxGrid {
@@ -80,6 +95,9 @@ void launch_vel_to_f64(const AuxGrid& g, int d, double* dst, const float* src, d
 void launch_incr_to_f64(double* dst, const double* base64, const float* x32, const float* base32,
                         long n, hipStream_t s);
 void launch_reset_red(unsigned long long* red, hipStream_t s);
+// Reduction slots of n_models consecutive models (a fill kernel, so that it
+// can be captured in a graph).
+void launch_reset_red_n(unsigned long long* red, int n_models, hipStream_t s);
 // Background velocities at the wall faces.
 void launch_set_walls(const AuxGrid& g, double* vx, double* vy, double* vz, const double erate[3],
                       double lx, double ly, double lz, hipStream_t s);

@@ -15,7 +15,8 @@
 //   from and written to HBM once per sweep; the halo reads of neighbouring
 //   tiles are served by L2 (blocks are remapped so that spatial neighbours
 //   run on the same XCD).
-//   2D: the same stages on a single TX x TY tile.
+//   2D: the same stages on a single TX x TY tile (ep_tile2d.h, run by the
+//   tile-list kernel of ep_sweep_batch.hip for single models and batches).
 //
 // The arithmetic of every point is that of the unfused sweep (same formulas,
 // same Jacobi order: all reads are of iteration k, all writes iteration k+1).
@@ -27,15 +28,6 @@ namespace {
 
 __device__ __forceinline__ int mod3(int f) { int r = f % 3; return r < 0 ? r + 3 : r; }
 __device__ __forceinline__ int mod2(int f) { return f & 1; }
-
-// Block index -> logical tile so that consecutive logical tiles run on the
-// same XCD (dispatch is round-robin over the 8 XCDs).  Bijective for any nb.
-__device__ __forceinline__ int xcd_remap(int b, int nb)
-{
-    const int q = nb / 8, r = nb % 8;
-    const int x = b % 8, s = b / 8;
-    return x < r ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
-}
 
 // ----------------------------------------------------------------------- 3D
 // Global data a march step needs is prefetched into registers one step
@@ -393,190 +385,9 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, int nbx, i
     }
 }
 
-// ----------------------------------------------------------------------- 2D
-template <typename R, int TX, int TY, int MODE>
-__global__ __launch_bounds__(TX * TY) void k_fused_2d(SweepArgs<R> a, int nbx, int nby)
-{
-    constexpr int W = TX + 4, H = TY + 4, N = W * H, NT = TX * TY;
-    __shared__ R s_vx[N], s_vy[N], s_Txy[N], s_lam[N], s_p[N], s_sxx[N], s_syy[N], s_nxy[N];
-    __shared__ double s_red[NT / 64 > 0 ? NT / 64 : 1];
-
-    const int lb = xcd_remap(blockIdx.x, nbx * nby);
-    const int bx = lb % nbx, by = lb / nbx;
-    const int i0 = bx * TX, j0 = by * TY;
-    const int nx = a.nx, ny = a.ny;
-    const long sy = a.sy;
-    const int tid = threadIdx.x;
-    const int hx = (i0 + TX == nx) ? 1 : 0;
-    const int hy = (j0 + TY == ny) ? 1 : 0;
-    const R idx = a.idx, idy = a.idy, igt = a.igt, igd = a.igd, ikt = a.ikt, ikd = a.ikd, D = a.D;
-    double rmax = 0.0, mmax = 0.0, vmax = 0.0, smax = 0.0;   // combined, momentum-only, |v|, |stress|
-
-    // issue every global load of the tile up front (velocities, shear stresses
-    // of iteration k and of the increment start, centre data), then the stages
-    constexpr int NQ = (N + NT - 1) / NT;
-    constexpr int CW = TX + 2, CN = (TX + 2) * (TY + 2), NR = (CN + NT - 1) / NT;
-    R gvx[NQ], gvy[NQ], gxy[NQ], gxyo[NQ];
-    R gp[NR], gpo[NR], gsx[NR], gsxo[NR], gsy[NR], gsyo[NR], gc[NR];
-#pragma unroll
-    for (int u = 0; u < NQ; ++u) {
-        const int q = tid + NT * u;
-        const int i = i0 - 2 + q % W, j = j0 - 2 + q / W;
-        const long e = i + sy * j;
-        const bool ok = q < N;
-        gvx[u] = (ok && i >= 0 && i <= nx && j >= 0 && j < ny) ? a.it[F_VX][e] : R(0);
-        gvy[u] = (ok && i >= 0 && i < nx && j >= 0 && j <= ny) ? a.it[F_VY][e] : R(0);
-        const bool exy = ok && i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1;
-        gxy[u] = exy ? a.it[F_TXY][e] : R(0);
-        gxyo[u] = exy ? a.old[O_TXY][e] : R(0);
-    }
-#pragma unroll
-    for (int u = 0; u < NR; ++u) {
-        const int r = tid + NT * u;
-        const int i = i0 - 1 + r % CW, j = j0 - 1 + r / CW;
-        const long e = i + sy * j;
-        const bool ok = r < CN && i >= 0 && i < nx && j >= 0 && j < ny;
-        gp[u] = ok ? a.it[F_P][e] : R(0);
-        gpo[u] = ok ? a.old[O_P][e] : R(0);
-        gsx[u] = ok ? a.it[F_TXX][e] : R(0);
-        gsxo[u] = ok ? a.old[O_TXX][e] : R(0);
-        gsy[u] = ok ? a.it[F_TYY][e] : R(0);
-        gsyo[u] = ok ? a.old[O_TYY][e] : R(0);
-        gc[u] = ok ? a.coh[e] : R(0);
-    }
-#pragma unroll
-    for (int u = 0; u < NQ; ++u) {
-        const int q = tid + NT * u;
-        if (q < N) {
-            s_vx[q] = gvx[u];
-            s_vy[q] = gvy[u];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < NQ; ++u) {
-        const int q = tid + NT * u;
-        if (q >= N) continue;
-        const int la = q % W, lbb = q / W;
-        if (la < 1 || lbb < 1) continue;
-        const int i = i0 - 2 + la, j = j0 - 2 + lbb;
-        R t = R(0);
-        if (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1) {
-            R e2 = (s_vx[q] - s_vx[q - W]) * idy + (s_vy[q] - s_vy[q - 1]) * idx;
-            t = gxy[u] * igt + gxyo[u] * igd + e2;
-        }
-        s_Txy[q] = t;
-    }
-    __syncthreads();
-    {
-#pragma unroll
-        for (int u = 0; u < NR; ++u) {
-            const int r = tid + NT * u;
-            if (r >= CN) continue;
-            const int la = 1 + r % CW, lbb = 1 + r / CW;
-            const int q = la + W * lbb;
-            const int i = i0 - 2 + la, j = j0 - 2 + lbb;
-            if (!(i >= 0 && i < nx && j >= 0 && j < ny)) {
-                s_lam[q] = R(0);
-                s_p[q] = R(0);
-                s_sxx[q] = R(0);
-                s_syy[q] = R(0);
-                continue;
-            }
-            const long e = i + sy * j;
-            R dvx = (s_vx[q + 1] - s_vx[q]) * idx + a.ebx;
-            R dvy = (s_vy[q + W] - s_vy[q]) * idy + a.eby;
-            R div = dvx + dvy;
-            const R pk = gp[u], txk = gsx[u], tyk = gsy[u];
-            R pn = (pk * ikt + gpo[u] * ikd - div) * a.ikk;
-            R Txx = txk * igt + gsxo[u] * igd + R(2) * (dvx - div / R(3));
-            R Tyy = tyk * igt + gsyo[u] * igd + R(2) * (dvy - div / R(3));
-            R Tb = R(0.25) * (s_Txy[q] + s_Txy[q + 1] + s_Txy[q + W] + s_Txy[q + W + 1]);
-            R J2 = R(0.5) * (Txx * Txx + Tyy * Tyy) + Tb * Tb;
-            R lam;
-            const R sc_ = return_scale(J2, D, a.invD, pn, gc[u], a.A, a.B, lam);
-            R txx = Txx * sc_, tyy = Tyy * sc_;
-            s_lam[q] = lam;
-            s_p[q] = pn;
-            s_sxx[q] = txx;
-            s_syy[q] = tyy;
-            if (la >= 2 && la < TX + 2 && lbb >= 2 && lbb < TY + 2) {
-                a.nx_[F_P][e] = pn;
-                a.nx_[F_TXX][e] = txx;
-                a.nx_[F_TYY][e] = tyy;
-                if (MODE == MODE_CHECK) {
-                    R dp = fabs(pn - pk) * a.rK;
-                    R dt = nmax(fabs(txx - txk), fabs(tyy - tyk)) * a.rG;
-                    rmax = nmax(rmax, nmax((double)dp, (double)dt));
-                    smax = nmax(smax, (double)nmax(nmax(fabs(pn), fabs(txx)), fabs(tyy)));
-                }
-            }
-        }
-    }
-    __syncthreads();
-    {
-        constexpr int EW = TX + 1, EN = (TX + 1) * (TY + 1);
-        for (int r = tid; r < EN; r += NT) {
-            const int la = 2 + r % EW, lbb = 2 + r / EW;
-            const int q = la + W * lbb;
-            const int i = i0 - 2 + la, j = j0 - 2 + lbb;
-            R t = R(0);
-            if (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1) {
-                R lv = R(0.25) * (s_lam[q - W - 1] + s_lam[q - W] + s_lam[q - 1] + s_lam[q]);
-                t = s_Txy[q] * fast_rcp(D + lv);
-            }
-            s_nxy[q] = t;
-            if (la < TX + 2 + hx && lbb < TY + 2 + hy && i <= nx && j <= ny) {
-                const long e = i + sy * j;
-                a.nx_[F_TXY][e] = t;
-                if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)(fabs(t - a.it[F_TXY][e]) * a.rG));
-            }
-        }
-    }
-    __syncthreads();
-    {
-        constexpr int FW = TX + 1, FN = (TX + 1) * (TY + 1);
-        for (int r = tid; r < FN; r += NT) {
-            const int la = 2 + r % FW, lbb = 2 + r / FW;
-            const int q = la + W * lbb;
-            const int i = i0 - 2 + la, j = j0 - 2 + lbb;
-            const long e = i + sy * j;
-            if (la < TX + 2 + hx && lbb < TY + 2 && i <= nx && j < ny) {
-                R v = s_vx[q];
-                if (i >= 1 && i <= nx - 1) {
-                    R Rx = ((s_sxx[q] - s_p[q]) - (s_sxx[q - 1] - s_p[q - 1])) * idx + (s_nxy[q + W] - s_nxy[q]) * idy;
-                    v = v + a.dtrho * Rx;
-                    mmax = nmax(mmax, (double)fabs(Rx));
-                }
-                if (MODE != MODE_PHYS) a.nx_[F_VX][e] = v;
-                vmax = nmax(vmax, (double)fabs(v));
-            }
-            if (la < TX + 2 && lbb < TY + 2 + hy && i < nx && j <= ny) {
-                R v = s_vy[q];
-                if (j >= 1 && j <= ny - 1) {
-                    R Ry = ((s_syy[q] - s_p[q]) - (s_syy[q - W] - s_p[q - W])) * idy + (s_nxy[q + 1] - s_nxy[q]) * idx;
-                    v = v + a.dtrho * Ry;
-                    mmax = nmax(mmax, (double)fabs(Ry));
-                }
-                if (MODE != MODE_PHYS) a.nx_[F_VY][e] = v;
-                vmax = nmax(vmax, (double)fabs(v));
-            }
-        }
-    }
-    if (MODE != MODE_UPDATE) {
-        block_max_to<NT>(mmax, a.red + RED_MOM, s_red);
-        if (MODE == MODE_CHECK) {
-            block_max_to<NT>(fmax(rmax, mmax), a.red + RED_RESID, s_red);
-            block_max_to<NT>(vmax, a.red + RED_VMAX, s_red);
-            block_max_to<NT>(smax, a.red + RED_SMAX, s_red);
-        }
-    }
-}
-
 // tile shapes
 constexpr int T3X = 32, T3Y = 16, T3Z = 32;         // FP32 3D
 constexpr int D3X = 32, D3Y = 4, D3Z = 32;          // FP64 3D (LDS-limited)
-constexpr int T2X = 64, T2Y = 8;                    // 2D
 
 template <typename R> struct Tile3;
 template <> struct Tile3<float> { static constexpr int X = T3X, Y = T3Y, Z = T3Z; };
@@ -590,12 +401,6 @@ void run_3d(const SweepArgs<R>& a, hipStream_t s)
     k_fused_3d<R, TX, TY, ZC, MODE><<<nbx * nby * nbz, TX * TY, 0, s>>>(a, nbx, nby, nbz);
 }
 
-template <typename R, int MODE>
-void run_2d(const SweepArgs<R>& a, hipStream_t s)
-{
-    const int nbx = (a.nx + T2X - 1) / T2X, nby = (a.ny + T2Y - 1) / T2Y;
-    k_fused_2d<R, T2X, T2Y, MODE><<<nbx * nby, T2X * T2Y, 0, s>>>(a, nbx, nby);
-}
 
 }  // namespace
 
@@ -611,16 +416,7 @@ void launch_sweep_fused_3d(const SweepArgs<R>& a, int mode, hipStream_t s)
     else run_3d<R, MODE_PHYS>(a, s);
 }
 
-template <typename R>
-void launch_sweep_fused_2d(const SweepArgs<R>& a, int mode, hipStream_t s)
-{
-    if (mode == MODE_UPDATE) run_2d<R, MODE_UPDATE>(a, s);
-    else if (mode == MODE_CHECK) run_2d<R, MODE_CHECK>(a, s);
-    else run_2d<R, MODE_PHYS>(a, s);
-}
 
-template void launch_sweep_fused_2d<double>(const SweepArgs<double>&, int, hipStream_t);
-template void launch_sweep_fused_2d<float>(const SweepArgs<float>&, int, hipStream_t);
 template void launch_sweep_fused_3d<double>(const SweepArgs<double>&, int, hipStream_t);
 template void launch_sweep_fused_3d<float>(const SweepArgs<float>&, int, hipStream_t);
 

@@ -1,0 +1,197 @@
+// One fused 2D PT sweep over a TX x TY tile of cells (shared by the
+// single-model kernel and the batched persistent kernel).
+//
+// The workgroup loads velocities, shear stresses (iteration k and increment
+// start) over a 2-point halo and the centre data over a 1-point halo, all
+// global loads issued before the first stage; then in LDS: shear trials at
+// vertices, centre update (pressure, deviatoric trial, return mapping),
+// vertex stresses from the averaged centre Lambda, velocities.  Halo points
+// are recomputed, so tiles are independent within a sweep.  A caller that
+// runs several tiles in one workgroup must put a barrier between them (the
+// last stage reads LDS that the next tile's first stage overwrites).
+#pragma once
+#include "ep_device.h"
+
+namespace ep {
+
+template <typename R, int TX, int TY, int MODE>
+__device__ __forceinline__ void sweep_tile_2d(const SweepArgs<R>& a, int bx, int by)
+{
+    // multiply-adds are fused only within one expression, so that every
+    // caller (single-model or batched kernel) rounds each point identically
+#pragma clang fp contract(on)
+    constexpr int W = TX + 4, H = TY + 4, N = W * H, NT = TX * TY;
+    __shared__ R s_vx[N], s_vy[N], s_Txy[N], s_lam[N], s_p[N], s_sxx[N], s_syy[N], s_nxy[N];
+    __shared__ double s_red[NT / 64 > 0 ? NT / 64 : 1];
+
+    const int i0 = bx * TX, j0 = by * TY;
+    const int nx = a.nx, ny = a.ny;
+    const long sy = a.sy;
+    const int tid = threadIdx.x;
+    const int hx = (i0 + TX == nx) ? 1 : 0;
+    const int hy = (j0 + TY == ny) ? 1 : 0;
+    const R idx = a.idx, idy = a.idy, igt = a.igt, igd = a.igd, ikt = a.ikt, ikd = a.ikd, D = a.D;
+    double rmax = 0.0, mmax = 0.0, vmax = 0.0, smax = 0.0;   // combined, momentum-only, |v|, |stress|
+
+    // issue every global load of the tile up front (velocities, shear stresses
+    // of iteration k and of the increment start, centre data), then the stages
+    constexpr int NQ = (N + NT - 1) / NT;
+    constexpr int CW = TX + 2, CN = (TX + 2) * (TY + 2), NR = (CN + NT - 1) / NT;
+    R gvx[NQ], gvy[NQ], gxy[NQ], gxyo[NQ];
+    R gp[NR], gpo[NR], gsx[NR], gsxo[NR], gsy[NR], gsyo[NR], gc[NR];
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+        const int q = tid + NT * u;
+        const int i = i0 - 2 + q % W, j = j0 - 2 + q / W;
+        const long e = i + sy * j;
+        const bool ok = q < N;
+        gvx[u] = (ok && i >= 0 && i <= nx && j >= 0 && j < ny) ? a.it[F_VX][e] : R(0);
+        gvy[u] = (ok && i >= 0 && i < nx && j >= 0 && j <= ny) ? a.it[F_VY][e] : R(0);
+        const bool exy = ok && i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1;
+        gxy[u] = exy ? a.it[F_TXY][e] : R(0);
+        gxyo[u] = exy ? a.old[O_TXY][e] : R(0);
+    }
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+        const int r = tid + NT * u;
+        const int i = i0 - 1 + r % CW, j = j0 - 1 + r / CW;
+        const long e = i + sy * j;
+        const bool ok = r < CN && i >= 0 && i < nx && j >= 0 && j < ny;
+        gp[u] = ok ? a.it[F_P][e] : R(0);
+        gpo[u] = ok ? a.old[O_P][e] : R(0);
+        gsx[u] = ok ? a.it[F_TXX][e] : R(0);
+        gsxo[u] = ok ? a.old[O_TXX][e] : R(0);
+        gsy[u] = ok ? a.it[F_TYY][e] : R(0);
+        gsyo[u] = ok ? a.old[O_TYY][e] : R(0);
+        gc[u] = ok ? a.coh[e] : R(0);
+    }
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+        const int q = tid + NT * u;
+        if (q < N) {
+            s_vx[q] = gvx[u];
+            s_vy[q] = gvy[u];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+        const int q = tid + NT * u;
+        if (q >= N) continue;
+        const int la = q % W, lbb = q / W;
+        if (la < 1 || lbb < 1) continue;
+        const int i = i0 - 2 + la, j = j0 - 2 + lbb;
+        R t = R(0);
+        if (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1) {
+            R e2 = (s_vx[q] - s_vx[q - W]) * idy + (s_vy[q] - s_vy[q - 1]) * idx;
+            t = gxy[u] * igt + gxyo[u] * igd + e2;
+        }
+        s_Txy[q] = t;
+    }
+    __syncthreads();
+    {
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            const int r = tid + NT * u;
+            if (r >= CN) continue;
+            const int la = 1 + r % CW, lbb = 1 + r / CW;
+            const int q = la + W * lbb;
+            const int i = i0 - 2 + la, j = j0 - 2 + lbb;
+            if (!(i >= 0 && i < nx && j >= 0 && j < ny)) {
+                s_lam[q] = R(0);
+                s_p[q] = R(0);
+                s_sxx[q] = R(0);
+                s_syy[q] = R(0);
+                continue;
+            }
+            const long e = i + sy * j;
+            R dvx = (s_vx[q + 1] - s_vx[q]) * idx + a.ebx;
+            R dvy = (s_vy[q + W] - s_vy[q]) * idy + a.eby;
+            R div = dvx + dvy;
+            const R pk = gp[u], txk = gsx[u], tyk = gsy[u];
+            R pn = (pk * ikt + gpo[u] * ikd - div) * a.ikk;
+            R Txx = txk * igt + gsxo[u] * igd + R(2) * (dvx - div / R(3));
+            R Tyy = tyk * igt + gsyo[u] * igd + R(2) * (dvy - div / R(3));
+            R Tb = R(0.25) * (s_Txy[q] + s_Txy[q + 1] + s_Txy[q + W] + s_Txy[q + W + 1]);
+            R J2 = R(0.5) * (Txx * Txx + Tyy * Tyy) + Tb * Tb;
+            R lam;
+            const R sc_ = return_scale(J2, D, a.invD, pn, gc[u], a.A, a.B, lam);
+            R txx = Txx * sc_, tyy = Tyy * sc_;
+            s_lam[q] = lam;
+            s_p[q] = pn;
+            s_sxx[q] = txx;
+            s_syy[q] = tyy;
+            if (la >= 2 && la < TX + 2 && lbb >= 2 && lbb < TY + 2) {
+                a.nx_[F_P][e] = pn;
+                a.nx_[F_TXX][e] = txx;
+                a.nx_[F_TYY][e] = tyy;
+                if (MODE == MODE_CHECK) {
+                    R dp = fabs(pn - pk) * a.rK;
+                    R dt = nmax(fabs(txx - txk), fabs(tyy - tyk)) * a.rG;
+                    rmax = nmax(rmax, nmax((double)dp, (double)dt));
+                    smax = nmax(smax, (double)nmax(nmax(fabs(pn), fabs(txx)), fabs(tyy)));
+                }
+            }
+        }
+    }
+    __syncthreads();
+    {
+        constexpr int EW = TX + 1, EN = (TX + 1) * (TY + 1);
+        for (int r = tid; r < EN; r += NT) {
+            const int la = 2 + r % EW, lbb = 2 + r / EW;
+            const int q = la + W * lbb;
+            const int i = i0 - 2 + la, j = j0 - 2 + lbb;
+            R t = R(0);
+            if (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1) {
+                R lv = R(0.25) * (s_lam[q - W - 1] + s_lam[q - W] + s_lam[q - 1] + s_lam[q]);
+                t = s_Txy[q] * fast_rcp(D + lv);
+            }
+            s_nxy[q] = t;
+            if (la < TX + 2 + hx && lbb < TY + 2 + hy && i <= nx && j <= ny) {
+                const long e = i + sy * j;
+                a.nx_[F_TXY][e] = t;
+                if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)(fabs(t - a.it[F_TXY][e]) * a.rG));
+            }
+        }
+    }
+    __syncthreads();
+    {
+        constexpr int FW = TX + 1, FN = (TX + 1) * (TY + 1);
+        for (int r = tid; r < FN; r += NT) {
+            const int la = 2 + r % FW, lbb = 2 + r / FW;
+            const int q = la + W * lbb;
+            const int i = i0 - 2 + la, j = j0 - 2 + lbb;
+            const long e = i + sy * j;
+            if (la < TX + 2 + hx && lbb < TY + 2 && i <= nx && j < ny) {
+                R v = s_vx[q];
+                if (i >= 1 && i <= nx - 1) {
+                    R Rx = ((s_sxx[q] - s_p[q]) - (s_sxx[q - 1] - s_p[q - 1])) * idx + (s_nxy[q + W] - s_nxy[q]) * idy;
+                    v = v + a.dtrho * Rx;
+                    mmax = nmax(mmax, (double)fabs(Rx));
+                }
+                if (MODE != MODE_PHYS) a.nx_[F_VX][e] = v;
+                vmax = nmax(vmax, (double)fabs(v));
+            }
+            if (la < TX + 2 && lbb < TY + 2 + hy && i < nx && j <= ny) {
+                R v = s_vy[q];
+                if (j >= 1 && j <= ny - 1) {
+                    R Ry = ((s_syy[q] - s_p[q]) - (s_syy[q - W] - s_p[q - W])) * idy + (s_nxy[q + 1] - s_nxy[q]) * idx;
+                    v = v + a.dtrho * Ry;
+                    mmax = nmax(mmax, (double)fabs(Ry));
+                }
+                if (MODE != MODE_PHYS) a.nx_[F_VY][e] = v;
+                vmax = nmax(vmax, (double)fabs(v));
+            }
+        }
+    }
+    if (MODE != MODE_UPDATE) {
+        block_max_to<NT>(mmax, a.red + RED_MOM, s_red);
+        if (MODE == MODE_CHECK) {
+            block_max_to<NT>(fmax(rmax, mmax), a.red + RED_RESID, s_red);
+            block_max_to<NT>(vmax, a.red + RED_VMAX, s_red);
+            block_max_to<NT>(smax, a.red + RED_SMAX, s_red);
+        }
+    }
+}
+
+}  // namespace ep

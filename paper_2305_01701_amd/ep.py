@@ -34,7 +34,10 @@ FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
 # every symbol include/ep.h declares
 SYMBOLS = ["ep_abi_version", "ep_workspace_size", "ep_init", "ep_load_step", "ep_sweep",
            "ep_residual", "ep_fields", "ep_field_shape", "ep_destroy", "ep_last_error",
-           "ep_enable_timing", "ep_sweep_timing", "ep_step_history"]
+           "ep_enable_timing", "ep_sweep_timing", "ep_step_history",
+           "ep_batch_workspace_size", "ep_batch_init", "ep_batch_tune", "ep_batch_tile_shape",
+           "ep_batch_load_step", "ep_batch_model", "ep_batch_enable_timing", "ep_batch_timing",
+           "ep_batch_destroy", "ep_batch_last_error"]
 
 
 class ep_params(C.Structure):
@@ -97,6 +100,21 @@ def lib():
         L.ep_enable_timing.argtypes = [vp, C.c_int]
         L.ep_sweep_timing.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_long)]
         L.ep_step_history.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_int]
+        L.ep_batch_workspace_size.argtypes = [C.c_int, C.POINTER(ep_params), C.POINTER(C.c_size_t)]
+        L.ep_batch_init.argtypes = [C.c_int, C.POINTER(ep_params), C.POINTER(C.POINTER(C.c_double)), vp,
+                                    C.c_size_t, vp, C.POINTER(vp)]
+        L.ep_batch_tune.argtypes = [vp, C.c_int]
+        L.ep_batch_tile_shape.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.ep_batch_load_step.argtypes = [vp, C.POINTER(ep_step_stats)]
+        L.ep_batch_model.restype = vp
+        L.ep_batch_model.argtypes = [vp, C.c_int]
+        L.ep_batch_enable_timing.argtypes = [vp, C.c_int]
+        L.ep_batch_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double), C.POINTER(C.c_long)]
+        L.ep_batch_destroy.argtypes = [vp]
+        L.ep_batch_destroy.restype = None
+        L.ep_batch_last_error.restype = C.c_char_p
+        L.ep_batch_last_error.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -159,6 +177,61 @@ def ep_last_error(h) -> str:
     return lib().ep_last_error(h).decode()
 
 
+def _params_array(params):
+    arr = (ep_params * len(params))()
+    for i, p in enumerate(params):
+        arr[i] = p
+    return arr
+
+
+def ep_batch_workspace_size(params) -> int:
+    n = C.c_size_t(0)
+    rc = lib().ep_batch_workspace_size(len(params), _params_array(params), C.byref(n))
+    if rc != EP_OK:
+        raise ValueError(f"ep_batch_workspace_size: {rc}")
+    return n.value
+
+
+def ep_batch_init(params, cohesions, d_workspace: int, ws_bytes: int, stream: int):
+    n = len(params)
+    keep = [None if c is None else np.ascontiguousarray(c, dtype=np.float64) for c in cohesions]
+    ptrs = (C.POINTER(C.c_double) * n)()
+    for i, c in enumerate(keep):
+        ptrs[i] = C.POINTER(C.c_double)() if c is None else c.ctypes.data_as(C.POINTER(C.c_double))
+    b = C.c_void_p()
+    rc = lib().ep_batch_init(n, _params_array(params), ptrs, C.c_void_p(d_workspace), ws_bytes,
+                             C.c_void_p(stream), C.byref(b))
+    return rc, b
+
+
+def ep_batch_load_step(b, n: int) -> tuple:
+    st = (ep_step_stats * n)()
+    rc = lib().ep_batch_load_step(b, st)
+    return rc, [s.as_dict() for s in st]
+
+
+def ep_batch_tune(b, reps: int) -> int:
+    return lib().ep_batch_tune(b, reps)
+
+
+def ep_batch_tile_shape(b, i: int) -> tuple:
+    tx, ty = C.c_int(0), C.c_int(0)
+    rc = lib().ep_batch_tile_shape(b, i, C.byref(tx), C.byref(ty))
+    return rc, (tx.value, ty.value)
+
+
+def ep_batch_model(b, i: int):
+    return C.c_void_p(lib().ep_batch_model(b, i))
+
+
+def ep_batch_destroy(b) -> None:
+    lib().ep_batch_destroy(b)
+
+
+def ep_batch_last_error(b) -> str:
+    return lib().ep_batch_last_error(b).decode()
+
+
 # ---- convenience -----------------------------------------------------------
 def ep_step_history(h, cap: int = 1 << 20) -> tuple:
     r = np.zeros(cap, dtype=np.float64)
@@ -189,7 +262,50 @@ class EpError(RuntimeError):
     pass
 
 
-class Solver:
+class ModelView:
+    """Field access and diagnostics of one solver handle."""
+
+    def __init__(self, h):
+        self.h = h
+
+    def _check(self, rc, what):
+        if rc not in (EP_OK,):
+            raise EpError(f"{what} failed with {rc}: {ep_last_error(self.h)}")
+
+    def sweep(self, n: int = 1) -> float:
+        rc, r = ep_sweep(self.h, n)
+        self._check(rc, "ep_sweep")
+        return r
+
+    def history(self) -> tuple:
+        """(normalised residual, precision) at each check of the last increment."""
+        return ep_step_history(self.h)
+
+    def residual(self) -> dict:
+        rc, r = ep_residual(self.h)
+        self._check(rc, "ep_residual")
+        return r
+
+    def size(self, name: str) -> int:
+        return ep_field_shape(self.h, FIELD_ID[name])[0]
+
+    def get(self, name: str) -> np.ndarray:
+        n = self.size(name)
+        out = np.zeros(max(n, 0), dtype=np.float64)
+        if n > 0:
+            self._check(ep_fields(self.h, FIELD_ID[name], EP_GET, out), f"get {name}")
+        return out
+
+    def set(self, name: str, values) -> None:
+        a = np.ascontiguousarray(values, dtype=np.float64).ravel()
+        self._check(ep_fields(self.h, FIELD_ID[name], EP_SET, a), f"set {name}")
+
+    def fields(self, names=None) -> Dict[str, np.ndarray]:
+        names = names or [n for n in FIELDS if self.size(n) > 0]
+        return {n: self.get(n) for n in names}
+
+
+class Solver(ModelView):
     """One model on the GPU (device memory from torch, work on its stream)."""
 
     def __init__(self, model, cohesion: Optional[np.ndarray] = None, precision: int = EP_FP64,
@@ -227,47 +343,11 @@ class Solver:
         except Exception:
             pass
 
-    def _check(self, rc, what):
-        if rc not in (EP_OK,):
-            raise EpError(f"{what} failed with {rc}: {ep_last_error(self.h)}")
-
     def load_step(self) -> dict:
         rc, st = ep_load_step(self.h)
         if rc not in (EP_OK, EP_ENOTCONV, EP_EDIVERGED):
             self._check(rc, "ep_load_step")
         return st
-
-    def sweep(self, n: int = 1) -> float:
-        rc, r = ep_sweep(self.h, n)
-        self._check(rc, "ep_sweep")
-        return r
-
-    def history(self) -> tuple:
-        """(normalised residual, precision) at each check of the last increment."""
-        return ep_step_history(self.h)
-
-    def residual(self) -> dict:
-        rc, r = ep_residual(self.h)
-        self._check(rc, "ep_residual")
-        return r
-
-    def size(self, name: str) -> int:
-        return ep_field_shape(self.h, FIELD_ID[name])[0]
-
-    def get(self, name: str) -> np.ndarray:
-        n = self.size(name)
-        out = np.zeros(max(n, 0), dtype=np.float64)
-        if n > 0:
-            self._check(ep_fields(self.h, FIELD_ID[name], EP_GET, out), f"get {name}")
-        return out
-
-    def set(self, name: str, values) -> None:
-        a = np.ascontiguousarray(values, dtype=np.float64).ravel()
-        self._check(ep_fields(self.h, FIELD_ID[name], EP_SET, a), f"set {name}")
-
-    def fields(self, names=None) -> Dict[str, np.ndarray]:
-        names = names or [n for n in FIELDS if self.size(n) > 0]
-        return {n: self.get(n) for n in names}
 
     def enable_timing(self, on: bool = True) -> None:
         self._check(lib().ep_enable_timing(self.h, 1 if on else 0), "ep_enable_timing")
@@ -276,3 +356,76 @@ class Solver:
         ms, n = C.c_double(0), C.c_long(0)
         self._check(lib().ep_sweep_timing(self.h, precision, C.byref(ms), C.byref(n)), "ep_sweep_timing")
         return ms.value, n.value
+
+
+class Batch:
+    """Many independent 2D models solved together (one workspace from torch)."""
+
+    def __init__(self, models, cohesions=None, precision: int = EP_FP32_FIELDS, device: str = "cuda:0",
+                 stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise EpError("no GPU visible: the solver runs only on the device")
+        self.models = list(models)
+        self.n = len(self.models)
+        self.params = [params_from_model(m, precision) for m in self.models]
+        self.ws_bytes = ep_batch_workspace_size(self.params)
+        self.device = torch.device(device)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        if cohesions is None:
+            from ep_workloads import cohesion_field
+            cohesions = [cohesion_field(m) for m in self.models]
+        with torch.cuda.device(self.device):
+            rc, b = ep_batch_init(self.params, cohesions, base, self.ws_bytes, self.stream.cuda_stream)
+        if rc != EP_OK:
+            raise EpError(f"ep_batch_init failed with {rc}")
+        self.b = b
+
+    def close(self):
+        if getattr(self, "b", None):
+            ep_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != EP_OK:
+            raise EpError(f"{what} failed with {rc}: {ep_batch_last_error(self.b)}")
+
+    def tune(self, reps: int = 5) -> list:
+        self._check(ep_batch_tune(self.b, reps), "ep_batch_tune")
+        return self.tile_shapes()
+
+    def tile_shapes(self) -> list:
+        out = []
+        for i in range(self.n):
+            rc, t = ep_batch_tile_shape(self.b, i)
+            self._check(rc, "ep_batch_tile_shape")
+            out.append(t)
+        return out
+
+    def load_step(self) -> list:
+        rc, st = ep_batch_load_step(self.b, self.n)
+        if rc not in (EP_OK, EP_ENOTCONV, EP_EDIVERGED):
+            self._check(rc, "ep_batch_load_step")
+        return st
+
+    def model(self, i: int) -> ModelView:
+        if not 0 <= i < self.n:
+            raise IndexError(i)
+        return ModelView(ep_batch_model(self.b, i))
+
+    def enable_timing(self, on: bool = True) -> None:
+        self._check(lib().ep_batch_enable_timing(self.b, 1 if on else 0), "ep_batch_enable_timing")
+
+    def timing(self) -> dict:
+        ms, c32, c64, n = C.c_double(0), C.c_double(0), C.c_double(0), C.c_long(0)
+        self._check(lib().ep_batch_timing(self.b, C.byref(ms), C.byref(c32), C.byref(c64), C.byref(n)),
+                    "ep_batch_timing")
+        return {"ms": ms.value, "cell_sweeps32": c32.value, "cell_sweeps64": c64.value, "replays": n.value}

@@ -75,3 +75,47 @@ def test_init_rejects_small_workspace_without_touching_device(E):
 
 def test_last_error_without_handle(E):
     assert E.lib().ep_last_error(None) == b"no handle"
+
+
+def _batch_rc(E, models, precisions=None):
+    ps = [E.params_from_model(m, precision=(precisions[i] if precisions else E.EP_FP32_FIELDS))
+          for i, m in enumerate(models)]
+    n = C.c_size_t(0)
+    return E.lib().ep_batch_workspace_size(len(ps), E._params_array(ps), C.byref(n)), n.value
+
+
+def test_batch_workspace_is_sum_of_models_plus_tables(E):
+    from ep_workloads import c4_batch
+    models = c4_batch(0, n_models=8)
+    rc, total = _batch_rc(E, models)
+    assert rc == E.EP_OK
+    singles = sum(E.ep_workspace_size(E.params_from_model(m, precision=E.EP_FP32_FIELDS)) for m in models)
+    assert singles < total < singles + 64 * 2 ** 20
+
+
+@pytest.mark.parametrize("case", ["3d", "odd_check", "mixed_precision", "empty", "bad_model"])
+def test_batch_rejects_invalid_sets(E, case):
+    a, b = c1_small_2d(), c1_small_2d().with_(nx=40)
+    precs = None
+    if case == "3d":
+        models = [a, c3_3d(7)]
+    elif case == "odd_check":
+        models = [a.with_(n_check=11), b.with_(n_check=11)]
+    elif case == "mixed_precision":
+        models, precs = [a, b], [E.EP_FP64, E.EP_FP32_FIELDS]
+    elif case == "empty":
+        n = C.c_size_t(0)
+        assert E.lib().ep_batch_workspace_size(0, None, C.byref(n)) == E.EP_EINVAL
+        return
+    else:
+        models = [a, b.with_(psi_deg=3.0)]
+    assert _batch_rc(E, models, precs)[0] == E.EP_EINVAL
+
+
+def test_batch_init_rejects_small_workspace(E):
+    models = [c1_small_2d(), c1_small_2d().with_(nx=40)]
+    ps = [E.params_from_model(m) for m in models]
+    need = E.ep_batch_workspace_size(ps)
+    rc, b = E.ep_batch_init(ps, [None, None], 256, need - 256, 0)
+    assert rc == E.EP_ENOMEM and not b.value
+    assert E.lib().ep_batch_last_error(None) == b"no batch"

@@ -1,0 +1,155 @@
+"""GPU parity of the batched 2D driver (many models in one persistent launch
+per sweep, graph replays, per-model retirement) through the C ABI.
+
+Every model of a batch must give what the FP64 oracle gives for that model
+alone (fields within 1e-6 in FP64, 1e-4 with FP32 fields; iteration counts
+and yielding cells exact in FP64), and exactly what the single-model solver
+gives (same kernels' arithmetic, same per-model decisions): bitwise equal
+fields and equal iteration counts, whatever tile shape the autotuner picks.
+"""
+import numpy as np
+import pytest
+
+from ep_workloads import Model, cohesion_field
+from gpu_common import IT2, accum_names, compare, compare_accumulators, say, solver
+from oracle.oracle import Oracle
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = 0, 1
+STEPS = 6
+
+
+def batch_models():
+    """Uneven sizes, parameters and inclusions; large increments so that the
+    models yield at different steps; one stays elastic (high cohesion)."""
+    base = dict(ndim=2, dt=2e-4, tol=1e-8, n_check=10, steps=STEPS)
+    return [
+        Model(nx=37, ny=29, lx=1.3, phi_deg=25.0, incl_radius=0.2, incl_centre=(0.07, -0.04, 0), **base),
+        Model(nx=64, ny=64, phi_deg=35.0, c0=1.2e-3, incl_radius=0.15, incl_centre=(-0.1, 0.05, 0), **base),
+        Model(nx=31, ny=45, ly=1.4, incl_radius=0.12, incl_centre=(0.03, 0.06, 0), **base),
+        Model(nx=50, ny=21, lx=2.0, c0=5e-2, incl_centre=(0.2, 0.01, 0), **base),
+        Model(nx=23, ny=23, phi_deg=20.0, c0=2.5e-3, incl_radius=0.25, incl_centre=(-0.04, -0.02, 0), **base),
+    ]
+
+
+def iters_agree(g_iters, o_iters, o_hist, m):
+    """Equal iteration counts, or a tie at the tolerance level: when a model's
+    state sits at the tolerance (an elastic increment starting from the
+    previous increment's tolerance-level error), every check is decided by
+    that error, which differs between the two implementations by rounding.
+    Accepted if the oracle's normalised residual at the checks between the two
+    stopping points lies within a factor 4 of the tolerance."""
+    if g_iters == o_iters:
+        return True
+    if g_iters % m.n_check or o_iters % m.n_check:
+        return False
+    lo, hi = sorted((g_iters, o_iters))
+    checks = [o_hist[k // m.n_check - 1] for k in range(lo, hi + 1, m.n_check) if k <= o_iters]
+    return all(m.tol / 4 <= r <= 4 * m.tol for r in checks)
+
+
+def make_batch(models, prec):
+    from paper_2305_01701_amd.ep import Batch
+    return Batch(models, [cohesion_field(m) for m in models], precision=prec)
+
+
+def run_batch(models, prec, steps, tune=False):
+    b = make_batch(models, prec)
+    shapes = b.tune(2) if tune else b.tile_shapes()
+    out = []
+    for n in range(steps):
+        st = b.load_step()
+        say("batch step", n + 1, [(s["status"], s["iters"], s["iters_fp32"], s["n_yield"]) for s in st])
+        out.append(st)
+    return b, out, shapes
+
+
+def run_single(m, prec, steps):
+    g = solver(m, precision=prec)
+    return g, [g.load_step() for _ in range(steps)]
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32], ids=["fp64", "fp32"])
+def test_batch_matches_single_and_oracle(prec):
+    models = batch_models()
+    say("batch vs single and oracle, prec", prec)
+    b, out, _ = run_batch(models, prec, STEPS)
+    iters = [[out[n][i]["iters"] for n in range(STEPS)] for i in range(len(models))]
+    assert len({tuple(r) for r in iters}) > 1, "models should converge at different iterations"
+    assert any(out[-1][i]["n_yield"] > 0 for i in range(len(models)))
+    assert out[-1][3]["n_yield"] == 0            # the high-cohesion model stays elastic
+    tol = 1e-6 if prec == FP64 else 1e-4
+    for i, m in enumerate(models):
+        g, sg = run_single(m, prec, STEPS)
+        view = b.model(i)
+        for n in range(STEPS):
+            sb = out[n][i]
+            assert sb["status"] == 0, (i, n, sb)
+            assert sb["iters"] == sg[n]["iters"] and sb["iters_fp32"] == sg[n]["iters_fp32"], (i, n)
+            assert sb["n_yield"] == sg[n]["n_yield"], (i, n)
+        for k in IT2 + accum_names(m):
+            a, r = view.get(k), g.get(k)
+            assert np.array_equal(a, r), (i, k, float(np.abs(a - r).max()))
+        g.close()
+        o = Oracle(m)
+        so, hist = [], []
+        for _ in range(STEPS):
+            o.record_history()
+            so.append(o.load_step())
+            hist.append(o.history() / so[-1]["ref"])
+        for n in range(STEPS):
+            assert so[n]["status"] == 0
+            if prec == FP64:
+                assert iters_agree(out[n][i]["iters"], so[n]["iters"], hist[n], m), (i, n, out[n][i]["iters"],
+                                                                                      so[n]["iters"])
+                assert out[n][i]["n_yield"] == so[n]["n_yield"], (i, n)
+            assert out[n][i]["sxx_centre"] == pytest.approx(so[n]["sxx_centre"], rel=tol)
+        compare(m, view.fields(IT2), o.fields(IT2), IT2, tol, f"model {i}")
+        compare_accumulators(m, view.fields(accum_names(m)), o.fields(accum_names(m)), tol, f"model {i}")
+        o.close()
+    b.close()
+
+
+def test_batch_tuned_shapes_give_identical_results():
+    models = batch_models()
+    b0, out0, shapes0 = run_batch(models, FP32, 3)
+    b1, out1, shapes1 = run_batch(models, FP32, 3, tune=True)
+    say("tuned tile shapes", shapes1)
+    allowed = {(64, 8), (64, 4), (32, 8), (128, 4), (64, 16), (32, 16)}
+    assert set(shapes0) == {(64, 8)} and set(shapes1) <= allowed
+    for i in range(len(models)):
+        # equal sizes share a shape
+        for j in range(len(models)):
+            if (models[i].nx, models[i].ny) == (models[j].nx, models[j].ny):
+                assert shapes1[i] == shapes1[j]
+        for n in range(3):
+            assert out0[n][i]["iters"] == out1[n][i]["iters"]
+        for k in IT2:
+            assert np.array_equal(b0.model(i).get(k), b1.model(i).get(k)), (i, k)
+    b0.close()
+    b1.close()
+
+
+def test_batch_failure_is_isolated():
+    """A model that cannot converge within its iteration cap is rolled back;
+    the other models advance exactly as they would alone."""
+    models = batch_models()[:3]
+    models[1] = models[1].with_(max_iter=20)
+    from paper_2305_01701_amd.ep import EP_ENOTCONV
+    b = make_batch(models, FP64)
+    sts = [b.load_step() for _ in range(4)]
+    assert any(s[1]["status"] == EP_ENOTCONV for s in sts)
+    # model 1 rolled back at every failed step: its velocities are the start values
+    g1 = solver(models[1])
+    for n in range(4):
+        g1.load_step()
+    for k in IT2:
+        assert np.array_equal(b.model(1).get(k), g1.get(k)), k
+    for i in (0, 2):
+        g, _ = run_single(models[i], FP64, 4)
+        for k in IT2:
+            assert np.array_equal(b.model(i).get(k), g.get(k)), (i, k)
+        g.close()
+    g1.close()
+    b.close()
