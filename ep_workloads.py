@@ -45,6 +45,7 @@ class Model:
     re: float = 0.0              # 0 -> 3 sqrt(10) pi / 2
     r: float = 0.5               # Ktilde / Gtilde
     cfl: float = 0.0             # 0 -> 0.9 / sqrt(ndim)
+    freeze_iter: int = 0         # 0: off; else freeze the plastic multiplier after this many iterations
     # weak inclusion in cohesion
     c0: float = 1.75e-3
     incl_radius: float = 0.1
@@ -99,7 +100,7 @@ def c1_small_2d() -> Model:
 def c2_2d(seed: int = 0, visc: float = math.inf) -> Model:
     rng = np.random.Generator(np.random.PCG64(seed))
     off = rng.uniform(-0.1, 0.1, size=2)
-    return Model(ndim=2, nx=1023, ny=1023, tol=1e-6, steps=50, visc=visc,
+    return Model(ndim=2, nx=1023, ny=1023, tol=1e-6, steps=50, visc=visc, freeze_iter=16 * 1023,
                  incl_centre=(float(off[0]), float(off[1]), 0.0),
                  name=f"2d-1023x1023-seed{seed}" + ("-vp" if math.isfinite(visc) else "-ep"))
 
@@ -126,7 +127,7 @@ def c4_batch(seed: int = 0, n_models: int = 256,
         lo, hi = -0.5 + rad + 0.05, 0.5 - rad - 0.05
         cx, cy = (float(v) for v in rng.uniform(lo, hi, size=2))
         out.append(Model(ndim=2, nx=n, ny=n, phi_deg=phi, c0=c0, incl_radius=rad,
-                         incl_centre=(cx, cy, 0.0), dt=1e-4, tol=1e-6, steps=20,
+                         incl_centre=(cx, cy, 0.0), dt=1e-4, tol=1e-6, steps=20, freeze_iter=16 * n,
                          name=f"batch{b}-{n}"))
     return out
 

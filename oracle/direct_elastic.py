@@ -60,12 +60,17 @@ def _mask(shape, walls):
     return sp.diags(keep.ravel().astype(np.float64))
 
 
-def solve(m, old: dict, cohesion=None) -> dict:
+def solve(m, old: dict, cohesion=None, lam=None) -> dict:
     """Solve one elastic increment.
 
     m: ep_workloads.Model (visc must be inf); old: dict with p_old, txx_old,
     tyy_old, (tzz_old,) txy_old, (txz_old, tyz_old) as flat x-fastest arrays.
-    Returns the face velocities and the stresses of the solution."""
+    Returns the face velocities and the stresses of the solution.
+
+    lam (2D only): a fixed plastic multiplier Lambda per cell (frozen
+    plasticity).  The deviator then satisfies tau (1/(G dt) + Lambda) =
+    tau^/(G dt) + 2 (sym grad v - div v / 3 I), with Lambda at a vertex the
+    mean of its four cells -- still linear in v."""
     assert np.isinf(m.visc)
     nx, ny = m.nx, m.ny
     dx, dy = m.lx / nx, m.ly / ny
@@ -86,11 +91,18 @@ def solve(m, old: dict, cohesion=None) -> dict:
         exx = sp.hstack([Dx_vx, Z(nc, nvy)]) - div / 3.0
         eyy = sp.hstack([Z(nc, nvx), Dy_vy]) - div / 3.0
         exy = mxy @ (0.5 * sp.hstack([Gy_vx, Gx_vy]))
-        # stresses = const + L v
+        # stresses = const + L v; compliance factor c = 1 / (1/(G dt) + Lambda)
+        igd = 1.0 / (G * dt)
+        lc = np.zeros(nc) if lam is None else np.asarray(lam, dtype=np.float64)
+        L2 = lc.reshape(ny, nx)
+        lv = np.zeros((ny + 1, nx + 1))
+        lv[1:ny, 1:nx] = 0.25 * (L2[:-1, :-1] + L2[:-1, 1:] + L2[1:, :-1] + L2[1:, 1:])
+        cc = sp.diags(1.0 / (igd + lc))
+        cv = sp.diags(1.0 / (igd + lv.ravel()))
         P_L, P_0 = -K * dt * div, old["p_old"]
-        Txx_L, Txx_0 = 2 * G * dt * exx, old["txx_old"]
-        Tyy_L, Tyy_0 = 2 * G * dt * eyy, old["tyy_old"]
-        Txy_L, Txy_0 = 2 * G * dt * exy, mxy @ old["txy_old"]
+        Txx_L, Txx_0 = cc @ (2 * exx), cc @ (igd * old["txx_old"])
+        Tyy_L, Tyy_0 = cc @ (2 * eyy), cc @ (igd * old["tyy_old"])
+        Txy_L, Txy_0 = cv @ (2 * exy), cv @ (mxy @ (igd * old["txy_old"]))
         # momentum operators
         Gx_c = _op([_back_interior(nx, dx), None], sh["c"])     # cells -> x-faces
         Dy_xy = _op([None, _fwd(ny, dy)], sh["xy"])             # vertices -> x-faces
@@ -122,6 +134,7 @@ def solve(m, old: dict, cohesion=None) -> dict:
             "txy": Txy_0 + Txy_L @ v,
         }
 
+    assert lam is None, "frozen Lambda: 2D only"
     nz = m.nz
     dz = m.lz / nz
     ez = m.erate[2]

@@ -78,6 +78,10 @@ struct orc_state {
     double vmax;
     long long n_yield;
     double *hist; int hist_cap, hist_len;
+    /* frozen plasticity: 0 off; 1 the next sweep stores its centre Lambda;
+     * 2 sweeps use the stored Lambda instead of the return mapping */
+    int freeze;
+    double *lamf;
 };
 
 /* ---------------------------------------------------------------- sizes */
@@ -188,6 +192,7 @@ orc_state* orc_create(const orc_params* prm, const double* cohesion)
     s->coh = zalloc(nc); s->dv = zalloc(nc);
     s->exx = zalloc(nc); s->eyy = zalloc(nc); s->ezz = zalloc(nc); s->eps_p = zalloc(nc);
     s->lam = zalloc(nc); s->tII = zalloc(nc); s->yld = zalloc(nc); s->lamdot = zalloc(nc);
+    s->lamf = zalloc(nc);
     s->txy = zalloc(n_xy(s)); s->txy_old = zalloc(n_xy(s)); s->txyn = zalloc(n_xy(s));
     s->Txy = zalloc(n_xy(s)); s->exy = zalloc(n_xy(s));
     s->txz = zalloc(n_xz(s)); s->txz_old = zalloc(n_xz(s)); s->txzn = zalloc(n_xz(s));
@@ -226,7 +231,7 @@ void orc_free(orc_state* s)
         &s->vx, &s->vy, &s->vz, &s->vxn, &s->vyn, &s->vzn, &s->vx0, &s->vy0, &s->vz0,
         &s->ux, &s->uy, &s->uz, &s->p, &s->txx, &s->tyy, &s->tzz,
         &s->p_old, &s->txx_old, &s->tyy_old, &s->tzz_old, &s->pn, &s->txxn, &s->tyyn, &s->tzzn,
-        &s->coh, &s->dv, &s->exx, &s->eyy, &s->ezz, &s->eps_p, &s->lam, &s->tII, &s->yld, &s->lamdot,
+        &s->coh, &s->dv, &s->exx, &s->eyy, &s->ezz, &s->eps_p, &s->lam, &s->tII, &s->yld, &s->lamdot, &s->lamf,
         &s->txy, &s->txy_old, &s->txyn, &s->Txy, &s->exy,
         &s->txz, &s->txz_old, &s->txzn, &s->Txz, &s->exz,
         &s->tyz, &s->tyz_old, &s->tyzn, &s->Tyz, &s->eyz,
@@ -269,6 +274,7 @@ static double* field_ptr(const orc_state* s, int f, long* n)
     case ORC_LAMBDA: *n = n_cells(s); return s->lamdot;
     case ORC_TAU_II: *n = n_cells(s); return s->tII;
     case ORC_YIELD: *n = n_cells(s); return s->yld;
+    case ORC_LAMBDA_FROZEN: *n = n_cells(s); return s->lamf;
     default: *n = -1; return NULL;
     }
 }
@@ -373,11 +379,13 @@ static double sweep2d(orc_state* s, int mode)
             double J2 = 0.5 * (Txx * Txx + Tyy * Tyy) + Tb * Tb;
             double tret, Y, ld;
             double lam = centre_lambda(J2, D, s->pn[c], s->coh[c], A, B, &tret, &Y, &ld);
-            s->lam[c] = lam;
             s->lamdot[c] = ld;
             s->tII[c] = tret;
             s->yld[c] = Y;
             if (lam > 0.0) ny_count++;
+            if (mode == 0 && s->freeze == 1) s->lamf[c] = lam;
+            if (mode == 0 && s->freeze == 2) lam = s->lamf[c];
+            s->lam[c] = lam;
             s->txxn[c] = Txx / (D + lam);
             s->tyyn[c] = Tyy / (D + lam);
             dpm = fmax(dpm, fabs(s->pn[c] - s->p[c]));
@@ -518,11 +526,13 @@ static double sweep3d(orc_state* s, int mode)
                           + Txyb * Txyb + Txzb * Txzb + Tyzb * Tyzb;
                 double tret, Y, ld;
                 double lam = centre_lambda(J2, D, s->pn[c], s->coh[c], A, B, &tret, &Y, &ld);
-                s->lam[c] = lam;
                 s->lamdot[c] = ld;
                 s->tII[c] = tret;
                 s->yld[c] = Y;
                 if (lam > 0.0) ny_count++;
+                if (mode == 0 && s->freeze == 1) s->lamf[c] = lam;
+                if (mode == 0 && s->freeze == 2) lam = s->lamf[c];
+                s->lam[c] = lam;
                 s->txxn[c] = Txx / (D + lam);
                 s->tyyn[c] = Tyy / (D + lam);
                 s->tzzn[c] = Tzz / (D + lam);
@@ -798,14 +808,24 @@ int orc_load_step(orc_state* s, orc_stats* st)
     int status = -4;
     double res = NAN;
     int it;
+    s->freeze = 0;
     for (it = 1; it <= s->prm.max_iter; ++it) {
         res = orc_sweep(s, 0);
+        if (s->freeze == 1) s->freeze = 2;   /* that sweep stored its Lambda */
         if (it % nchk == 0) {
             if (s->hist && s->hist_len < s->hist_cap) s->hist[s->hist_len++] = res;
             if (!(res == res) || isinf(res) || res > 1e8 * st->ref) { status = -5; break; }
             if (res <= s->prm.tol * st->ref) { status = 0; break; }
+            /* frozen plasticity: an increment still iterating after
+             * freeze_iter iterations continues with the plastic multiplier
+             * of the next sweep held fixed (a linear problem) */
+            if (s->prm.freeze_iter > 0 && s->freeze == 0 && it >= s->prm.freeze_iter) {
+                s->freeze = 1;
+                st->frozen_at = it;
+            }
         }
     }
+    s->freeze = 0;
     st->iters = it > s->prm.max_iter ? s->prm.max_iter : it;
     st->resid = res;
     st->eps_rel = s->vmax > 0 ? s->dtrho * res / s->vmax : 0.0;

@@ -32,6 +32,8 @@ typedef struct orc_params {
     int    max_iter;         /* pseudo-time iteration cap per increment */
     int    n_check;          /* check the residual every n_check iterations */
     double re, r, cfl;       /* PT numerical Reynolds number, Ktilde/Gtilde, Courant number */
+    int    freeze_iter;      /* 0: off; else freeze Lambda at the first check at or after
+                                this iteration that has not converged */
 } orc_params;
 
 typedef struct orc_stats {
@@ -46,6 +48,7 @@ typedef struct orc_stats {
     double sxx_right;        /* ... over the last column */
     long long n_yield;       /* cells on the yield surface in a PT evaluation of the accepted state */
     double max_violation;    /* max over cells of tauII(stored stresses) - max(0, A p + B c) */
+    int    frozen_at;        /* iteration whose check froze Lambda (0: not frozen) */
 } orc_stats;
 
 enum {
@@ -55,6 +58,7 @@ enum {
     ORC_UX, ORC_UY, ORC_UZ,
     ORC_EXX, ORC_EYY, ORC_EZZ, ORC_EXY, ORC_EXZ, ORC_EYZ,
     ORC_EPS_P, ORC_COHESION, ORC_LAMBDA, ORC_TAU_II, ORC_YIELD,
+    ORC_LAMBDA_FROZEN,       /* centre Lambda held fixed by the last frozen increment */
     ORC_NFIELDS
 };
 

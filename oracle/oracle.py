@@ -20,7 +20,7 @@ FIELDS = [
     "vx", "vy", "vz", "p", "txx", "tyy", "tzz", "txy", "txz", "tyz",
     "p_old", "txx_old", "tyy_old", "tzz_old", "txy_old", "txz_old", "tyz_old",
     "ux", "uy", "uz", "exx", "eyy", "ezz", "exy", "exz", "eyz",
-    "eps_p", "cohesion", "lambda_dot", "tau_ii", "yield",
+    "eps_p", "cohesion", "lambda_dot", "tau_ii", "yield", "lambda_frozen",
 ]
 FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
 
@@ -34,6 +34,7 @@ class OrcParams(C.Structure):
         ("erate", C.c_double * 3), ("tol", C.c_double),
         ("max_iter", C.c_int), ("n_check", C.c_int),
         ("re", C.c_double), ("r", C.c_double), ("cfl", C.c_double),
+        ("freeze_iter", C.c_int),
     ]
 
 
@@ -43,6 +44,7 @@ class OrcStats(C.Structure):
         ("r_ref", C.c_double), ("ref", C.c_double), ("resid", C.c_double),
         ("eps_rel", C.c_double), ("sxx_centre", C.c_double), ("sxx_left", C.c_double),
         ("sxx_right", C.c_double), ("n_yield", C.c_longlong), ("max_violation", C.c_double),
+        ("frozen_at", C.c_int),
     ]
 
     def as_dict(self) -> dict:
@@ -88,6 +90,7 @@ def params_from_model(m) -> OrcParams:
         p.erate[q] = m.erate[q]
     p.tol, p.max_iter, p.n_check = m.tol, m.max_iter, m.n_check
     p.re, p.r, p.cfl = m.re, m.r, m.cfl
+    p.freeze_iter = m.freeze_iter
     return p
 
 

@@ -211,6 +211,36 @@ def test_elastic_increment_matches_direct_solve(ndim, n):
         assert err < 1e-9, (k, err)
 
 
+def test_frozen_increment_matches_direct_solve_with_fixed_lambda():
+    """Frozen plasticity (accelerated PT section): an increment frozen before
+    it converged ends at the fixed point of the linear problem with the
+    stored per-cell Lambda; the direct sparse solve of that linear problem
+    (different code: assembled operators, LU) must give the same fields."""
+    m = c1_small_2d().with_(n_check=10, dt=2e-4, tol=1e-12, freeze_iter=300,
+                            incl_centre=(0.05, 0.03, 0.0))
+    o = Oracle(m)
+    frozen = None
+    for _ in range(8):
+        st = o.load_step()
+        assert st["status"] == 0
+        if st["frozen_at"] > 0:
+            frozen = st
+            break
+    assert frozen is not None and frozen["frozen_at"] >= 300 and frozen["frozen_at"] % 10 == 0
+    lam = o.get("lambda_frozen")
+    assert lam.max() > 0
+    old = {k: o.get(k) for k in ("p_old", "txx_old", "tyy_old", "txy_old")}
+    ref = direct_elastic.solve(m, old, lam=lam)
+    f = o.fields()
+    for k in ("vx", "vy", "p", "txx", "tyy", "txy"):
+        scale = max(np.abs(ref[k]).max(), 1e-30)
+        err = np.abs(f[k] - ref[k]).max() / scale
+        assert err < 1e-8, (k, err)
+    # the frozen state is an approximation: Lambda came from a sweep before
+    # convergence, so the yield condition holds only approximately
+    assert 0 < frozen["max_violation"] < 0.5 * m.c0
+
+
 # ------------------------------------------------------------ invariants
 @pytest.fixture(scope="module")
 def c1_run():
