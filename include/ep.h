@@ -83,6 +83,11 @@ typedef struct ep_params {
                                 rounding floor 8 u32 max|sigma| / h, ... */
     int    fp32_stall;       /* ... or, within 20x of that floor, has not halved for
                                 this many checks (0: 16 max(nx,ny,nz) / n_check; < 0: never) */
+    int    freeze_iter;      /* frozen plasticity (accelerated PT section): 0 off; else an
+                                increment not converged at the first check at or after this
+                                iteration continues with the plastic multiplier Lambda of
+                                the next sweep held fixed at every cell (a linear problem).
+                                2D with the fused sweep only (EP_EINVAL otherwise) */
 } ep_params;
 
 typedef struct ep_step_stats {
@@ -100,6 +105,7 @@ typedef struct ep_step_stats {
     double max_violation;    /* max over cells of tauII(stored stresses) - (A p + B c) */
     double seconds;          /* wall time of the call */
     double fp32_exit;        /* normalised residual when FP32 handed over (0 in FP64 mode) */
+    int    frozen_at;        /* iteration whose check froze Lambda (0: not frozen) */
 } ep_step_stats;
 
 typedef struct ep_residual_info {
@@ -117,6 +123,7 @@ enum {
     EP_F_UX, EP_F_UY, EP_F_UZ,
     EP_F_EXX, EP_F_EYY, EP_F_EZZ, EP_F_EXY, EP_F_EXZ, EP_F_EYZ,
     EP_F_EPS_P, EP_F_COHESION, EP_F_LAMBDA_DOT, EP_F_TAU_II, EP_F_YIELD,
+    EP_F_LAMBDA_FROZEN,      /* 2D: centre Lambda held fixed by the last frozen increment */
     EP_F_COUNT
 };
 #define EP_GET 0
@@ -174,7 +181,8 @@ int ep_residual(ep_handle* h, ep_residual_info* r);
  * rejected in 3D (the deviator is stored trace-free: tzz = -(txx + tyy));
  * accumulators, cohesion and the old stresses may be set (checkpoint
  * restore).  LAMBDA_DOT, TAU_II and YIELD describe the last accepted
- * increment and are read-only.  EP_EINVAL on a bad id or count. */
+ * increment and are read-only, as is LAMBDA_FROZEN (meaningful after an
+ * increment whose stats report frozen_at > 0).  EP_EINVAL on a bad id or count. */
 int ep_fields(ep_handle* h, int field, int dir, double* host, size_t count);
 
 /* Shape (x, y, z extents; z = 1 in 2D) of a field; 0 extents if the field

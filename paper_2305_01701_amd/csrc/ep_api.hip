@@ -59,6 +59,8 @@ int validate(const ep_params* p)
     if (p->cfl > 0 && p->cfl >= 1.0 / std::sqrt((double)p->ndim)) return EP_EINVAL;
     if (p->precision != EP_FP64 && p->precision != EP_FP32_FIELDS) return EP_EINVAL;
     if (p->sweep < EP_SWEEP_AUTO || p->sweep > EP_SWEEP_UNFUSED) return EP_EINVAL;
+    if (p->freeze_iter < 0) return EP_EINVAL;
+    if (p->freeze_iter > 0 && (p->ndim != 2 || p->sweep == EP_SWEEP_UNFUSED)) return EP_EINVAL;
     return EP_OK;
 }
 
@@ -119,8 +121,8 @@ size_t carve(const ep_params* p, ep_handle* h, char* base)
     if (p->ndim == 2) {
         const long nt = (long)((nx + kBatchTiles[0][0] - 1) / kBatchTiles[0][0]) *
                         ((ny + kBatchTiles[0][1] - 1) / kBatchTiles[0][1]);
-        q = take(4 * sizeof(SweepArgs<double>)); if (h) h->tab64 = (SweepArgs<double>*)q;
-        q = take(2 * sizeof(SweepArgs<float>)); if (h) h->tab32 = (SweepArgs<float>*)q;
+        q = take(8 * sizeof(SweepArgs<double>)); if (h) h->tab64 = (SweepArgs<double>*)q;
+        q = take(6 * sizeof(SweepArgs<float>)); if (h) h->tab32 = (SweepArgs<float>*)q;
         q = take(nt * sizeof(TileRef)); if (h) h->tiles = (TileRef*)q;
         q = take(sizeof(int)); if (h) h->tcount = (int*)q;
         if (h) h->ntiles = nt;
@@ -219,6 +221,7 @@ SweepArgs<R> make_args(const ep_handle* h, R* const* from, R* const* to, R* cons
     a.ebx = (R)(bg ? h->prm.erate[0] : 0.0);
     a.eby = (R)(bg ? h->prm.erate[1] : 0.0);
     a.ebz = (R)(bg && h->ndim == 3 ? h->prm.erate[2] : 0.0);
+    a.lam_mode = LAM_COMPUTE;
     return a;
 }
 
@@ -234,21 +237,21 @@ SweepArgs<float> args32(const ep_handle* h, int from)
     return make_args<float>(h, h->it32[from], h->it32[1 - from], h->old32, h->coh32, h->lam32, false);
 }
 
-// One PT sweep reading buffer `from` (physical: pseudo-time terms removed).
-// 2D fused sweeps run the batched tile kernel on this model's own one-entry
-// table and tile list, so that a model gives bitwise the same iterates alone
-// and inside a batch.
+// One PT sweep reading buffer `from` (physical: pseudo-time terms removed;
+// lam_mode: LAM_*, 2D tile sweeps only).  2D fused sweeps run the batched
+// tile kernel on this model's own one-entry table and tile list, so that a
+// model gives bitwise the same iterates alone and inside a batch.
 template <typename R>
-void launch_sweep(const ep_handle* h, bool physical, int from, int mode)
+void launch_sweep(const ep_handle* h, bool physical, int from, int mode, int lam_mode = LAM_COMPUTE)
 {
     const bool fused = sizeof(R) == 4 ? h->fused32 : h->fused64;
     if (h->ndim == 2 && fused) {
-        const int q = sizeof(R) == 4 ? 1 : 0;
-        if (q == 1)
-            launch_sweep_batch_2d<float>(0, h->tab32 + from, h->tiles, h->tcount, mode, h->grid2[1], h->st);
+        if (sizeof(R) == 4)
+            launch_sweep_batch_2d<float>(0, h->tab32 + 2 * lam_mode + from, h->tiles, h->tcount, mode, h->grid2[1],
+                                         h->st);
         else
-            launch_sweep_batch_2d<double>(0, h->tab64 + (physical ? 2 : 0) + from, h->tiles, h->tcount, mode,
-                                          h->grid2[0], h->st);
+            launch_sweep_batch_2d<double>(0, h->tab64 + (physical ? 6 : 2 * lam_mode) + from, h->tiles, h->tcount,
+                                          mode, h->grid2[0], h->st);
         return;
     }
     SweepArgs<R> a;
@@ -262,17 +265,26 @@ void launch_sweep(const ep_handle* h, bool physical, int from, int mode)
     }
 }
 
-// Device tables of the 2D tile kernel: FP64 [from 0, from 1, physical 0,
-// physical 1], FP32 [from 0, from 1], and the tile list (shape 0).
+// Device tables of the 2D tile kernel: FP64 [lam mode][from] then physical
+// [from]; FP32 [lam mode][from].  The tile list (shape 0) is written once.
 int upload_tables(ep_handle* h)
 {
     if (h->ndim != 2) return EP_OK;
-    SweepArgs<double> t64[4] = {args64(h, false, 0), args64(h, false, 1), args64(h, true, 0), args64(h, true, 1)};
+    SweepArgs<double> t64[8];
+    SweepArgs<float> t32[6];
+    for (int lm = 0; lm < 3; ++lm)
+        for (int from = 0; from < 2; ++from) {
+            t64[2 * lm + from] = args64(h, false, from);
+            t64[2 * lm + from].lam_mode = lm;
+            if (h->fp32) {
+                t32[2 * lm + from] = args32(h, from);
+                t32[2 * lm + from].lam_mode = lm;
+            }
+        }
+    t64[6] = args64(h, true, 0);
+    t64[7] = args64(h, true, 1);
     HIPCHK(h, hipMemcpyAsync(h->tab64, t64, sizeof(t64), hipMemcpyHostToDevice, h->st));
-    if (h->fp32) {
-        SweepArgs<float> t32[2] = {args32(h, 0), args32(h, 1)};
-        HIPCHK(h, hipMemcpyAsync(h->tab32, t32, sizeof(t32), hipMemcpyHostToDevice, h->st));
-    }
+    if (h->fp32) HIPCHK(h, hipMemcpyAsync(h->tab32, t32, sizeof(t32), hipMemcpyHostToDevice, h->st));
     HIPCHK(h, hipStreamSynchronize(h->st));
     return EP_OK;
 }
@@ -307,6 +319,10 @@ void copy_it64(ep_handle* h, double* const* dst, double* const* src)
 void ensure_it64(ep_handle* h)
 {
     if (h->it64_valid) return;
+    if (h->freeze == 2 && h->lam_in32) {     // Lambda frozen by an FP32 sweep
+        launch_to_f64(h->lam64, h->lam32, h->nelem, h->st);
+        h->lam_in32 = false;
+    }
     for (int f = 0; f < F_NIT; ++f) {
         if (!h->it64[h->cur64][f]) continue;
         int o = f == F_P ? O_P : f == F_TXX ? O_TXX : f == F_TYY ? O_TYY : f == F_TXY ? O_TXY
@@ -342,6 +358,14 @@ void ensure_it32(ep_handle* h)
     }
 }
 
+// Lambda mode of sweep b of a batch: the first sweep after a freeze decision
+// stores Lambda, every later sweep reads it.
+int sweep_lam_mode(const ep_handle* h, int b)
+{
+    if (h->freeze == 0) return LAM_COMPUTE;
+    return (h->freeze == 1 && b == 0) ? LAM_STORE : LAM_FROZEN;
+}
+
 // Run nb sweeps in one precision; the last one reduces the residual.
 int run_batch(ep_handle* h, bool use32, int nb, bool check_last)
 {
@@ -349,13 +373,18 @@ int run_batch(ep_handle* h, bool use32, int nb, bool check_last)
     launch_reset_red(h->red, h->st);
     for (int b = 0; b < nb; ++b) {
         int mode = (check_last && b == nb - 1) ? MODE_CHECK : MODE_UPDATE;
+        const int lm = sweep_lam_mode(h, b);
         if (use32) {
-            launch_sweep<float>(h, false, h->cur32, mode);
+            launch_sweep<float>(h, false, h->cur32, mode, lm);
             h->cur32 = 1 - h->cur32;
         } else {
-            launch_sweep<double>(h, false, h->cur64, mode);
+            launch_sweep<double>(h, false, h->cur64, mode, lm);
             h->cur64 = 1 - h->cur64;
         }
+    }
+    if (h->freeze == 1 && nb > 0) {
+        h->freeze = 2;
+        h->lam_in32 = use32;
     }
     if (use32) h->it64_valid = false;
     else h->it32_valid = false;
@@ -401,6 +430,8 @@ void step_begin(ep_handle* h, ep_step_stats* st)
     c.resid = NAN;
     c.vmax = 0;
     std::memset(st, 0, sizeof(*st));
+    h->freeze = 0;
+    h->lam_in32 = false;
 
     // increment start state and wall velocities
     ensure_it64(h);
@@ -487,6 +518,12 @@ bool step_check(ep_handle* h, const double red[RED_N], int nb)
         c.status = EP_OK;
         c.running = false;
     }
+    // frozen plasticity: still iterating at freeze_iter -> the next sweep
+    // stores its centre Lambda and later sweeps hold it fixed
+    if (c.running && h->prm.freeze_iter > 0 && h->freeze == 0 && st->iters >= h->prm.freeze_iter) {
+        h->freeze = 1;
+        st->frozen_at = st->iters;
+    }
     if (c.running && st->iters >= h->prm.max_iter) {
         c.status = EP_ENOTCONV;
         c.running = false;
@@ -496,6 +533,7 @@ bool step_check(ep_handle* h, const double red[RED_N], int nb)
 
 int step_finish(ep_handle* h)
 {
+    h->freeze = 0;                  // sweeps outside an increment compute Lambda
     StepCtl& c = h->ctl;
     ep_step_stats* st = c.st;
     st->resid = c.resid;
@@ -574,6 +612,7 @@ FieldRef field_ref(ep_handle* h, int f)
     case EP_F_LAMBDA_DOT: set(h->lamdot64, nx, ny, nz, false); break;
     case EP_F_TAU_II: set(h->tii64, nx, ny, nz, false); break;
     case EP_F_YIELD: set(h->yld64, nx, ny, nz, false); break;
+    case EP_F_LAMBDA_FROZEN: if (!d3) set(h->lam64, nx, ny, nz, false); break;
     default: break;
     }
     return r;

@@ -123,8 +123,8 @@ BatchLayout layout(int n, const ep_params* p)
     auto take = [&](size_t bytes) { size_t r = off; off = align256(off + bytes); return r; };
     L.red = take((size_t)n * RED_N * sizeof(unsigned long long));
     L.cols = take((size_t)n * 4 * sizeof(double));
-    L.tab64 = take((size_t)2 * n * sizeof(SweepArgs<double>));
-    L.tab32 = take((size_t)2 * n * sizeof(SweepArgs<float>));
+    L.tab64 = take((size_t)3 * n * sizeof(SweepArgs<double>));
+    L.tab32 = take((size_t)3 * n * sizeof(SweepArgs<float>));
     const bool fp32 = p[0].precision == EP_FP32_FIELDS;
     for (int q = 0; q < 2; ++q)
         for (int s = 0; s < BATCH_SHAPES; ++s) {
@@ -138,13 +138,24 @@ BatchLayout layout(int n, const ep_params* p)
     return L;
 }
 
+// Model tables, 3 x n entries: [0] the first sweep of a replay (reads the
+// current buffers; stores Lambda when a freeze was just decided), [1] and [2]
+// the later sweeps reading the current / the other buffers.
 void fill_tables(ep_batch* b)
 {
-    for (int i = 0; i < b->n; ++i) {
+    const int n = b->n;
+    for (int i = 0; i < n; ++i) {
         ep_handle* h = b->m[i];
-        for (int par = 0; par < 2; ++par) {
-            b->h_tab64[par * b->n + i] = args64(h, false, h->cur64 ^ par);
-            if (b->fp32) b->h_tab32[par * b->n + i] = args32(h, h->cur32 ^ par);
+        const int lm_first = sweep_lam_mode(h, 0), lm_rest = sweep_lam_mode(h, 1);
+        for (int slot = 0; slot < 3; ++slot) {
+            const int par = slot == 2 ? 1 : 0;
+            const int lm = slot == 0 ? lm_first : lm_rest;
+            b->h_tab64[slot * n + i] = args64(h, false, h->cur64 ^ par);
+            b->h_tab64[slot * n + i].lam_mode = lm;
+            if (b->fp32) {
+                b->h_tab32[slot * n + i] = args32(h, h->cur32 ^ par);
+                b->h_tab32[slot * n + i].lam_mode = lm;
+            }
         }
     }
 }
@@ -179,7 +190,7 @@ void fill_lists(ep_batch* b, bool all_models)
 
 int upload(ep_batch* b)
 {
-    const size_t n2 = 2 * (size_t)b->n;
+    const size_t n2 = 3 * (size_t)b->n;
     BCHK(b, hipMemcpyAsync(b->tab64, b->h_tab64.data(), n2 * sizeof(SweepArgs<double>), hipMemcpyHostToDevice, b->st));
     if (b->fp32)
         BCHK(b, hipMemcpyAsync(b->tab32, b->h_tab32.data(), n2 * sizeof(SweepArgs<float>), hipMemcpyHostToDevice,
@@ -211,13 +222,13 @@ void enqueue_sweeps(ep_batch* b, int nsw, bool check, bool reset, bool alternate
     if (reset) launch_reset_red_n(b->red, b->n, s);
     for (int k = 0; k < nsw; ++k) {
         const int mode = (check && k == nsw - 1) ? MODE_CHECK : MODE_UPDATE;
-        const int par = alternate ? (k & 1) : 0;
+        const int slot = !alternate ? 1 : k == 0 ? 0 : (k & 1) ? 2 : 1;
         for (int sh = 0; sh < BATCH_SHAPES; ++sh) {
             if (!shape_used(b, sh)) continue;
             if (b->fp32)
-                launch_sweep_batch_2d<float>(sh, b->tab32 + par * b->n, b->list[1][sh], b->cnt + BATCH_SHAPES + sh,
+                launch_sweep_batch_2d<float>(sh, b->tab32 + slot * b->n, b->list[1][sh], b->cnt + BATCH_SHAPES + sh,
                                              mode, b->grid[1][sh], s);
-            launch_sweep_batch_2d<double>(sh, b->tab64 + par * b->n, b->list[0][sh], b->cnt + sh, mode,
+            launch_sweep_batch_2d<double>(sh, b->tab64 + slot * b->n, b->list[0][sh], b->cnt + sh, mode,
                                           b->grid[0][sh], s);
         }
     }
@@ -328,8 +339,8 @@ int ep_batch_init(int n, const ep_params* p, const double* const* cohesion, void
         b->grid[0][s] = ncu * std::min(8, batch_blocks_per_cu<double>(s));
         b->grid[1][s] = ncu * std::min(8, batch_blocks_per_cu<float>(s));
     }
-    b->h_tab64.resize(2 * (size_t)n);
-    b->h_tab32.resize(2 * (size_t)n);
+    b->h_tab64.resize(3 * (size_t)n);
+    b->h_tab32.resize(3 * (size_t)n);
     b->h_red.assign((size_t)n * RED_N, 0ull);
     b->h_cols.assign((size_t)n * 4, 0.0);
     if (hipGetLastError() != hipSuccess) return fail(EP_EDEVICE);
@@ -479,10 +490,16 @@ int ep_batch_load_step(ep_batch* b, ep_step_stats* st)
             const bool was32 = h->ctl.use32;
             if (was32) h->it64_valid = false;
             else h->it32_valid = false;
+            if (h->freeze == 1) {           // the replay's first sweep stored Lambda
+                h->freeze = 2;
+                h->lam_in32 = was32;
+                dirty = true;
+            }
             double red[RED_N];
             model_red(b, i, red);
+            const int freeze_before = h->freeze;
             const bool cont = step_check(h, red, b->n_check);
-            if (!cont || h->ctl.use32 != was32) dirty = true;
+            if (!cont || h->ctl.use32 != was32 || h->freeze != freeze_before) dirty = true;
         }
     }
     int worst = EP_OK;

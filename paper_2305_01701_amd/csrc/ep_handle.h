@@ -65,6 +65,8 @@ struct ep_handle {
     long ntiles;
     int grid2[2];
     ep::StepCtl ctl;
+    int freeze;            // 0 off, 1 the next sweep stores Lambda, 2 Lambda frozen
+    bool lam_in32;         // the frozen Lambda is in lam32 (else lam64)
     bool in_batch;         // owned by an ep_batch (ep_destroy ignores it)
     char err[512];
 };
@@ -84,6 +86,8 @@ size_t carve(const ep_params* p, ep_handle* h, char* base);
 void handle_free(ep_handle* h);
 // (Re-)write the device tables of the 2D tile kernel (after h->red moved).
 int upload_tables(ep_handle* h);
+// LAM_* mode of sweep b of the next batch of sweeps.
+int sweep_lam_mode(const ep_handle* h, int b);
 int handle_create(const ep_params* p, const double* cohesion, char* d_workspace, hipStream_t stream,
                   ep_handle** out);
 

@@ -44,7 +44,12 @@ struct SweepArgs {
     R rK, rG;              // pseudo-rate -> residual factors: K dt/(K~dtau L), eta/(G~dtau L)
     R ebx, eby, ebz;       // background strain rate subtracted from the stored velocities
                            // (FP32 fields store v - erate * x; 0 when v is stored in full)
+    int lam_mode;          // 2D tile sweep: LAM_* (frozen plasticity)
 };
+
+// Centre Lambda of the 2D tile sweep: from the return mapping; from the
+// return mapping and stored to lam (the sweep that freezes it); read from lam.
+enum { LAM_COMPUTE = 0, LAM_STORE = 1, LAM_FROZEN = 2 };
 
 // Sweep modes.
 enum { MODE_UPDATE = 0,    // write iteration k+1

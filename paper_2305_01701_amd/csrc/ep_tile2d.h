@@ -115,13 +115,20 @@ __device__ __forceinline__ void sweep_tile_2d(const SweepArgs<R>& a, int bx, int
             R Tb = R(0.25) * (s_Txy[q] + s_Txy[q + 1] + s_Txy[q + W] + s_Txy[q + W + 1]);
             R J2 = R(0.5) * (Txx * Txx + Tyy * Tyy) + Tb * Tb;
             R lam;
-            const R sc_ = return_scale(J2, D, a.invD, pn, gc[u], a.A, a.B, lam);
+            R sc_ = return_scale(J2, D, a.invD, pn, gc[u], a.A, a.B, lam);
+            const bool own = la >= 2 && la < TX + 2 && lbb >= 2 && lbb < TY + 2;
+            if (a.lam_mode == LAM_FROZEN) {
+                lam = a.lam[e];
+                sc_ = R(1) / (D + lam);
+            } else if (a.lam_mode == LAM_STORE && own) {
+                a.lam[e] = lam;
+            }
             R txx = Txx * sc_, tyy = Tyy * sc_;
             s_lam[q] = lam;
             s_p[q] = pn;
             s_sxx[q] = txx;
             s_syy[q] = tyy;
-            if (la >= 2 && la < TX + 2 && lbb >= 2 && lbb < TY + 2) {
+            if (own) {
                 a.nx_[F_P][e] = pn;
                 a.nx_[F_TXX][e] = txx;
                 a.nx_[F_TYY][e] = tyy;

@@ -27,7 +27,7 @@ FIELDS = [
     "vx", "vy", "vz", "p", "txx", "tyy", "tzz", "txy", "txz", "tyz",
     "p_old", "txx_old", "tyy_old", "tzz_old", "txy_old", "txz_old", "tyz_old",
     "ux", "uy", "uz", "exx", "eyy", "ezz", "exy", "exz", "eyz",
-    "eps_p", "cohesion", "lambda_dot", "tau_ii", "yield",
+    "eps_p", "cohesion", "lambda_dot", "tau_ii", "yield", "lambda_frozen",
 ]
 FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
 
@@ -50,7 +50,7 @@ class ep_params(C.Structure):
         ("max_iter", C.c_int), ("n_check", C.c_int),
         ("re", C.c_double), ("r", C.c_double), ("cfl", C.c_double),
         ("precision", C.c_int), ("sweep", C.c_int), ("fp32_switch", C.c_double),
-        ("fp32_stall", C.c_int),
+        ("fp32_stall", C.c_int), ("freeze_iter", C.c_int),
     ]
 
 
@@ -60,7 +60,7 @@ class ep_step_stats(C.Structure):
         ("r_ref", C.c_double), ("ref", C.c_double), ("resid", C.c_double), ("eps_rel", C.c_double),
         ("sxx_centre", C.c_double), ("sxx_left", C.c_double), ("sxx_right", C.c_double),
         ("n_yield", C.c_longlong), ("max_violation", C.c_double), ("seconds", C.c_double),
-        ("fp32_exit", C.c_double),
+        ("fp32_exit", C.c_double), ("frozen_at", C.c_int),
     ]
 
     def as_dict(self) -> dict:
@@ -255,6 +255,7 @@ def params_from_model(m, precision: int = EP_FP64, sweep: int = EP_SWEEP_AUTO,
     p.tol, p.max_iter, p.n_check = m.tol, m.max_iter, m.n_check
     p.re, p.r, p.cfl = m.re, m.r, m.cfl
     p.precision, p.sweep, p.fp32_switch, p.fp32_stall = precision, sweep, fp32_switch, fp32_stall
+    p.freeze_iter = m.freeze_iter
     return p
 
 

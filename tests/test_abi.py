@@ -54,7 +54,7 @@ def test_workspace_size_scales_with_grid_and_precision(E):
 
 @pytest.mark.parametrize("change", [
     dict(psi_deg=5.0), dict(nx=2), dict(bulk=0.0), dict(shear=-1.0), dict(dt=0.0), dict(tol=0.0),
-    dict(cfl=0.75), dict(ndim=4), dict(max_iter=0), dict(visc=0.0),
+    dict(cfl=0.75), dict(ndim=4), dict(max_iter=0), dict(visc=0.0), dict(freeze_iter=-1),
 ])
 def test_invalid_parameters_rejected(E, change):
     m = c1_small_2d().with_(**change)
@@ -119,3 +119,13 @@ def test_batch_init_rejects_small_workspace(E):
     rc, b = E.ep_batch_init(ps, [None, None], 256, need - 256, 0)
     assert rc == E.EP_ENOMEM and not b.value
     assert E.lib().ep_batch_last_error(None) == b"no batch"
+
+
+@pytest.mark.parametrize("case", ["3d", "unfused"])
+def test_freeze_needs_the_2d_tile_sweep(E, case):
+    m = (c3_3d(7) if case == "3d" else c1_small_2d()).with_(freeze_iter=100)
+    p = E.params_from_model(m, sweep=E.EP_SWEEP_UNFUSED if case == "unfused" else E.EP_SWEEP_AUTO)
+    n = C.c_size_t(0)
+    assert E.lib().ep_workspace_size(C.byref(p), C.byref(n)) == E.EP_EINVAL
+    p.freeze_iter = 0
+    assert E.lib().ep_workspace_size(C.byref(p), C.byref(n)) == E.EP_OK
