@@ -106,6 +106,8 @@ typedef struct ep_step_stats {
     double seconds;          /* wall time of the call */
     double fp32_exit;        /* normalised residual when FP32 handed over (0 in FP64 mode) */
     int    frozen_at;        /* iteration whose check froze Lambda (0: not frozen) */
+    int    guess_used;       /* 1: the increment started from a supplied guess (ep_net_predict) */
+    double r_guess;          /* momentum residual of the physical stresses of that guess (0: none) */
 } ep_step_stats;
 
 typedef struct ep_residual_info {

@@ -118,6 +118,10 @@ size_t carve(const ep_params* p, ep_handle* h, char* base)
     }
     q = fp32 ? take(b32) : nullptr; if (h) h->coh32 = (float*)q;
     q = fp32 ? take(b32) : nullptr; if (h) h->lam32 = (float*)q;
+    for (int d = 0; d < 3; ++d) {
+        q = p->ndim == 3 ? take(b64) : nullptr;
+        if (h) h->vguess64[d] = (double*)q;
+    }
     if (p->ndim == 2) {
         const long nt = (long)((nx + kBatchTiles[0][0] - 1) / kBatchTiles[0][0]) *
                         ((ny + kBatchTiles[0][1] - 1) / kBatchTiles[0][1]);
@@ -460,6 +464,26 @@ int step_start(ep_handle* h, const double red[RED_N])
         roll_back(h);
         st->seconds = seconds_since(c);
         return EP_EDIVERGED;
+    }
+    if (h->guess_ready) {
+        // a supplied guess replaces the plain one when its physical stresses
+        // balance better; the normaliser stays that of the plain guess
+        h->guess_ready = false;
+        for (int d = 0; d < h->ndim; ++d) launch_copy(h->it64[h->cur64][F_VX + d], h->vguess64[d], h->nelem, h->st);
+        launch_reset_red(h->red, h->st);
+        launch_sweep<double>(h, true, h->cur64, MODE_PHYS);
+        double rg[RED_N];
+        int rc = read_red(h, rg);
+        if (rc) return rc;
+        st->r_guess = rg[RED_MOM];
+        if (rg[RED_MOM] < st->r_ref) {
+            st->guess_used = 1;
+        } else {
+            for (int d = 0; d < h->ndim; ++d)
+                launch_copy(h->it64[h->cur64][F_VX + d], h->vstart64[d], h->nelem, h->st);
+            launch_reset_red(h->red, h->st);
+            launch_sweep<double>(h, true, h->cur64, MODE_PHYS);
+        }
     }
     // the physical stresses just written to the other buffer are the
     // pseudo-time starting point; the velocities carry over unchanged

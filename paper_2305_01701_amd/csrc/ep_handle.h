@@ -65,6 +65,8 @@ struct ep_handle {
     long ntiles;
     int grid2[2];
     ep::StepCtl ctl;
+    double* vguess64[3];   // 3D: velocities of a supplied starting guess
+    bool guess_ready;      // the next increment tries vguess64
     int freeze;            // 0 off, 1 the next sweep stores Lambda, 2 Lambda frozen
     bool lam_in32;         // the frozen Lambda is in lam32 (else lam64)
     bool in_batch;         // owned by an ep_batch (ep_destroy ignores it)

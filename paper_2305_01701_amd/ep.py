@@ -37,7 +37,10 @@ SYMBOLS = ["ep_abi_version", "ep_workspace_size", "ep_init", "ep_load_step", "ep
            "ep_enable_timing", "ep_sweep_timing", "ep_step_history",
            "ep_batch_workspace_size", "ep_batch_init", "ep_batch_tune", "ep_batch_tile_shape",
            "ep_batch_load_step", "ep_batch_model", "ep_batch_enable_timing", "ep_batch_timing",
-           "ep_batch_destroy", "ep_batch_last_error"]
+           "ep_batch_destroy", "ep_batch_last_error",
+           "ep_net_workspace_size", "ep_net_init", "ep_net_param_count", "ep_net_params", "ep_net_sample",
+           "ep_net_record", "ep_net_observe", "ep_net_forward", "ep_net_gradient", "ep_net_train",
+           "ep_net_predict", "ep_net_destroy", "ep_net_last_error"]
 
 
 class ep_params(C.Structure):
@@ -60,11 +63,17 @@ class ep_step_stats(C.Structure):
         ("r_ref", C.c_double), ("ref", C.c_double), ("resid", C.c_double), ("eps_rel", C.c_double),
         ("sxx_centre", C.c_double), ("sxx_left", C.c_double), ("sxx_right", C.c_double),
         ("n_yield", C.c_longlong), ("max_violation", C.c_double), ("seconds", C.c_double),
-        ("fp32_exit", C.c_double), ("frozen_at", C.c_int),
+        ("fp32_exit", C.c_double), ("frozen_at", C.c_int), ("guess_used", C.c_int),
+        ("r_guess", C.c_double),
     ]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ep_net_config(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("base", C.c_int),
+                ("max_samples", C.c_int), ("scale", C.c_float * 4), ("seed", C.c_int)]
 
 
 class ep_residual_info(C.Structure):
@@ -115,6 +124,23 @@ def lib():
         L.ep_batch_destroy.restype = None
         L.ep_batch_last_error.restype = C.c_char_p
         L.ep_batch_last_error.argtypes = [vp]
+        fp, dp, ip = C.POINTER(C.c_float), C.POINTER(C.c_double), C.POINTER(C.c_int)
+        L.ep_net_workspace_size.argtypes = [C.POINTER(ep_net_config), C.POINTER(C.c_size_t)]
+        L.ep_net_init.argtypes = [C.POINTER(ep_net_config), vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.ep_net_param_count.restype = C.c_long
+        L.ep_net_param_count.argtypes = [vp]
+        L.ep_net_params.argtypes = [vp, C.c_int, fp, C.c_size_t]
+        L.ep_net_sample.argtypes = [vp, C.c_int, C.c_int, fp, fp]
+        L.ep_net_record.argtypes = [vp, vp, C.c_int]
+        L.ep_net_observe.argtypes = [vp, vp, C.c_int]
+        L.ep_net_forward.argtypes = [vp, C.c_int, fp]
+        L.ep_net_gradient.argtypes = [vp, C.c_int, dp, fp]
+        L.ep_net_train.argtypes = [vp, ip, C.c_int, C.c_int, C.c_float, fp]
+        L.ep_net_predict.argtypes = [vp, vp]
+        L.ep_net_destroy.argtypes = [vp]
+        L.ep_net_destroy.restype = None
+        L.ep_net_last_error.restype = C.c_char_p
+        L.ep_net_last_error.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -430,3 +456,106 @@ class Batch:
         self._check(lib().ep_batch_timing(self.b, C.byref(ms), C.byref(c32), C.byref(c64), C.byref(n)),
                     "ep_batch_timing")
         return {"ms": ms.value, "cell_sweeps32": c32.value, "cell_sweeps64": c64.value, "replays": n.value}
+
+
+def _fptr(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class Net:
+    """The warm-start network of one 3D grid (workspace from torch)."""
+
+    def __init__(self, nx, ny, nz, base=32, max_samples=8, scale=(1e-3, 1e-4, 1e-5, 1e-5), seed=0,
+                 device="cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise EpError("no GPU visible: the network runs only on the device")
+        c = ep_net_config()
+        c.nx, c.ny, c.nz, c.base, c.max_samples, c.seed = nx, ny, nz, base, max_samples, seed
+        for q in range(4):
+            c.scale[q] = scale[q]
+        self.cfg = c
+        n = C.c_size_t(0)
+        if lib().ep_net_workspace_size(C.byref(c), C.byref(n)) != EP_OK:
+            raise ValueError("invalid network configuration")
+        self.ws_bytes = n.value
+        self.device = torch.device(device)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base_ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = lib().ep_net_init(C.byref(c), C.c_void_p(base_ptr), self.ws_bytes,
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != EP_OK:
+            raise EpError(f"ep_net_init failed with {rc}")
+        self.h = h
+        r4 = lambda v: (v + 3) // 4 * 4
+        self.dims = (r4(nz), r4(ny), r4(nx))
+        self.nvox = int(np.prod(self.dims))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ep_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != EP_OK:
+            raise EpError(f"{what} failed with {rc}: {lib().ep_net_last_error(self.h).decode()}")
+
+    @property
+    def param_count(self) -> int:
+        return lib().ep_net_param_count(self.h)
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.param_count, dtype=np.float32)
+        self._check(lib().ep_net_params(self.h, EP_GET, _fptr(out), out.size), "ep_net_params")
+        return out
+
+    def set_params(self, w) -> None:
+        a = np.ascontiguousarray(w, dtype=np.float32)
+        self._check(lib().ep_net_params(self.h, EP_SET, _fptr(a), a.size), "ep_net_params")
+
+    def set_sample(self, slot, x=None, t=None) -> None:
+        xa = None if x is None else np.ascontiguousarray(x, dtype=np.float32)
+        ta = None if t is None else np.ascontiguousarray(t, dtype=np.float32)
+        self._check(lib().ep_net_sample(self.h, slot, EP_SET, _fptr(xa), _fptr(ta)), "ep_net_sample")
+
+    def get_sample(self, slot):
+        x = np.zeros(self.dims + (16,), dtype=np.float32)
+        t = np.zeros(self.dims + (4,), dtype=np.float32)
+        self._check(lib().ep_net_sample(self.h, slot, EP_GET, _fptr(x), _fptr(t)), "ep_net_sample")
+        return x, t
+
+    def record(self, solver, slot) -> None:
+        self._check(lib().ep_net_record(self.h, solver.h, slot), "ep_net_record")
+
+    def observe(self, solver, slot=-1) -> None:
+        self._check(lib().ep_net_observe(self.h, solver.h, slot), "ep_net_observe")
+
+    def forward(self, slot) -> np.ndarray:
+        y = np.zeros(self.dims + (16,), dtype=np.float32)
+        self._check(lib().ep_net_forward(self.h, slot, _fptr(y)), "ep_net_forward")
+        return y
+
+    def gradient(self, slot):
+        loss = C.c_double(0)
+        g = np.zeros(self.param_count, dtype=np.float32)
+        self._check(lib().ep_net_gradient(self.h, slot, C.byref(loss), _fptr(g)), "ep_net_gradient")
+        return loss.value, g
+
+    def train(self, slots, steps, lr=1e-3) -> np.ndarray:
+        s = np.ascontiguousarray(slots, dtype=np.int32)
+        losses = np.zeros(steps, dtype=np.float32)
+        self._check(lib().ep_net_train(self.h, s.ctypes.data_as(C.POINTER(C.c_int)), s.size, steps, lr,
+                                       _fptr(losses)), "ep_net_train")
+        return losses
+
+    def predict(self, solver) -> None:
+        self._check(lib().ep_net_predict(self.h, solver.h), "ep_net_predict")

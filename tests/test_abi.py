@@ -23,7 +23,8 @@ def E():
 
 
 def declared_functions():
-    src = open(os.path.join(ROOT, "include", "ep.h")).read()
+    inc = os.path.join(ROOT, "include")
+    src = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(ep_[a-z_0-9]+)\s*\(", src)))
 

@@ -1,0 +1,153 @@
+"""GPU parity of the warm-start network kernels (through the C ABI) against the
+float64 oracle of oracle/warmstart.py.
+
+The oracle is run with bfloat16 rounding at the points where the GPU stores
+bfloat16 tensors (input, weights, activations, gradients), so the remaining
+differences are FP32 versus float64 accumulation (relative ~1e-6) and the
+rare bfloat16 rounding flips they cause (one unit in the last place,
+2^-8 relative, at isolated entries).  Bars, relative to the norm of the
+reference: outputs and gradients within 2e-2 in L2 norm; features within one
+bfloat16 unit; the Adam update to FP32 rounding.
+"""
+import numpy as np
+import pytest
+
+from ep_workloads import Model, random_state
+from gpu_common import say
+from oracle import warmstart as W
+
+pytestmark = pytest.mark.gpu
+
+
+def net(nx, ny, nz, base=16, samples=2, seed=1, scale=(1e-3, 1e-4, 1e-5, 1e-5)):
+    from paper_2305_01701_amd.ep import Net
+    return Net(nx, ny, nz, base=base, max_samples=samples, scale=scale, seed=seed)
+
+
+def to_list(flat, base):
+    out, o = [], 0
+    for ci, co in W.channels(16, base, 16):
+        n = co * 27 * ci
+        w = flat[o:o + n].reshape(co, 27, ci).astype(np.float64)
+        o += n
+        out.append((w, flat[o:o + co].astype(np.float64)))
+        o += co
+    return out
+
+
+def to_flat(params):
+    return np.concatenate([np.concatenate([w.ravel(), b]) for w, b in params]).astype(np.float32)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-30))
+
+
+def random_net(n, base, seed):
+    """Random weights everywhere, including a nonzero head and biases."""
+    r = np.random.Generator(np.random.PCG64(seed))
+    ps = to_list(n.get_params(), base)
+    ps[-1] = (r.standard_normal(ps[-1][0].shape) * 0.05, r.standard_normal(16) * 0.01)
+    ps = [(w, r.standard_normal(b.shape) * 0.01) for w, b in ps]
+    n.set_params(to_flat(ps))
+    return to_list(n.get_params(), base)
+
+
+GRIDS = [(8, 8, 8), (12, 8, 16), (13, 9, 11)]
+
+
+@pytest.mark.parametrize("grid", GRIDS, ids=["8^3", "12x8x16", "13x9x11"])
+@pytest.mark.parametrize("base", [16, 32])
+def test_forward_matches_oracle(grid, base):
+    nx, ny, nz = grid
+    say("net forward", grid, base)
+    n = net(nx, ny, nz, base=base)
+    ps = random_net(n, base, seed=2)
+    r = np.random.Generator(np.random.PCG64(3))
+    x = r.standard_normal(n.dims + (16,))
+    n.set_sample(0, x=x)
+    y = n.forward(0)
+    yr, _ = W.forward(ps, x, store=W.bf16)
+    err = rel(y, yr)
+    say("forward rel err", err)
+    assert err < 2e-2
+    assert np.abs(y - yr).max() < 5e-2 * np.abs(yr).max()
+    n.close()
+
+
+@pytest.mark.parametrize("grid", GRIDS[1:], ids=["12x8x16", "13x9x11"])
+def test_gradient_matches_oracle(grid):
+    nx, ny, nz = grid
+    base = 16
+    n = net(nx, ny, nz, base=base)
+    ps = random_net(n, base, seed=4)
+    r = np.random.Generator(np.random.PCG64(5))
+    x = r.standard_normal(n.dims + (16,))
+    t = r.standard_normal(n.dims + (4,)) * 0.1
+    n.set_sample(1, x=x, t=t)
+    loss, g = n.gradient(1)
+    m = Model(ndim=3, nx=nx, ny=ny, nz=nz)
+    zero = {k: np.zeros((nx + (k == "vx")) * (ny + (k == "vy")) * (nz + (k == "vz"))) for k in ("vx", "vy", "vz")}
+    _, mask = W.targets(m, zero, 1.0)
+    t16 = np.zeros(n.dims + (16,))
+    t16[..., :3] = t[..., :3].astype(np.float32)
+    yr, cache = W.forward(ps, x, store=W.bf16)
+    lr_, gy = W.loss_grad(yr, t16, mask)
+    gr = W.backward(cache, gy, store=W.bf16)
+    say("loss", loss, lr_)
+    assert loss == pytest.approx(lr_, rel=1e-3)
+    gl = to_list(g, base)
+    for l in range(W.N_LAYERS):
+        ew, eb = rel(gl[l][0], gr[l][0]), rel(gl[l][1], gr[l][1])
+        say("layer", l, "dW rel", ew, "db rel", eb)
+        assert ew < 2e-2 and eb < 2e-2, (l, ew, eb)
+    n.close()
+
+
+def test_adam_step_matches_oracle_and_training_reduces_loss():
+    base = 16
+    n = net(12, 8, 16, base=base)
+    ps = random_net(n, base, seed=6)
+    r = np.random.Generator(np.random.PCG64(7))
+    n.set_sample(0, x=r.standard_normal(n.dims + (16,)), t=r.standard_normal(n.dims + (4,)) * 0.1)
+    _, g = n.gradient(0)
+    losses = n.train([0], 1, lr=1e-3)
+    after = to_list(n.get_params(), base)
+    opt = W.Adam(ps, lr=1e-3)
+    ref = opt.step(ps, to_list(g, base))
+    for l in range(W.N_LAYERS):
+        assert np.allclose(after[l][0], ref[l][0], rtol=1e-5, atol=1e-7), l
+        assert np.allclose(after[l][1], ref[l][1], rtol=1e-5, atol=1e-7), l
+    more = n.train([0], 30, lr=1e-3)
+    say("losses", losses[0], more[0], more[-1])
+    assert more[-1] < 0.5 * losses[0]
+    n.close()
+
+
+def test_features_and_tracking_match_oracle():
+    from paper_2305_01701_amd.ep import Solver
+    m = Model(ndim=3, nx=13, ny=9, nz=11, incl_radius=0.3)
+    scale = (1e-3, 1e-4, 1e-3, 1e-3)
+    g = Solver(m)
+    st1 = random_state(m, seed=8)
+    st2 = random_state(m, seed=9)
+    for k in ("vx", "vy", "vz", "p", "txx", "tyy", "txy", "txz", "tyz"):
+        g.set(k, st1[k])
+    eps = np.abs(random_state(m, seed=10)["p"]) * 0.1
+    g.set("eps_p", eps)
+    n = net(m.nx, m.ny, m.nz, scale=scale)
+    n.observe(g)                                   # starts tracking (change 0)
+    for k in ("vx", "vy", "vz"):
+        g.set(k, st2[k])
+    n.observe(g, slot=1)                           # change = st2 - st1, also the target of slot 1
+    n.record(g, 0)
+    x, _ = n.get_sample(0)
+    _, t = n.get_sample(1)
+    f = g.fields(["p", "txx", "tyy", "txy", "txz", "tyz", "eps_p"])
+    dv = {k: st2[k] - st1[k] for k in ("vx", "vy", "vz")}
+    xr = W.bf16(W.features(m, f, dv, scale[:3]))
+    assert np.allclose(x, xr, rtol=2 ** -7, atol=1e-30)
+    tr, _ = W.targets(m, dv, scale[3])
+    assert np.allclose(t[..., :3], tr[..., :3], rtol=1e-6, atol=1e-9)
+    n.close()
+    g.close()
