@@ -88,6 +88,12 @@ typedef struct ep_params {
                                 iteration continues with the plastic multiplier Lambda of
                                 the next sweep held fixed at every cell (a linear problem).
                                 2D with the fused sweep only (EP_EINVAL otherwise) */
+    double guess_accept;     /* a supplied starting guess (ep_net_predict) is used when the
+                                residual of its physical stresses is below guess_accept times
+                                that of the plain guess (0: 1, i.e. only when lower).  The PT
+                                iteration removes rough errors of a guess within few sweeps,
+                                so a larger value can pay off; an increment that fails from
+                                the guess is redone from the plain guess */
 } ep_params;
 
 typedef struct ep_step_stats {
@@ -106,7 +112,9 @@ typedef struct ep_step_stats {
     double seconds;          /* wall time of the call */
     double fp32_exit;        /* normalised residual when FP32 handed over (0 in FP64 mode) */
     int    frozen_at;        /* iteration whose check froze Lambda (0: not frozen) */
-    int    guess_used;       /* 1: the increment started from a supplied guess (ep_net_predict) */
+    int    guess_used;       /* 1: the increment started from a supplied guess (ep_net_predict);
+                                -1: it failed from the guess and was redone from the plain guess
+                                (iters counts both attempts) */
     double r_guess;          /* momentum residual of the physical stresses of that guess (0: none) */
 } ep_step_stats;
 

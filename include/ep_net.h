@@ -82,6 +82,10 @@ int ep_net_record(ep_net* n, ep_handle* h, int slot);
  * target of that slot.  The first call only starts the tracking (change 0). */
 int ep_net_observe(ep_net* n, ep_handle* h, int slot);
 
+/* Forget the tracked velocities: the next ep_net_observe starts a new
+ * trajectory (change 0). */
+int ep_net_reset(ep_net* n);
+
 /* Forward pass on a slot (-1: the inference input); y (may be NULL):
  * D*H*W*16 FP32 outputs. */
 int ep_net_forward(ep_net* n, int slot, float* y);

@@ -59,7 +59,7 @@ int validate(const ep_params* p)
     if (p->cfl > 0 && p->cfl >= 1.0 / std::sqrt((double)p->ndim)) return EP_EINVAL;
     if (p->precision != EP_FP64 && p->precision != EP_FP32_FIELDS) return EP_EINVAL;
     if (p->sweep < EP_SWEEP_AUTO || p->sweep > EP_SWEEP_UNFUSED) return EP_EINVAL;
-    if (p->freeze_iter < 0) return EP_EINVAL;
+    if (p->freeze_iter < 0 || p->guess_accept < 0) return EP_EINVAL;
     if (p->freeze_iter > 0 && (p->ndim != 2 || p->sweep == EP_SWEEP_UNFUSED)) return EP_EINVAL;
     return EP_OK;
 }
@@ -476,7 +476,8 @@ int step_start(ep_handle* h, const double red[RED_N])
         int rc = read_red(h, rg);
         if (rc) return rc;
         st->r_guess = rg[RED_MOM];
-        if (rg[RED_MOM] < st->r_ref) {
+        const double accept = h->prm.guess_accept > 0 ? h->prm.guess_accept : 1.0;
+        if (rg[RED_MOM] < accept * st->r_ref) {
             st->guess_used = 1;
         } else {
             for (int d = 0; d < h->ndim; ++d)
@@ -868,7 +869,19 @@ int ep_load_step(ep_handle* h, ep_step_stats* st)
         add_timing(h, use32, nb);
         step_check(h, red, nb);
     }
-    if ((rc = step_finish(h))) return rc;
+    if ((rc = step_finish(h))) {
+        if (st->guess_used != 1) return rc;
+        // failed from the supplied guess: the state is back at the increment
+        // start; redo the increment from the plain guess
+        const ep_step_stats first = *st;
+        rc = ep_load_step(h, st);
+        st->guess_used = -1;
+        st->r_guess = first.r_guess;
+        st->iters += first.iters;
+        st->iters_fp32 += first.iters_fp32;
+        st->seconds += first.seconds;
+        return rc;
+    }
     double cols[4];
     HIPCHK(h, hipMemcpyAsync(cols, h->cols64, sizeof(cols), hipMemcpyDeviceToHost, h->st));
     if ((rc = read_red(h, red))) return rc;

@@ -927,6 +927,13 @@ int ep_net_observe(ep_net* n, ep_handle* h, int slot)
     return EP_OK;
 }
 
+int ep_net_reset(ep_net* n)
+{
+    if (!n) return EP_EINVAL;
+    n->have_last = false;
+    return EP_OK;
+}
+
 int ep_net_forward(ep_net* n, int slot, float* y)
 {
     if (!n || slot < -1 || slot >= n->cfg.max_samples) return EP_EINVAL;

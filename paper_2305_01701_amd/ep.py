@@ -39,7 +39,7 @@ SYMBOLS = ["ep_abi_version", "ep_workspace_size", "ep_init", "ep_load_step", "ep
            "ep_batch_load_step", "ep_batch_model", "ep_batch_enable_timing", "ep_batch_timing",
            "ep_batch_destroy", "ep_batch_last_error",
            "ep_net_workspace_size", "ep_net_init", "ep_net_param_count", "ep_net_params", "ep_net_sample",
-           "ep_net_record", "ep_net_observe", "ep_net_forward", "ep_net_gradient", "ep_net_train",
+           "ep_net_record", "ep_net_observe", "ep_net_reset", "ep_net_forward", "ep_net_gradient", "ep_net_train",
            "ep_net_predict", "ep_net_destroy", "ep_net_last_error"]
 
 
@@ -53,7 +53,7 @@ class ep_params(C.Structure):
         ("max_iter", C.c_int), ("n_check", C.c_int),
         ("re", C.c_double), ("r", C.c_double), ("cfl", C.c_double),
         ("precision", C.c_int), ("sweep", C.c_int), ("fp32_switch", C.c_double),
-        ("fp32_stall", C.c_int), ("freeze_iter", C.c_int),
+        ("fp32_stall", C.c_int), ("freeze_iter", C.c_int), ("guess_accept", C.c_double),
     ]
 
 
@@ -133,6 +133,7 @@ def lib():
         L.ep_net_sample.argtypes = [vp, C.c_int, C.c_int, fp, fp]
         L.ep_net_record.argtypes = [vp, vp, C.c_int]
         L.ep_net_observe.argtypes = [vp, vp, C.c_int]
+        L.ep_net_reset.argtypes = [vp]
         L.ep_net_forward.argtypes = [vp, C.c_int, fp]
         L.ep_net_gradient.argtypes = [vp, C.c_int, dp, fp]
         L.ep_net_train.argtypes = [vp, ip, C.c_int, C.c_int, C.c_float, fp]
@@ -269,7 +270,7 @@ def ep_step_history(h, cap: int = 1 << 20) -> tuple:
 
 
 def params_from_model(m, precision: int = EP_FP64, sweep: int = EP_SWEEP_AUTO,
-                      fp32_switch: float = 0.0, fp32_stall: int = 0) -> ep_params:
+                      fp32_switch: float = 0.0, fp32_stall: int = 0, guess_accept: float = 0.0) -> ep_params:
     p = ep_params()
     p.ndim, p.nx, p.ny = m.ndim, m.nx, m.ny
     p.nz = m.nz if m.ndim == 3 else 1
@@ -282,6 +283,7 @@ def params_from_model(m, precision: int = EP_FP64, sweep: int = EP_SWEEP_AUTO,
     p.re, p.r, p.cfl = m.re, m.r, m.cfl
     p.precision, p.sweep, p.fp32_switch, p.fp32_stall = precision, sweep, fp32_switch, fp32_stall
     p.freeze_iter = m.freeze_iter
+    p.guess_accept = guess_accept
     return p
 
 
@@ -337,12 +339,12 @@ class Solver(ModelView):
 
     def __init__(self, model, cohesion: Optional[np.ndarray] = None, precision: int = EP_FP64,
                  sweep: int = EP_SWEEP_AUTO, fp32_switch: float = 0.0, fp32_stall: int = 0,
-                 device: str = "cuda:0", stream=None):
+                 guess_accept: float = 0.0, device: str = "cuda:0", stream=None):
         import torch
         if not torch.cuda.is_available():
             raise EpError("no GPU visible: the solver runs only on the device")
         self.model = model
-        self.params = params_from_model(model, precision, sweep, fp32_switch, fp32_stall)
+        self.params = params_from_model(model, precision, sweep, fp32_switch, fp32_stall, guess_accept)
         self.ws_bytes = ep_workspace_size(self.params)
         self.torch = torch
         self.device = torch.device(device)
@@ -538,6 +540,9 @@ class Net:
 
     def observe(self, solver, slot=-1) -> None:
         self._check(lib().ep_net_observe(self.h, solver.h, slot), "ep_net_observe")
+
+    def reset(self) -> None:
+        self._check(lib().ep_net_reset(self.h), "ep_net_reset")
 
     def forward(self, slot) -> np.ndarray:
         y = np.zeros(self.dims + (16,), dtype=np.float32)

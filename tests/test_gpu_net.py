@@ -151,3 +151,60 @@ def test_features_and_tracking_match_oracle():
     assert np.allclose(t[..., :3], tr[..., :3], rtol=1e-6, atol=1e-9)
     n.close()
     g.close()
+
+
+def test_warm_start_pipeline_converges_to_the_plain_solution():
+    """The learned warm start end to end on the GPU: trajectories of two 3D
+    models generate the training samples, the network trains on them, and a
+    held-out model is solved from the network's guesses (accepted only when
+    their physical residual is lower than that of the plain guess).  Every
+    increment must converge to the tolerance and end where the plain run ends;
+    the iteration counts of both runs are reported (the gain)."""
+    from paper_2305_01701_amd.ep import Solver
+    N, steps = 15, 8
+
+    def model(c):
+        return Model(ndim=3, nx=N, ny=N, nz=N, dt=2e-4, tol=1e-6, n_check=10, incl_radius=0.2,
+                     incl_centre=c, max_iter=100000)
+
+    train_models = [model((0.05, -0.03, 0.02)), model((-0.04, 0.06, -0.01))]
+    held = model((0.02, 0.02, -0.05))
+    n = net(N, N, N, base=16, samples=len(train_models) * steps, scale=(3.5e-3, 3e-2, 0.5, 0.5))
+    slots = []
+    for q, m in enumerate(train_models):
+        s = Solver(m)
+        n.reset()
+        n.observe(s)
+        for k in range(steps):
+            n.record(s, q * steps + k)
+            assert s.load_step()["status"] == 0
+            n.observe(s, q * steps + k)
+            slots.append(q * steps + k)
+        s.close()
+    losses = n.train(slots, 1600, lr=3e-4)
+    first, last = losses[:len(slots)].mean(), losses[-len(slots):].mean()
+    say("training loss", first, "->", last)
+    assert last < 0.5 * first
+
+    plain = Solver(held)
+    warm = Solver(held)
+    n.reset()
+    n.observe(warm)
+    it_p, it_w, used = [], [], []
+    for k in range(steps):
+        sp = plain.load_step()
+        n.predict(warm)
+        sw = warm.load_step()
+        n.observe(warm)
+        assert sp["status"] == 0 and sw["status"] == 0, (k, sp["status"], sw["status"])
+        assert sw["resid"] <= held.tol * sw["ref"]
+        it_p.append(sp["iters"])
+        it_w.append(sw["iters"])
+        used.append(sw["guess_used"])
+    say("iterations plain", it_p, sum(it_p), "warm", it_w, sum(it_w), "guess used", used)
+    names = ["vx", "vy", "vz", "p", "txx", "tyy", "txy", "txz", "tyz"]
+    a, b = plain.fields(names), warm.fields(names)
+    for k in names:
+        err = np.abs(a[k] - b[k]).max() / max(np.abs(a[k]).max(), 1e-30)
+        assert err < 1e-3, (k, err)
+    n.close()
