@@ -20,6 +20,8 @@
 //
 // The arithmetic of every point is that of the unfused sweep (same formulas,
 // same Jacobi order: all reads are of iteration k, all writes iteration k+1).
+#include <type_traits>
+
 #include "ep_device.h"
 
 namespace ep {
@@ -29,13 +31,21 @@ namespace {
 __device__ __forceinline__ int mod3(int f) { int r = f % 3; return r < 0 ? r + 3 : r; }
 __device__ __forceinline__ int mod2(int f) { return f & 1; }
 
+// Tile grid of a 3D sweep and its interior rectangle [bx0, bx1) x [by0,
+// by1): tiles whose points, 2-point halo included, lie strictly inside the
+// domain in x and y.
+struct TileSet {
+    int nbx, nby, nbz;
+    int bx0, bx1, by0, by1;
+};
+
 // ----------------------------------------------------------------------- 3D
 // Global data a march step needs is prefetched into registers one step
 // ahead (velocities of plane f+1, edge stresses of level f+1 and plane f,
 // centre data of plane f), so that HBM latency overlaps the LDS work of the
 // current step.  Each thread owns the same plane positions in every step.
 template <typename R, int TX, int TY, int ZC, int MODE>
-__global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, int nbx, int nby, int nbz)
+__global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, TileSet ts)
 {
     constexpr int W = TX + 4, H = TY + 4, N = W * H, NT = TX * TY;
     constexpr int NQ = (N + NT - 1) / NT;                  // plane positions per thread
@@ -47,8 +57,12 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, int nbx, i
     __shared__ R s_nxy[2][N], s_nxz[2][N], s_nyz[2][N];
     __shared__ double s_red[NT / 64 > 0 ? NT / 64 : 1];
 
-    const int lb = xcd_remap(blockIdx.x, nbx * nby * nbz);
-    const int bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
+    const int lb = xcd_remap(blockIdx.x, ts.nbx * ts.nby * ts.nbz);
+    const int bx = lb % ts.nbx, by = (lb / ts.nbx) % ts.nby, bz = lb / (ts.nbx * ts.nby);
+    // the same sweep, compiled twice: for tiles strictly inside the domain in
+    // x and y no point needs a boundary test
+    auto body = [&](auto interior) {
+    constexpr bool INT = decltype(interior)::value;
     const int i0 = bx * TX, j0 = by * TY;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int k0 = bz * ZC, k1 = min(k0 + ZC, nz);
@@ -95,16 +109,16 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, int nbx, i
             const int i = qi[u], j = qj[u];
             const long e = i + sy * j + sz * g;
             const bool ok = qok[u];
-            fvx[u] = (ok && pl && i >= 0 && i <= nx && j >= 0 && j < ny) ? vx[e] : R(0);
-            fvy[u] = (ok && pl && i >= 0 && i < nx && j >= 0 && j <= ny) ? vy[e] : R(0);
-            fvz[u] = (ok && lv && i >= 0 && i < nx && j >= 0 && j < ny) ? vz[e] : R(0);
-            const bool exz = ok && inner && i >= 1 && i <= nx - 1 && j >= 0 && j < ny;
-            const bool eyz = ok && inner && j >= 1 && j <= ny - 1 && i >= 0 && i < nx;
+            fvx[u] = (ok && pl && (INT || (i >= 0 && i <= nx && j >= 0 && j < ny))) ? vx[e] : R(0);
+            fvy[u] = (ok && pl && (INT || (i >= 0 && i < nx && j >= 0 && j <= ny))) ? vy[e] : R(0);
+            fvz[u] = (ok && lv && (INT || (i >= 0 && i < nx && j >= 0 && j < ny))) ? vz[e] : R(0);
+            const bool exz = ok && inner && (INT || (i >= 1 && i <= nx - 1 && j >= 0 && j < ny));
+            const bool eyz = ok && inner && (INT || (j >= 1 && j <= ny - 1 && i >= 0 && i < nx));
             fxz[u] = exz ? txz_k[e] : R(0);
             fxzo[u] = exz ? txz_o[e] : R(0);
             fyz[u] = eyz ? tyz_k[e] : R(0);
             fyzo[u] = eyz ? tyz_o[e] : R(0);
-            const bool exy = ok && pm && i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1;
+            const bool exy = ok && pm && (INT || (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1));
             fxy[u] = exy ? txy_k[e - sz] : R(0);
             fxyo[u] = exy ? txy_o[e - sz] : R(0);
         }
@@ -112,7 +126,7 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, int nbx, i
         for (int u = 0; u < NR; ++u) {
             const int i = ri[u], j = rj[u];
             const long e = i + sy * j + sz * (g - 1);
-            const bool ok = rok[u] && pm && i >= 0 && i < nx && j >= 0 && j < ny;
+            const bool ok = rok[u] && pm && (INT || (i >= 0 && i < nx && j >= 0 && j < ny));
             fp[u] = ok ? p_k[e] : R(0);
             fpo[u] = ok ? p_o[e] : R(0);
             fsx[u] = ok ? txx_k[e] : R(0);
@@ -173,11 +187,11 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, int nbx, i
                 const int i = qi[u], j = qj[u];
                 if (do_l) {
                     R txz = R(0), tyz = R(0);
-                    if (inner_l && i >= 1 && i <= nx - 1 && j >= 0 && j < ny) {
+                    if (inner_l && (INT || (i >= 1 && i <= nx - 1 && j >= 0 && j < ny))) {
                         R e2 = (s_vx[cm][q] - s_vx[cp3][q]) * idz + (s_vz[sl][q] - s_vz[sl][q - 1]) * idx;
                         txz = cxz[u] * igt + cxzo[u] * igd + e2;
                     }
-                    if (inner_l && j >= 1 && j <= ny - 1 && i >= 0 && i < nx) {
+                    if (inner_l && (INT || (j >= 1 && j <= ny - 1 && i >= 0 && i < nx))) {
                         R e2 = (s_vy[cm][q] - s_vy[cp3][q]) * idz + (s_vz[sl][q] - s_vz[sl][q - W]) * idy;
                         tyz = cyz[u] * igt + cyzo[u] * igd + e2;
                     }
@@ -186,7 +200,7 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, int nbx, i
                 }
                 if (do_p) {
                     R t = R(0);
-                    if (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1) {
+                    if (INT || (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1)) {
                         R e2 = (s_vx[pm][q] - s_vx[pm][q - W]) * idy + (s_vy[pm][q] - s_vy[pm][q - 1]) * idx;
                         t = cxy[u] * igt + cxyo[u] * igd + e2;
                     }
@@ -206,7 +220,7 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, int nbx, i
                 const int la = 1 + r % CW, lbb = 1 + r / CW;
                 const int q = la + W * lbb;
                 const int i = ri[u], j = rj[u];
-                if (!(i >= 0 && i < nx && j >= 0 && j < ny)) {
+                if (!INT && !(i >= 0 && i < nx && j >= 0 && j < ny)) {
                     s_lam[sc][q] = R(0);
                     s_p[sc][q] = R(0);
                     s_sxx[sc][q] = R(0);
@@ -260,12 +274,12 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, int nbx, i
                     const int q = la + W * lbb;
                     const int i = i0 - 2 + la, j = j0 - 2 + lbb;
                     R t = R(0);
-                    if (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1) {
+                    if (INT || (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1)) {
                         R lv = R(0.25) * (s_lam[sp][q - W - 1] + s_lam[sp][q - W] + s_lam[sp][q - 1] + s_lam[sp][q]);
                         t = s_Txy[q] * fast_rcp(D + lv);
                     }
                     s_nxy[sp][q] = t;
-                    if (la < TX + 2 + hx && lbb < TY + 2 + hy && i <= nx && j <= ny) {
+                    if (la < TX + 2 + hx && lbb < TY + 2 + hy && (INT || (i <= nx && j <= ny))) {
                         const long e = i + sy * j + sz * p;
                         a.nx_[F_TXY][e] = t;
                         if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)(fabs(t - a.it[F_TXY][e]) * a.rG));
@@ -286,12 +300,12 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, int nbx, i
                     // xz edge (i, j) at level l: x-extent nx+1, y-extent ny
                     if (lbb < TY + 2) {
                         R t = R(0);
-                        if (inner_l && i >= 1 && i <= nx - 1 && j < ny) {
+                        if (inner_l && (INT || (i >= 1 && i <= nx - 1 && j < ny))) {
                             R lv = R(0.25) * (s_lam[sm][q - 1] + s_lam[sm][q] + s_lam[sl][q - 1] + s_lam[sl][q]);
                             t = s_Txz[sl][q] * fast_rcp(D + lv);
                         }
                         s_nxz[sl][q] = t;
-                        if (own_l && la < TX + 2 + hx && i <= nx && j < ny) {
+                        if (own_l && la < TX + 2 + hx && (INT || (i <= nx && j < ny))) {
                             a.nx_[F_TXZ][e] = t;
                             if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)(fabs(t - a.it[F_TXZ][e]) * a.rG));
                         }
@@ -299,12 +313,12 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, int nbx, i
                     // yz edge (i, j) at level l: x-extent nx, y-extent ny+1
                     if (la < TX + 2) {
                         R t = R(0);
-                        if (inner_l && j >= 1 && j <= ny - 1 && i < nx) {
+                        if (inner_l && (INT || (j >= 1 && j <= ny - 1 && i < nx))) {
                             R lv = R(0.25) * (s_lam[sm][q - W] + s_lam[sm][q] + s_lam[sl][q - W] + s_lam[sl][q]);
                             t = s_Tyz[sl][q] * fast_rcp(D + lv);
                         }
                         s_nyz[sl][q] = t;
-                        if (own_l && lbb < TY + 2 + hy && i < nx && j <= ny) {
+                        if (own_l && lbb < TY + 2 + hy && (INT || (i < nx && j <= ny))) {
                             a.nx_[F_TYZ][e] = t;
                             if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)(fabs(t - a.it[F_TYZ][e]) * a.rG));
                         }
@@ -324,9 +338,9 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, int nbx, i
                     const int q = la + W * lbb;
                     const int i = i0 - 2 + la, j = j0 - 2 + lbb;
                     const long e = i + sy * j + sz * p;
-                    if (la < TX + 2 + hx && lbb < TY + 2 && i <= nx && j < ny) {      // x-face
+                    if (la < TX + 2 + hx && lbb < TY + 2 && (INT || (i <= nx && j < ny))) {      // x-face
                         R v = s_vx[cm][q];
-                        if (i >= 1 && i <= nx - 1) {
+                        if (INT || (i >= 1 && i <= nx - 1)) {
                             R Rx = ((s_sxx[sp][q] - s_p[sp][q]) - (s_sxx[sp][q - 1] - s_p[sp][q - 1])) * idx
                                  + (s_nxy[sp][q + W] - s_nxy[sp][q]) * idy + (s_nxz[sp1][q] - s_nxz[sp][q]) * idz;
                             v = v + a.dtrho * Rx;
@@ -335,9 +349,9 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, int nbx, i
                         if (MODE != MODE_PHYS) a.nx_[F_VX][e] = v;
                         vmax = nmax(vmax, (double)fabs(v));
                     }
-                    if (la < TX + 2 && lbb < TY + 2 + hy && i < nx && j <= ny) {      // y-face
+                    if (la < TX + 2 && lbb < TY + 2 + hy && (INT || (i < nx && j <= ny))) {      // y-face
                         R v = s_vy[cm][q];
-                        if (j >= 1 && j <= ny - 1) {
+                        if (INT || (j >= 1 && j <= ny - 1)) {
                             R Ry = (s_nxy[sp][q + 1] - s_nxy[sp][q]) * idx
                                  + ((s_syy[sp][q] - s_p[sp][q]) - (s_syy[sp][q - W] - s_p[sp][q - W])) * idy
                                  + (s_nyz[sp1][q] - s_nyz[sp][q]) * idz;
@@ -357,7 +371,7 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, int nbx, i
                     const int la = 2 + r % TX, lbb = 2 + r / TX;
                     const int q = la + W * lbb;
                     const int i = i0 - 2 + la, j = j0 - 2 + lbb;
-                    if (i >= nx || j >= ny) continue;
+                    if (!INT && (i >= nx || j >= ny)) continue;
                     const long e = i + sy * j + sz * l;
                     R v = s_vz[sl][q];
                     if (inner_l) {
@@ -383,6 +397,9 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, int nbx, i
             block_max_to<NT>(smax, a.red + RED_SMAX, s_red);
         }
     }
+    };
+    if (bx >= ts.bx0 && bx < ts.bx1 && by >= ts.by0 && by < ts.by1) body(std::true_type{});
+    else body(std::false_type{});
 }
 
 // tile shapes
@@ -393,12 +410,27 @@ template <typename R> struct Tile3;
 template <> struct Tile3<float> { static constexpr int X = T3X, Y = T3Y, Z = T3Z; };
 template <> struct Tile3<double> { static constexpr int X = D3X, Y = D3Y, Z = D3Z; };
 
+// first and one-past-last tile index along an axis whose tiles lie strictly
+// inside with their 2-point halo: 3 <= i0 and i0 + T + 2 <= n
+inline void interior_range(int n, int T, int nb, int& b0, int& b1)
+{
+    b0 = (3 + T - 1) / T;
+    b1 = (n - T - 2) >= 0 ? (n - T - 2) / T + 1 : 0;
+    if (b1 > nb) b1 = nb;
+    if (b1 < b0) b1 = b0;
+}
+
 template <typename R, int MODE>
 void run_3d(const SweepArgs<R>& a, hipStream_t s)
 {
     constexpr int TX = Tile3<R>::X, TY = Tile3<R>::Y, ZC = Tile3<R>::Z;
-    const int nbx = (a.nx + TX - 1) / TX, nby = (a.ny + TY - 1) / TY, nbz = (a.nz + ZC - 1) / ZC;
-    k_fused_3d<R, TX, TY, ZC, MODE><<<nbx * nby * nbz, TX * TY, 0, s>>>(a, nbx, nby, nbz);
+    TileSet ts;
+    ts.nbx = (a.nx + TX - 1) / TX;
+    ts.nby = (a.ny + TY - 1) / TY;
+    ts.nbz = (a.nz + ZC - 1) / ZC;
+    interior_range(a.nx, TX, ts.nbx, ts.bx0, ts.bx1);
+    interior_range(a.ny, TY, ts.nby, ts.by0, ts.by1);
+    k_fused_3d<R, TX, TY, ZC, MODE><<<ts.nbx * ts.nby * ts.nbz, TX * TY, 0, s>>>(a, ts);
 }
 
 

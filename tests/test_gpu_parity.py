@@ -43,6 +43,8 @@ SWEEP_CASES = [
     ("3d-13x11x9", Model(ndim=3, nx=13, ny=11, nz=9, lz=0.8, incl_radius=0.3)),
     ("3d-3x3x3", Model(ndim=3, nx=3, ny=3, nz=3)),
     ("3d-70x33x17", Model(ndim=3, nx=70, ny=33, nz=17, incl_radius=0.25)),
+    # tiles strictly inside the domain in x and y (the 3D sweep's interior fast path)
+    ("3d-100x60x20", Model(ndim=3, nx=100, ny=60, nz=20, ly=0.7, lz=0.4, incl_radius=0.2)),
 ]
 
 
