@@ -51,6 +51,10 @@ def workload(name):
                       "phi U[20,40], c0 U[1e-3,3e-3], inclusion radius U[0.05,0.15] at seeded positions, "
                       "strain increment 1e-4, tol 1e-6, one persistent launch per sweep under graph replays, "
                       "autotuned tile shapes")
+    if name.startswith("3d-") and name.endswith("-warm"):
+        n = int(name[3:-5])
+        return c3_3d(n), (f"3d-{n}^3 pure shear, spherical weak inclusion, strain increment 5e-5, tol 1e-6; "
+                          "plain guess vs learned warm start (network trained on two other inclusion positions)")
     if name.startswith("3d-"):
         n = int(name[3:])
         return c3_3d(n), f"3d-{n}^3 pure shear, spherical weak inclusion"
@@ -63,11 +67,12 @@ def bytes_per_cell(ndim, prec_bytes):
 
 
 def kernel_sources_hash():
+    """Hash of the sources that define the 3D sweep kernels (the traffic
+    counters are void once these change)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2305_01701_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in ("ep_device.h", "ep_internal.h", "ep_sweep_fused.hip", "ep_sweep_unfused.hip"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -167,6 +172,117 @@ def run_batch(args, E):
     }
 
 
+def net_flops_per_voxel(base):
+    """Forward FLOPs of the warm-start network per voxel of its level-0 volume."""
+    c, c2, c4 = base, 2 * base, 4 * base
+    l0 = 16 * c + c * c + c2 * c + c * c + c * 16
+    l1 = c * c2 + c2 * c2 + c4 * c2 + c2 * c2
+    l2 = c2 * c4 + c4 * c4
+    return 2 * 27 * (l0 + l1 / 8 + l2 / 64)
+
+
+def run_warm(args, E, name):
+    """Plain vs learned warm start on a 3D model: the network is trained on
+    trajectories of two models with other inclusion positions, then the
+    held-out model is solved both ways."""
+    import numpy as np
+    import torch
+    base_model, desc = workload(name)
+    n = base_model.nx
+    T = args.warmup + args.steps
+    prec = E.EP_FP32_FIELDS if args.precision == "fp32" else E.EP_FP64
+    mk = lambda c: base_model.with_(incl_centre=c, max_iter=2_000_000)
+    train_models = [mk((0.06, -0.04, 0.03)), mk((-0.05, 0.05, -0.02))]
+    held = mk((0.02, 0.03, -0.04))
+    # scales of the features and targets from the first training trajectory
+    s = E.Solver(train_models[0], precision=prec)
+    v0 = {k: s.get(k) for k in ("vx", "vy", "vz")}
+    smax = emax = dvmax = 0.0
+    for k in range(T):
+        s.load_step()
+        v1 = {q: s.get(q) for q in v0}
+        dvmax = max(dvmax, max(float(np.abs(v1[q] - v0[q]).max()) for q in v0))
+        v0 = v1
+        smax = max(smax, float(np.abs(s.get("txx")).max()), float(np.abs(s.get("p")).max()))
+        emax = max(emax, float(np.abs(s.get("eps_p")).max()))
+    s.close()
+    scale = (smax, max(emax, 1e-12), max(dvmax, 1e-12), max(dvmax, 1e-12))
+    log("feature scales", scale)
+    net = E.Net(n, n, n, base=32, max_samples=len(train_models) * T, scale=scale, seed=0)
+    t0 = time.perf_counter()
+    slots = []
+    for q, m in enumerate(train_models):
+        s = E.Solver(m, precision=prec)
+        net.reset()
+        net.observe(s)
+        for k in range(T):
+            net.record(s, q * T + k)
+            s.load_step()
+            net.observe(s, q * T + k)
+            slots.append(q * T + k)
+        s.close()
+        log(f"training trajectory {q + 1}/{len(train_models)} generated ({time.perf_counter() - t0:.1f}s)")
+    t1 = time.perf_counter()
+    steps_train = 1200
+    losses = net.train(slots, steps_train, lr=3e-4)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    log(f"trained {steps_train} Adam steps in {train_s:.1f}s, loss {losses[:len(slots)].mean():.3e} -> "
+        f"{losses[-len(slots):].mean():.3e}")
+
+    def solve(warm):
+        s = E.Solver(held, precision=prec)
+        if warm:
+            net.reset()
+            net.observe(s)
+        its, secs, used, pred = [], [], [], []
+        for k in range(T):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            if warm:
+                net.predict(s)
+                torch.cuda.synchronize()
+                pred.append(time.perf_counter() - t)
+            st = s.load_step()
+            if warm:
+                net.observe(s)
+            torch.cuda.synchronize()
+            its.append(st["iters"])
+            secs.append(time.perf_counter() - t)
+            used.append(st["guess_used"])
+        s.close()
+        return its, secs, used, pred
+
+    ip, sp, _, _ = solve(False)
+    iw, sw, used, pred = solve(True)
+    timed = slice(args.warmup, T)
+    cells = held.n_cells
+    log(f"plain iters {ip}\nwarm  iters {iw}\nguess used {used}")
+    pred_ms = 1e3 * sum(pred) / len(pred)
+    flops = net_flops_per_voxel(32) * net.nvox
+    achieved = flops / (pred_ms * 1e-3) / 1e12
+    it_w, s_w = sum(iw[timed]), sum(sw[timed])
+    value = it_w * cells * bytes_per_cell(3, 4 if prec else 8) / s_w / 1e9
+    return {
+        "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(s_w / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == E.EP_FP32_FIELDS else "f64", "data": "synthetic",
+        "config": {"workload": desc, "cells": cells, "increments_timed": f"{args.warmup + 1}..{T}",
+                   "precision": args.precision},
+        "plain": {"iters_per_step": sum(ip[timed]) / args.steps, "s_per_step": round(sum(sp[timed]) / args.steps, 4)},
+        "warm": {"iters_per_step": it_w / args.steps, "s_per_step": round(s_w / args.steps, 4),
+                 "guesses_used": sum(1 for u in used[timed] if u == 1)},
+        "training": {"samples": len(slots), "adam_steps": steps_train, "seconds": round(train_s, 2),
+                     "loss_first": float(losses[:len(slots)].mean()), "loss_last": float(losses[-len(slots):].mean())},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": round(achieved / 2500.0, 5), "traffic": None,
+                     "kernel": "warm-start network inference (bf16 MFMA convolutions)",
+                     "flops_per_inference": flops, "avg_inference_ms": round(pred_ms, 3)},
+        "cpu_baseline": None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,6 +306,9 @@ def main():
 
     if args.workload == "batch-2d-256":
         print(json.dumps(run_batch(args, E)), flush=True)
+        return
+    if args.workload.endswith("-warm"):
+        print(json.dumps(run_warm(args, E, args.workload)), flush=True)
         return
     m, desc = workload(args.workload)
     m = m.with_(max_iter=2_000_000)
