@@ -252,7 +252,7 @@ def test_checkpoint_restore_continues_bitwise():
     keep = b.fields()
     c = solver(m)
     for k, v in keep.items():
-        if k in ("lambda_dot", "tau_ii", "yield", "tzz", "tzz_old"):
+        if k in ("lambda_dot", "tau_ii", "yield", "lambda_frozen", "tzz", "tzz_old"):
             continue
         c.set(k, v)
     for _ in range(2):
