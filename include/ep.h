@@ -171,6 +171,16 @@ int ep_init(const ep_params* p, const double* cohesion, void* d_workspace, size_
  * increment start and st is still filled.  st may be NULL. */
 int ep_load_step(ep_handle* h, ep_step_stats* st);
 
+/* Starting guess of the next ep_load_step: face velocities (host FP64 arrays
+ * at the shapes of EP_F_VX, EP_F_VY, EP_F_VZ; vz NULL in 2D), copied.  The
+ * increment starts from them when the residual of their physical stresses is
+ * below guess_accept times that of the plain guess (the previous
+ * velocities), else from the plain guess; wall normal velocities are reset
+ * to their prescribed values either way; the stopping rule is unchanged
+ * (its normaliser is that of the plain guess).  Used once.  EP_EINVAL on a
+ * NULL array. */
+int ep_set_guess(ep_handle* h, const double* vx, const double* vy, const double* vz);
+
 /* Residual history of the last ep_load_step: for each check, the normalised
  * residual (resid / ref) and the precision of the sweeps that produced it
  * (EP_FP64 or EP_FP32_FIELDS).  Copies at most cap entries; returns the

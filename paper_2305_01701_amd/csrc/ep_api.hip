@@ -119,7 +119,7 @@ size_t carve(const ep_params* p, ep_handle* h, char* base)
     q = fp32 ? take(b32) : nullptr; if (h) h->coh32 = (float*)q;
     q = fp32 ? take(b32) : nullptr; if (h) h->lam32 = (float*)q;
     for (int d = 0; d < 3; ++d) {
-        q = p->ndim == 3 ? take(b64) : nullptr;
+        q = d < p->ndim ? take(b64) : nullptr;
         if (h) h->vguess64[d] = (double*)q;
     }
     if (p->ndim == 2) {
@@ -469,7 +469,9 @@ int step_start(ep_handle* h, const double red[RED_N])
         // a supplied guess replaces the plain one when its physical stresses
         // balance better; the normaliser stays that of the plain guess
         h->guess_ready = false;
-        for (int d = 0; d < h->ndim; ++d) launch_copy(h->it64[h->cur64][F_VX + d], h->vguess64[d], h->nelem, h->st);
+        double** it = h->it64[h->cur64];
+        for (int d = 0; d < h->ndim; ++d) launch_copy(it[F_VX + d], h->vguess64[d], h->nelem, h->st);
+        launch_set_walls(h->g, it[F_VX], it[F_VY], it[F_VZ], h->prm.erate, h->prm.lx, h->prm.ly, h->prm.lz, h->st);
         launch_reset_red(h->red, h->st);
         launch_sweep<double>(h, true, h->cur64, MODE_PHYS);
         double rg[RED_N];
@@ -910,6 +912,20 @@ long ep_field_shape(const ep_handle* h, int field, int shape[3])
         shape[2] = r.ext[2];
     }
     return (long)r.ext[0] * r.ext[1] * r.ext[2];
+}
+
+int ep_set_guess(ep_handle* h, const double* vx, const double* vy, const double* vz)
+{
+    if (!h || !vx || !vy || (h->ndim == 3 && !vz)) return EP_EINVAL;
+    const double* src[3] = {vx, vy, vz};
+    const int nz1 = h->ndim == 3 ? h->nz : 1;
+    int rc;
+    for (int d = 0; d < h->ndim; ++d) {
+        const int ext[3] = {h->nx + (d == 0), h->ny + (d == 1), nz1 + (d == 2)};
+        if ((rc = upload(h, h->vguess64[d], src[d], ext))) return rc;
+    }
+    h->guess_ready = true;
+    return EP_OK;
 }
 
 int ep_fields(ep_handle* h, int field, int dir, double* host, size_t count)

@@ -34,7 +34,7 @@ FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
 # every symbol include/ep.h declares
 SYMBOLS = ["ep_abi_version", "ep_workspace_size", "ep_init", "ep_load_step", "ep_sweep",
            "ep_residual", "ep_fields", "ep_field_shape", "ep_destroy", "ep_last_error",
-           "ep_enable_timing", "ep_sweep_timing", "ep_step_history",
+           "ep_enable_timing", "ep_sweep_timing", "ep_step_history", "ep_set_guess",
            "ep_batch_workspace_size", "ep_batch_init", "ep_batch_tune", "ep_batch_tile_shape",
            "ep_batch_load_step", "ep_batch_model", "ep_batch_enable_timing", "ep_batch_timing",
            "ep_batch_destroy", "ep_batch_last_error",
@@ -109,6 +109,7 @@ def lib():
         L.ep_enable_timing.argtypes = [vp, C.c_int]
         L.ep_sweep_timing.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_long)]
         L.ep_step_history.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_int]
+        L.ep_set_guess.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.ep_batch_workspace_size.argtypes = [C.c_int, C.POINTER(ep_params), C.POINTER(C.c_size_t)]
         L.ep_batch_init.argtypes = [C.c_int, C.POINTER(ep_params), C.POINTER(C.POINTER(C.c_double)), vp,
                                     C.c_size_t, vp, C.POINTER(vp)]
@@ -332,6 +333,12 @@ class ModelView:
     def fields(self, names=None) -> Dict[str, np.ndarray]:
         names = names or [n for n in FIELDS if self.size(n) > 0]
         return {n: self.get(n) for n in names}
+
+    def set_guess(self, vx, vy, vz=None) -> None:
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (vx, vy)]
+        arrs.append(None if vz is None else np.ascontiguousarray(vz, dtype=np.float64))
+        ptr = lambda a: None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+        self._check(lib().ep_set_guess(self.h, ptr(arrs[0]), ptr(arrs[1]), ptr(arrs[2])), "ep_set_guess")
 
 
 class Solver(ModelView):

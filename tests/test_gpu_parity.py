@@ -295,3 +295,49 @@ def test_c3_full_size_sweep_matches_oracle(prec):
     o.close()
     compare(m, got, ref, IT3, 1e-11 if prec == FP64 else 2e-5, "c3 sweep")
     assert rg == pytest.approx(ro, rel=1e-9 if prec == FP64 else 1e-3)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_supplied_guess(ndim):
+    """ep_set_guess: the converged velocities of an increment as its guess
+    converge at the first check to the same state; a poor guess is rejected
+    and the increment is then bitwise the plain one."""
+    if ndim == 2:
+        m = offcentre(c1_small_2d().with_(n_check=10, dt=2e-4))
+        names = ["vx", "vy"]
+    else:
+        m = Model(ndim=3, nx=17, ny=15, nz=13, dt=2e-4, tol=1e-8, n_check=10, incl_radius=0.25,
+                  incl_centre=(0.04, -0.03, 0.02))
+        names = ["vx", "vy", "vz"]
+    say("supplied guess", ndim)
+    a, b, c = solver(m), solver(m), solver(m)
+    for _ in range(3):
+        for s in (a, b, c):
+            assert s.load_step()["status"] == 0
+    sa = a.load_step()                       # a plastic increment, plain
+    assert sa["iters"] > 10
+    good = [a.get(k) for k in names]
+    b.set_guess(*good)
+    sb = b.load_step()
+    assert sb["status"] == 0 and sb["guess_used"] == 1 and sb["iters"] < sa["iters"]
+    # the physical stresses of the converged velocities do not balance exactly
+    # in yielding cells (the PT fixed point's Lambda mixes the averaged shear
+    # points), but far better than those of the previous velocities
+    assert sb["r_guess"] < 0.5 * sb["r_ref"]
+    fa = a.fields(it_names(m))
+    if ndim == 3:
+        compare(m, b.fields(it_names(m)), fa, it_names(m), 1e-6)
+    else:
+        # this 2D plastic increment has more than one converged state (started
+        # from the guess's physical stresses the iteration settles in another
+        # one): check that the state is a converged one
+        assert b.residual()["resid"] <= 10 * m.tol * sb["ref"]
+        assert sb["max_violation"] <= 2 * max(sa["max_violation"], 1e-9)
+    r = np.random.Generator(np.random.PCG64(3))
+    poor = [g + r.standard_normal(g.shape) * 0.1 for g in good]
+    c.set_guess(*poor)
+    sc = c.load_step()
+    assert sc["guess_used"] == 0 and sc["iters"] == sa["iters"]
+    fc = c.fields(it_names(m))
+    for k in it_names(m):
+        assert np.array_equal(fc[k], fa[k]), k
