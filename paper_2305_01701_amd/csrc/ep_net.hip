@@ -11,8 +11,9 @@
 // the reduction runs over 27 taps x input channels.  One wave computes 64
 // voxels (4 MFMA row blocks of 16) x all output channels with
 // v_mfma_f32_16x16x16_bf16: the A operand of a lane is 4 consecutive input
-// channels of one voxel (one 8-byte load), the B operand 4 consecutive input
-// channels of one output channel's weights.  The gradient with respect to
+// channels of one voxel (read from an LDS copy of the block's input with
+// halo), the B operand 4 consecutive input channels of one output channel's
+// weights.  The gradient with respect to
 // the input is the same kernel on the output gradient with the weights
 // transposed (input <-> output channels) and the taps mirrored.  The weight
 // gradient reduces over voxels: a workgroup stages 64 voxels of the output
@@ -111,67 +112,92 @@ enum { EPI_RELU = 0, EPI_LIN = 1, EPI_MASK = 2, EPI_F32 = 3 };
 
 // Y[v][c] = epilogue(b[c] + sum_t sum_i X[v + off_t][i] W[c][t][i]) for the
 // NB*16 output channels.  EPI_F32 writes an unpadded FP32 [V][16] array.
+// A workgroup computes a 4 (z) x 4 (y) x 16 (x) block of output voxels; wave w
+// takes the z-slice w, its 4 MFMA row blocks are the 4 y-rows of 16 voxels.
+// The input block with its one-voxel halo (6 x 6 x 18 voxels) is staged in
+// LDS 32 input channels at a time (rows of 40 bf16: 16-byte aligned, and 16
+// lanes reading 16 consecutive voxels hit distinct banks) and serves all 27
+// taps; the weights come through the L1/L2 caches.
+constexpr int CB_X = 16, CB_Y = 4, CB_Z = 4;
+constexpr int CT_X = CB_X + 2, CT_Y = CB_Y + 2, CT_Z = CB_Z + 2, CT_N = CT_X * CT_Y * CT_Z;
+constexpr int CT_ROW = 40;
+
 template <int NB, int EPI>
 __global__ __launch_bounds__(256) void k_conv(const bf16_t* __restrict__ X, int cin, const bf16_t* __restrict__ Wt,
                                               const float* __restrict__ bias, void* __restrict__ Y,
                                               const bf16_t* __restrict__ M, Vol g)
 {
     constexpr int CO = NB * 16;
+    __shared__ __attribute__((aligned(16))) bf16_t tile[CT_N * CT_ROW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, kq = lane >> 4;
-    const long vbase = ((long)blockIdx.x * 4 + wave) * 64;
-    if (vbase >= g.V) return;
-    long pa[4];
-    bool va[4];
-#pragma unroll
-    for (int mb = 0; mb < 4; ++mb) {
-        const long v = vbase + mb * 16 + r;
-        va[mb] = v < g.V;
-        pa[mb] = va[mb] ? pidx(g, v) : 0;
-    }
+    const int x0 = blockIdx.x * CB_X, y0 = blockIdx.y * CB_Y, z0 = blockIdx.z * CB_Z;
     f4 acc[4][NB];
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f4{0.f, 0.f, 0.f, 0.f};
-    const s4 zero = {0, 0, 0, 0};
-    for (int t = 0; t < 27; ++t) {
-        const long off = tap_off(g, t);
-        for (int c0 = 0; c0 < cin; c0 += 16) {
-            s4 a[4];
-#pragma unroll
-            for (int mb = 0; mb < 4; ++mb)
-                a[mb] = va[mb] ? *(const s4*)(X + (pa[mb] + off) * cin + c0 + kq * 4) : zero;
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                const s4 b = *(const s4*)(Wt + ((long)(nb * 16 + r) * 27 + t) * cin + c0 + kq * 4);
-#pragma unroll
-                for (int mb = 0; mb < 4; ++mb)
-                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mb], b, acc[mb][nb], 0, 0, 0);
-            }
+    for (int c0 = 0; c0 < cin; c0 += 32) {
+        const int kc = cin - c0 < 32 ? cin - c0 : 32;    // 16 or 32 channels in this chunk
+        const int nq = kc / 8;                            // 16-byte pieces per voxel
+        __syncthreads();
+        for (int e = threadIdx.x; e < CT_N * nq; e += 256) {
+            const int tv = e / nq, q = e % nq;
+            const int tx = tv % CT_X, ty = (tv / CT_X) % CT_Y, tz = tv / (CT_X * CT_Y);
+            // padded coordinates of the tile voxel (the halo starts at the border)
+            const int px = x0 + tx, py = y0 + ty, pz = z0 + tz;
+            uint4 val = {0u, 0u, 0u, 0u};
+            if (px < g.Wp && py < g.Hp && pz < g.D + 2)
+                val = *(const uint4*)(X + (((long)pz * g.Hp + py) * g.Wp + px) * cin + c0 + q * 8);
+            *(uint4*)(tile + tv * CT_ROW + q * 8) = val;
         }
-    }
-    // lane holds rows kq*4 + i (voxels) of column r (output channel)
+        __syncthreads();
+        for (int t = 0; t < 27; ++t) {
+            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;     // 0..2: tap offset + 1
+            for (int cs = 0; cs < kc; cs += 16) {
+                s4 a[4];
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
+                for (int mb = 0; mb < 4; ++mb) {
+                    const int tv = ((wave + dz) * CT_Y + (mb + dy)) * CT_X + (r + dx);
+                    a[mb] = *(const s4*)(tile + tv * CT_ROW + cs + kq * 4);
+                }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const long v = vbase + mb * 16 + kq * 4 + i;
-            if (v >= g.V) continue;
-            const long p = pidx(g, v);
+                for (int nb = 0; nb < NB; ++nb) {
+                    const s4 bw = *(const s4*)(Wt + ((long)(nb * 16 + r) * 27 + t) * cin + c0 + cs + kq * 4);
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                const int c = nb * 16 + r;
-                float z = acc[mb][nb][i] + (bias ? bias[c] : 0.f);
-                if (EPI == EPI_F32) {
-                    ((float*)Y)[v * CO + c] = z;
-                } else {
-                    if (EPI == EPI_RELU) z = fmaxf(z, 0.f);
-                    if (EPI == EPI_MASK) z = bf2f(M[p * CO + c]) > 0.f ? z : 0.f;
-                    ((bf16_t*)Y)[p * CO + c] = f2bf(z);
+                    for (int mb = 0; mb < 4; ++mb)
+                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mb], bw, acc[mb][nb], 0, 0, 0);
                 }
             }
         }
+    }
+    // lane holds rows kq*4 + i (x within the row block) of column r (output channel)
+    const int z = z0 + wave;
+    if (z >= g.D) return;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+        const int y = y0 + mb;
+        if (y >= g.H) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int x = x0 + kq * 4 + i;
+            if (x >= g.W) continue;
+            const long v = ((long)z * g.H + y) * g.W + x;
+            const long p = ((long)(z + 1) * g.Hp + (y + 1)) * g.Wp + (x + 1);
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int c = nb * 16 + r;
+                float zz = acc[mb][nb][i] + (bias ? bias[c] : 0.f);
+                if (EPI == EPI_F32) {
+                    ((float*)Y)[v * CO + c] = zz;
+                } else {
+                    if (EPI == EPI_RELU) zz = fmaxf(zz, 0.f);
+                    if (EPI == EPI_MASK) zz = bf2f(M[p * CO + c]) > 0.f ? zz : 0.f;
+                    ((bf16_t*)Y)[p * CO + c] = f2bf(zz);
+                }
+            }
+        }
+    }
 }
 
 // dW[o][t][i] += sum over voxels of G[v][o] X[v + off_t][i] (one tap per
@@ -628,7 +654,7 @@ template <int EPI>
 void conv_epi(int nb, const bf16_t* X, int cin, const bf16_t* W, const float* b, void* Y, const bf16_t* M,
               const Vol& g, hipStream_t s)
 {
-    const unsigned grid = nblk(g.V, 256);
+    const dim3 grid((g.W + CB_X - 1) / CB_X, (g.H + CB_Y - 1) / CB_Y, (g.D + CB_Z - 1) / CB_Z);
     switch (nb) {
     case 1: k_conv<1, EPI><<<grid, 256, 0, s>>>(X, cin, W, b, Y, M, g); break;
     case 2: k_conv<2, EPI><<<grid, 256, 0, s>>>(X, cin, W, b, Y, M, g); break;
