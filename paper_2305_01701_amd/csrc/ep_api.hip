@@ -497,7 +497,7 @@ int step_start(ep_handle* h, const double red[RED_N])
     h->hist_p.clear();
 
     c.tol_abs = h->prm.tol * st->ref;
-    c.sw = (h->prm.fp32_switch > 0 ? h->prm.fp32_switch : 10.0 * h->prm.tol) * st->ref;
+    c.sw = (h->prm.fp32_switch > 0 ? h->prm.fp32_switch : 2.0 * h->prm.tol) * st->ref;
     c.use32 = h->fp32;
     if (c.use32) ensure_it32(h);
     const int nmax = std::max(h->nx, std::max(h->ny, h->nz));
@@ -525,9 +525,10 @@ bool step_check(ep_handle* h, const double red[RED_N], int nb)
     } else if (c.use32) {
         // FP32 rounding of the stresses bounds what an FP32 sweep can
         // resolve: about 8 u32 max|sigma| / h in residual units (measured on
-        // a converged 3D plastic increment: 2-3 times that).  Above it FP32
-        // keeps iterating, also through plateaus where the yielding zone
-        // reorganises; close to it, FP64 sweeps take over.
+        // a converged 3D plastic increment: 2-3 times that).  Above 3 times
+        // it FP32 keeps iterating, also through plateaus where the yielding
+        // zone reorganises; there, or within 2x of the tolerance, or after a
+        // long stall within 6x of it, FP64 sweeps take over.
         const double floor32 = 8.0 * 5.96e-8 * red[RED_SMAX] / h->h;
         if (c.resid < 0.5 * c.best) {
             c.best = c.resid;
@@ -535,8 +536,8 @@ bool step_check(ep_handle* h, const double red[RED_N], int nb)
         } else {
             ++c.since_best;
         }
-        const bool near_floor = c.resid <= 20.0 * floor32;
-        if (c.resid <= std::max(c.sw, 10.0 * floor32) || (near_floor && c.since_best >= c.stall_checks)) {
+        const bool near_floor = c.resid <= 6.0 * floor32;
+        if (c.resid <= std::max(c.sw, 3.0 * floor32) || (near_floor && c.since_best >= c.stall_checks)) {
             ensure_it64(h);          // continue from the FP32 state in FP64
             c.use32 = false;
             st->fp32_exit = c.resid / st->ref;
