@@ -86,8 +86,7 @@ typedef struct ep_params {
     int    freeze_iter;      /* frozen plasticity (accelerated PT section): 0 off; else an
                                 increment not converged at the first check at or after this
                                 iteration continues with the plastic multiplier Lambda of
-                                the next sweep held fixed at every cell (a linear problem).
-                                2D with the fused sweep only (EP_EINVAL otherwise) */
+                                the next sweep held fixed at every cell (a linear problem) */
     double guess_accept;     /* a supplied starting guess (ep_net_predict) is used when the
                                 residual of its physical stresses is below guess_accept times
                                 that of the plain guess (0: 1, i.e. only when lower).  The PT

@@ -60,7 +60,6 @@ int validate(const ep_params* p)
     if (p->precision != EP_FP64 && p->precision != EP_FP32_FIELDS) return EP_EINVAL;
     if (p->sweep < EP_SWEEP_AUTO || p->sweep > EP_SWEEP_UNFUSED) return EP_EINVAL;
     if (p->freeze_iter < 0 || p->guess_accept < 0) return EP_EINVAL;
-    if (p->freeze_iter > 0 && (p->ndim != 2 || p->sweep == EP_SWEEP_UNFUSED)) return EP_EINVAL;
     return EP_OK;
 }
 
@@ -261,6 +260,7 @@ void launch_sweep(const ep_handle* h, bool physical, int from, int mode, int lam
     SweepArgs<R> a;
     if constexpr (sizeof(R) == 4) a = args32(h, from);
     else a = args64(h, physical, from);
+    a.lam_mode = lam_mode;
     if (h->ndim == 2) {
         launch_sweep_unfused_2d<R>(a, mode, h->st);
     } else {

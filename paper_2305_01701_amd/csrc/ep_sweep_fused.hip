@@ -241,13 +241,22 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, TileSet ts
                 R Tyzb = R(0.25) * (s_Tyz[sc][q] + s_Tyz[sc][q + W] + s_Tyz[sc1][q] + s_Tyz[sc1][q + W]);
                 R J2 = R(0.5) * (Txx * Txx + Tyy * Tyy + Tzz * Tzz) + Txyb * Txyb + Txzb * Txzb + Tyzb * Tyzb;
                 R lam;
-                const R sc_ = return_scale(J2, D, a.invD, pn, cc[u], a.A, a.B, lam);
+                R sc_ = return_scale(J2, D, a.invD, pn, cc[u], a.A, a.B, lam);
+                const bool own = la >= 2 && la < TX + 2 && lbb >= 2 && lbb < TY + 2 && c >= k0 && c < k1;
+                if (a.lam_mode != LAM_COMPUTE) {                 // frozen plasticity
+                    const long ec = i + sy * j + sz * c;
+                    if (a.lam_mode == LAM_FROZEN) {
+                        lam = a.lam[ec];
+                        sc_ = R(1) / (D + lam);
+                    } else if (own) {
+                        a.lam[ec] = lam;
+                    }
+                }
                 R txx = Txx * sc_, tyy = Tyy * sc_;
                 s_lam[sc][q] = lam;
                 s_p[sc][q] = pn;
                 s_sxx[sc][q] = txx;
                 s_syy[sc][q] = tyy;
-                const bool own = la >= 2 && la < TX + 2 && lbb >= 2 && lbb < TY + 2 && c >= k0 && c < k1;
                 if (own) {
                     const long e = i + sy * j + sz * c;
                     a.nx_[F_P][e] = pn;

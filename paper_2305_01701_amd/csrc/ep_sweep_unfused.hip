@@ -53,11 +53,12 @@ __global__ __launch_bounds__(NT) void k_centre_2d(SweepArgs<R> a)
         R J2 = R(0.5) * (Txx * Txx + Tyy * Tyy) + Tb * Tb;
         R ld, tii, Y;
         R lam = centre_lambda(J2, a.D, pn, a.coh[c], a.A, a.B, ld, tii, Y);
+        if (a.lam_mode == LAM_FROZEN) lam = a.lam[c];    // frozen plasticity: Lambda held fixed
+        else a.lam[c] = lam;                             // read by the shear-point kernel
         R txx = Txx / (a.D + lam), tyy = Tyy / (a.D + lam);
         a.nx_[F_P][c] = pn;
         a.nx_[F_TXX][c] = txx;
         a.nx_[F_TYY][c] = tyy;
-        a.lam[c] = lam;
         if (MODE == MODE_CHECK) {
             R dp = fabs(pn - a.it[F_P][c]) * a.rK;
             R dt = nmax(fabs(txx - a.it[F_TXX][c]), fabs(tyy - a.it[F_TYY][c])) * a.rG;
@@ -185,11 +186,12 @@ __global__ __launch_bounds__(NT) void k_centre_3d(SweepArgs<R> a)
         R J2 = R(0.5) * (Txx * Txx + Tyy * Tyy + Tzz * Tzz) + Txy * Txy + Txz * Txz + Tyz * Tyz;
         R ld, tii, Y;
         R lam = centre_lambda(J2, a.D, pn, a.coh[c], a.A, a.B, ld, tii, Y);
+        if (a.lam_mode == LAM_FROZEN) lam = a.lam[c];    // frozen plasticity: Lambda held fixed
+        else a.lam[c] = lam;                             // read by the shear-point kernel
         R txx = Txx / (a.D + lam), tyy = Tyy / (a.D + lam);
         a.nx_[F_P][c] = pn;
         a.nx_[F_TXX][c] = txx;
         a.nx_[F_TYY][c] = tyy;
-        a.lam[c] = lam;
         if (MODE == MODE_CHECK) {
             R dp = fabs(pn - a.it[F_P][c]) * a.rK;
             R dtx = fabs(txx - a.it[F_TXX][c]), dty = fabs(tyy - a.it[F_TYY][c]);

@@ -123,10 +123,8 @@ def test_batch_init_rejects_small_workspace(E):
 
 
 @pytest.mark.parametrize("case", ["3d", "unfused"])
-def test_freeze_needs_the_2d_tile_sweep(E, case):
+def test_freeze_accepted_in_every_sweep_form(E, case):
     m = (c3_3d(7) if case == "3d" else c1_small_2d()).with_(freeze_iter=100)
     p = E.params_from_model(m, sweep=E.EP_SWEEP_UNFUSED if case == "unfused" else E.EP_SWEEP_AUTO)
     n = C.c_size_t(0)
-    assert E.lib().ep_workspace_size(C.byref(p), C.byref(n)) == E.EP_EINVAL
-    p.freeze_iter = 0
     assert E.lib().ep_workspace_size(C.byref(p), C.byref(n)) == E.EP_OK
