@@ -45,7 +45,8 @@ def workload(name):
     if name == "2d-1023":
         return c2_2d(0), "2d-1023^2 pure shear, circular weak inclusion r=0.1L offset from seed 0, tol 1e-6"
     if name == "3d-511":
-        return c5_3d(), "3d-511^3 pure shear, spherical weak inclusion, strain increment 5e-5, tol 1e-6"
+        return c5_3d(), ("3d-511^3 pure shear, spherical weak inclusion, strain increment 5e-5, tol 1e-6, "
+                         "frozen plasticity after 16 nx iterations")
     if name == "batch-2d-256":
         return None, ("256 independent 2D pure-shear models, sizes uniform in {127,255,383,511}^2, "
                       "phi U[20,40], c0 U[1e-3,3e-3], inclusion radius U[0.05,0.15] at seeded positions, "

@@ -111,7 +111,8 @@ def c3_3d(n: int = 255, bulk: float = 2.0) -> Model:
 
 
 def c5_3d() -> Model:
-    return Model(ndim=3, nx=511, ny=511, nz=511, dt=5e-5, tol=1e-6, steps=100,
+    # more than 10^6 cells: frozen plasticity after 16 nx iterations
+    return Model(ndim=3, nx=511, ny=511, nz=511, dt=5e-5, tol=1e-6, steps=100, freeze_iter=16 * 511,
                  name="3d-511^3")
 
 
