@@ -182,16 +182,13 @@ def net_flops_per_voxel(base):
     return 2 * 27 * (l0 + l1 / 8 + l2 / 64)
 
 
-def run_warm(args, E, name):
+def warm_compare(E, base_model, T, t_from, prec, steps_train=1200):
     """Plain vs learned warm start on a 3D model: the network is trained on
     trajectories of two models with other inclusion positions, then the
-    held-out model is solved both ways."""
+    held-out model is solved both ways.  Returns the per-increment results."""
     import numpy as np
     import torch
-    base_model, desc = workload(name)
     n = base_model.nx
-    T = args.warmup + args.steps
-    prec = E.EP_FP32_FIELDS if args.precision == "fp32" else E.EP_FP64
     mk = lambda c: base_model.with_(incl_centre=c, max_iter=2_000_000)
     train_models = [mk((0.06, -0.04, 0.03)), mk((-0.05, 0.05, -0.02))]
     held = mk((0.02, 0.03, -0.04))
@@ -224,7 +221,6 @@ def run_warm(args, E, name):
         s.close()
         log(f"training trajectory {q + 1}/{len(train_models)} generated ({time.perf_counter() - t0:.1f}s)")
     t1 = time.perf_counter()
-    steps_train = 1200
     losses = net.train(slots, steps_train, lr=3e-4)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t1
@@ -256,30 +252,48 @@ def run_warm(args, E, name):
 
     ip, sp, _, _ = solve(False)
     iw, sw, used, pred = solve(True)
-    timed = slice(args.warmup, T)
-    cells = held.n_cells
-    log(f"plain iters {ip}\nwarm  iters {iw}\nguess used {used}")
+    net.close()
+    log(f"plain iters {ip}")
+    log(f"warm  iters {iw}, guess used {used}")
+    timed = slice(t_from, T)
+    steps = T - t_from
     pred_ms = 1e3 * sum(pred) / len(pred)
     flops = net_flops_per_voxel(32) * net.nvox
-    achieved = flops / (pred_ms * 1e-3) / 1e12
-    it_w, s_w = sum(iw[timed]), sum(sw[timed])
-    value = it_w * cells * bytes_per_cell(3, 4 if prec else 8) / s_w / 1e9
+    return {
+        "grid": f"{n}^3", "increments_timed": f"{t_from + 1}..{T}", "cells": held.n_cells,
+        "plain": {"iters_per_step": sum(ip[timed]) / steps, "s_per_step": round(sum(sp[timed]) / steps, 4)},
+        "warm": {"iters_per_step": sum(iw[timed]) / steps, "s_per_step": round(sum(sw[timed]) / steps, 4),
+                 "guesses_used": sum(1 for u in used[timed] if u == 1)},
+        "training": {"samples": len(slots), "adam_steps": steps_train, "seconds": round(train_s, 2),
+                     "loss_first": float(losses[:len(slots)].mean()), "loss_last": float(losses[-len(slots):].mean())},
+        "inference": {"ms": round(pred_ms, 3), "flops": flops,
+                      "tflops": round(flops / (pred_ms * 1e-3) / 1e12, 2)},
+        "_iters_warm": iw, "_secs_warm": sw,
+    }
+
+
+def run_warm(args, E, name):
+    """The warm-start workload: plain vs learned guess at the named size."""
+    base_model, desc = workload(name)
+    T = args.warmup + args.steps
+    prec = E.EP_FP32_FIELDS if args.precision == "fp32" else E.EP_FP64
+    w = warm_compare(E, base_model, T, args.warmup, prec)
+    timed = slice(args.warmup, T)
+    it_w, s_w = sum(w.pop("_iters_warm")[timed]), sum(w.pop("_secs_warm")[timed])
+    value = it_w * w["cells"] * bytes_per_cell(3, 4 if prec else 8) / s_w / 1e9
+    inf = w["inference"]
     return {
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(s_w / args.steps * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if prec == E.EP_FP32_FIELDS else "f64", "data": "synthetic",
-        "config": {"workload": desc, "cells": cells, "increments_timed": f"{args.warmup + 1}..{T}",
+        "config": {"workload": desc, "cells": w["cells"], "increments_timed": w["increments_timed"],
                    "precision": args.precision},
-        "plain": {"iters_per_step": sum(ip[timed]) / args.steps, "s_per_step": round(sum(sp[timed]) / args.steps, 4)},
-        "warm": {"iters_per_step": it_w / args.steps, "s_per_step": round(s_w / args.steps, 4),
-                 "guesses_used": sum(1 for u in used[timed] if u == 1)},
-        "training": {"samples": len(slots), "adam_steps": steps_train, "seconds": round(train_s, 2),
-                     "loss_first": float(losses[:len(slots)].mean()), "loss_last": float(losses[-len(slots):].mean())},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": 2500.0, "unit": "TFLOP/s",
-                     "frac": round(achieved / 2500.0, 5), "traffic": None,
+        "plain": w["plain"], "warm": w["warm"], "training": w["training"],
+        "roofline": {"bound": "mfma", "achieved": inf["tflops"], "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": round(inf["tflops"] / 2500.0, 5), "traffic": None,
                      "kernel": "warm-start network inference (bf16 MFMA convolutions)",
-                     "flops_per_inference": flops, "avg_inference_ms": round(pred_ms, 3)},
+                     "flops_per_inference": inf["flops"], "avg_inference_ms": inf["ms"]},
         "cpu_baseline": None,
     }
 
@@ -294,6 +308,8 @@ def main():
     ap.add_argument("--sweep", default="auto", choices=["auto", "fused", "unfused"])
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-warm-compare", action="store_true",
+                    help="skip the small plain vs learned-warm-start comparison of 3D workloads")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -360,6 +376,14 @@ def main():
         log("cpu baseline (oracle) ...")
         cpu = cpu_baseline(m, args.cpu_budget)
         log("cpu baseline", cpu)
+    warm = None
+    if not args.no_warm_compare and m.ndim == 3:
+        # plain vs learned warm start on a 63^3 version of the same workload
+        # (outside the timed region)
+        log("warm-start comparison at 63^3 ...")
+        from ep_workloads import c3_3d
+        warm = warm_compare(E, c3_3d(63).with_(bulk=m.bulk), 13, 10, prec, steps_train=600)
+        warm.pop("_iters_warm"), warm.pop("_secs_warm")
 
     iters = it32 + it64
     out = {
@@ -375,7 +399,7 @@ def main():
         "iters_per_step": round(iters / max(args.steps, 1), 1),
         "iters_fp32_per_step": round(it32 / max(args.steps, 1), 1),
         "failed_steps": sum(1 for st in stats if st["status"] != 0),
-        "roofline": roof, "cpu_baseline": cpu,
+        "roofline": roof, "cpu_baseline": cpu, "warm_start": warm,
     }
     print(json.dumps(out), flush=True)
 
