@@ -79,10 +79,11 @@ typedef struct ep_params {
     int    precision;        /* EP_FP64 or EP_FP32_FIELDS */
     int    sweep;            /* EP_SWEEP_* */
     double fp32_switch;      /* FP32 mode: leave FP32 when the normalised residual is
-                                below this (0: 2 * tol), or within 3x of the FP32
+                                below this (0: 2 * tol), or within 3x (3D) or 10x (2D) of the FP32
                                 rounding floor 8 u32 max|sigma| / h, ... */
-    int    fp32_stall;       /* ... or, within 6x of that floor, has not halved for
-                                this many checks (0: 16 max(nx,ny,nz) / n_check; < 0: never) */
+    int    fp32_stall;       /* ... or, within 20x of that floor, has not halved for
+                                this many checks (or for 4x as many anywhere)
+                                (0: 16 max(nx,ny,nz) / n_check; < 0: never) */
     int    freeze_iter;      /* frozen plasticity (accelerated PT section): 0 off; else an
                                 increment not converged at the first check at or after this
                                 iteration continues with the plastic multiplier Lambda of

@@ -524,20 +524,25 @@ bool step_check(ep_handle* h, const double red[RED_N], int nb)
         c.running = false;
     } else if (c.use32) {
         // FP32 rounding of the stresses bounds what an FP32 sweep can
-        // resolve: about 8 u32 max|sigma| / h in residual units (measured on
-        // a converged 3D plastic increment: 2-3 times that).  Above 3 times
-        // it FP32 keeps iterating, also through plateaus where the yielding
-        // zone reorganises; there, or within 2x of the tolerance, or after a
-        // long stall within 6x of it, FP64 sweeps take over.
+        // resolve: about 8 u32 max|sigma| / h in residual units (measured:
+        // 2-3 times that on a converged 3D plastic increment, up to ~10
+        // times on frozen 2D increments).  Above that multiple (3 in 3D, 10
+        // in 2D) FP32 keeps iterating, also through plateaus where the
+        // yielding zone reorganises; there, or within 2x of the tolerance,
+        // or after a stall within 20x of the floor, or after a 4x longer
+        // stall anywhere, FP64 sweeps take over.
         const double floor32 = 8.0 * 5.96e-8 * red[RED_SMAX] / h->h;
+        const double at_floor = (h->ndim == 3 ? 3.0 : 10.0) * floor32;
         if (c.resid < 0.5 * c.best) {
             c.best = c.resid;
             c.since_best = 0;
         } else {
             ++c.since_best;
         }
-        const bool near_floor = c.resid <= 6.0 * floor32;
-        if (c.resid <= std::max(c.sw, 3.0 * floor32) || (near_floor && c.since_best >= c.stall_checks)) {
+        const bool near_floor = c.resid <= 20.0 * floor32;
+        const bool stalled = c.since_best >= c.stall_checks;
+        if (c.resid <= std::max(c.sw, at_floor) || (near_floor && stalled) ||
+            c.since_best / 4 >= c.stall_checks) {
             ensure_it64(h);          // continue from the FP32 state in FP64
             c.use32 = false;
             st->fp32_exit = c.resid / st->ref;

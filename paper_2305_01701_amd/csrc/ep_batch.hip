@@ -5,8 +5,8 @@
 // so prologue, precision conversions, epilogue and field I/O are the
 // single-model code.  What is shared is the PT iteration: a graph of n_check
 // sweeps (a reduction reset, then per sweep one persistent launch per
-// precision and tile shape, the last sweep with the residual check) is
-// captured once and replayed; each launch walks a device tile list of the
+// precision and tile shape in use, the last sweep with the residual check)
+// is captured on first use and replayed; each launch walks a device tile list of the
 // models still iterating in that precision.  After a replay the host reads
 // every model's residual in one copy, applies the single-model convergence
 // logic per model, and retires or re-files the models whose state changed by
@@ -53,9 +53,9 @@ struct ep_batch {
     std::vector<unsigned long long> h_red;
     std::vector<double> h_cols;
     double cs32, cs64;                  // cell-sweeps of the current replay set-up
-    hipGraph_t graph;
-    hipGraphExec_t exec;
-    bool graph_ok;
+    // captured replays keyed by the set of non-empty tile lists (a precision
+    // whose lists are empty is not launched at all)
+    std::map<unsigned, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
     bool timing;
     hipEvent_t ev0, ev1;
     double t_ms, t_cs32, t_cs64;
@@ -213,45 +213,66 @@ bool shape_used(const ep_batch* b, int s)
     return false;
 }
 
-// nsw sweeps of every listed tile; the last one in CHECK mode when check is
-// set.  With alternate, the sweeps advance the iteration (ping-pong);
-// without, every sweep reads the current buffers and writes the other ones
-// (timing runs that leave the state unchanged).
-void enqueue_sweeps(ep_batch* b, int nsw, bool check, bool reset, bool alternate, hipStream_t s)
+// Bit q * BATCH_SHAPES + shape for every non-empty tile list (q: 0 FP64, 1 FP32).
+unsigned list_mask(const ep_batch* b)
+{
+    unsigned m = 0;
+    for (int q = 0; q < 2; ++q)
+        for (int sh = 0; sh < BATCH_SHAPES; ++sh)
+            if (b->h_cnt[q * BATCH_SHAPES + sh] > 0) m |= 1u << (q * BATCH_SHAPES + sh);
+    return m;
+}
+
+// nsw sweeps of every tile in the lists selected by mask; the last one in
+// CHECK mode when check is set.  With alternate, the sweeps advance the
+// iteration (ping-pong); without, every sweep reads the current buffers and
+// writes the other ones (timing runs that leave the state unchanged).
+void enqueue_sweeps(ep_batch* b, int nsw, bool check, bool reset, bool alternate, unsigned mask, hipStream_t s)
 {
     if (reset) launch_reset_red_n(b->red, b->n, s);
     for (int k = 0; k < nsw; ++k) {
         const int mode = (check && k == nsw - 1) ? MODE_CHECK : MODE_UPDATE;
         const int slot = !alternate ? 1 : k == 0 ? 0 : (k & 1) ? 2 : 1;
         for (int sh = 0; sh < BATCH_SHAPES; ++sh) {
-            if (!shape_used(b, sh)) continue;
-            if (b->fp32)
+            if (b->fp32 && (mask >> (BATCH_SHAPES + sh) & 1u))
                 launch_sweep_batch_2d<float>(sh, b->tab32 + slot * b->n, b->list[1][sh], b->cnt + BATCH_SHAPES + sh,
                                              mode, b->grid[1][sh], s);
-            launch_sweep_batch_2d<double>(sh, b->tab64 + slot * b->n, b->list[0][sh], b->cnt + sh, mode,
-                                          b->grid[0][sh], s);
+            if (mask >> sh & 1u)
+                launch_sweep_batch_2d<double>(sh, b->tab64 + slot * b->n, b->list[0][sh], b->cnt + sh, mode,
+                                              b->grid[0][sh], s);
         }
     }
 }
 
-int capture(ep_batch* b)
+void drop_graphs(ep_batch* b)
 {
-    if (b->graph_ok) {
-        (void)hipGraphExecDestroy(b->exec);
-        (void)hipGraphDestroy(b->graph);
-        b->graph_ok = false;
+    for (auto& g : b->graphs) {
+        (void)hipGraphExecDestroy(g.second.second);
+        (void)hipGraphDestroy(g.second.first);
+    }
+    b->graphs.clear();
+}
+
+// The replay of n_check sweeps for the lists in mask (captured on first use).
+int replay_for(ep_batch* b, unsigned mask, hipGraphExec_t* out)
+{
+    auto it = b->graphs.find(mask);
+    if (it != b->graphs.end()) {
+        *out = it->second.second;
+        return EP_OK;
     }
     BCHK(b, hipStreamBeginCapture(b->cs, hipStreamCaptureModeRelaxed));
-    enqueue_sweeps(b, b->n_check, true, true, true, b->cs);
+    enqueue_sweeps(b, b->n_check, true, true, true, mask, b->cs);
     hipGraph_t g = nullptr;
     BCHK(b, hipStreamEndCapture(b->cs, &g));
-    b->graph = g;
-    hipError_t e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-        (void)hipGraphDestroy(b->graph);
+        (void)hipGraphDestroy(g);
         return berr(b, EP_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
     }
-    b->graph_ok = true;
+    b->graphs[mask] = {g, ex};
+    *out = ex;
     return EP_OK;
 }
 
@@ -271,10 +292,7 @@ void model_red(const ep_batch* b, int i, double out[RED_N]) { decode_red(&b->h_r
 
 void destroy_batch(ep_batch* b)
 {
-    if (b->graph_ok) {
-        (void)hipGraphExecDestroy(b->exec);
-        (void)hipGraphDestroy(b->graph);
-    }
+    drop_graphs(b);
     for (ep_handle* h : b->m) handle_free(h);
     if (b->cs) (void)hipStreamDestroy(b->cs);
     if (b->ev0) (void)hipEventDestroy(b->ev0);
@@ -386,9 +404,10 @@ int ep_batch_tune(ep_batch* b, int reps)
         fill_lists(b, true);
         int rc = upload(b);
         if (rc) return rc;
-        enqueue_sweeps(b, 1, false, false, false, b->st);    // warm-up
+        const unsigned mask = list_mask(b);
+        enqueue_sweeps(b, 1, false, false, false, mask, b->st);    // warm-up
         BCHK(b, hipEventRecord(b->ev0, b->st));
-        enqueue_sweeps(b, reps, false, false, false, b->st);
+        enqueue_sweeps(b, reps, false, false, false, mask, b->st);
         BCHK(b, hipEventRecord(b->ev1, b->st));
         BCHK(b, hipEventSynchronize(b->ev1));
         BCHK(b, hipGetLastError());
@@ -417,11 +436,7 @@ int ep_batch_tune(ep_batch* b, int reps)
             for (int i : cl.second) b->shape[i] = best_s;
         }
     }
-    if (b->graph_ok) {                  // recaptured at the next load step
-        (void)hipGraphExecDestroy(b->exec);
-        (void)hipGraphDestroy(b->graph);
-        b->graph_ok = false;
-    }
+    drop_graphs(b);                     // recaptured for the new shapes when used
     return EP_OK;
 }
 
@@ -448,7 +463,6 @@ int ep_batch_load_step(ep_batch* b, ep_step_stats* st)
 {
     if (!b || !st) return EP_EINVAL;
     int rc;
-    if (!b->graph_ok && (rc = capture(b))) return rc;
     // prologue of every model, then one read of all reference residuals
     for (int i = 0; i < b->n; ++i) step_begin(b->m[i], &st[i]);
     if ((rc = read_all(b, false))) return rc;
@@ -471,7 +485,9 @@ int ep_batch_load_step(ep_batch* b, ep_step_stats* st)
             dirty = false;
         }
         if (b->timing) BCHK(b, hipEventRecord(b->ev0, b->st));
-        BCHK(b, hipGraphLaunch(b->exec, b->st));
+        hipGraphExec_t ex = nullptr;
+        if ((rc = replay_for(b, list_mask(b), &ex))) return rc;
+        BCHK(b, hipGraphLaunch(ex, b->st));
         if (b->timing) BCHK(b, hipEventRecord(b->ev1, b->st));
         if ((rc = read_all(b, false))) return rc;
         if (b->timing) {
