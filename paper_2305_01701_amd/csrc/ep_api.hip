@@ -225,6 +225,16 @@ SweepArgs<R> make_args(const ep_handle* h, R* const* from, R* const* to, R* cons
     a.eby = (R)(bg ? h->prm.erate[1] : 0.0);
     a.ebz = (R)(bg && h->ndim == 3 ? h->prm.erate[2] : 0.0);
     a.lam_mode = LAM_COMPUTE;
+    // the workspace takes the fields of a group one after the other, equal
+    // sizes, equal alignment: a uniform stride in 3D (checked here)
+    a.fs = 0;
+    if (h->ndim == 3) {
+        const long fs = from[1] - from[0];
+        bool ok = fs > 0;
+        for (int f = 0; f < F_NIT; ++f) ok = ok && from[f] == from[0] + f * fs && to[f] == to[0] + f * fs;
+        for (int f = 0; f < O_N; ++f) ok = ok && old[f] == old[0] + f * fs;
+        if (ok) a.fs = fs;
+    }
     return a;
 }
 
@@ -264,7 +274,7 @@ void launch_sweep(const ep_handle* h, bool physical, int from, int mode, int lam
     if (h->ndim == 2) {
         launch_sweep_unfused_2d<R>(a, mode, h->st);
     } else {
-        if (fused) launch_sweep_fused_3d<R>(a, mode, h->st);
+        if (fused && a.fs > 0) launch_sweep_fused_3d<R>(a, mode, h->st);
         else launch_sweep_unfused_3d<R>(a, mode, h->st);
     }
 }

@@ -45,6 +45,8 @@ struct SweepArgs {
     R ebx, eby, ebz;       // background strain rate subtracted from the stored velocities
                            // (FP32 fields store v - erate * x; 0 when v is stored in full)
     int lam_mode;          // 2D tile sweep: LAM_* (frozen plasticity)
+    long fs;               // 3D: element stride between consecutive fields of it, nx_ and old
+                           // (field f of a group = group[0] + f * fs; 0 when not uniform)
 };
 
 // Centre Lambda of the 2D tile sweep: from the return mapping; from the

@@ -44,10 +44,11 @@ struct TileSet {
 // ahead (velocities of plane f+1, edge stresses of level f+1 and plane f,
 // centre data of plane f), so that HBM latency overlaps the LDS work of the
 // current step.  Each thread owns the same plane positions in every step.
-template <typename R, int TX, int TY, int ZC, int MODE>
-__global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, TileSet ts)
+template <typename R, int TX, int TY, int ZC, int MODE, int NT, int WPE>
+__global__ __attribute__((amdgpu_flat_work_group_size(1, NT), amdgpu_waves_per_eu(WPE)))
+void k_fused_3d(SweepArgs<R> a, TileSet ts)
 {
-    constexpr int W = TX + 4, H = TY + 4, N = W * H, NT = TX * TY;
+    constexpr int W = TX + 4, H = TY + 4, N = W * H;
     constexpr int NQ = (N + NT - 1) / NT;                  // plane positions per thread
     constexpr int CW = TX + 2, CN = (TX + 2) * (TY + 2);   // centre region (1-cell halo)
     constexpr int NR = (CN + NT - 1) / NT;
@@ -66,36 +67,50 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, TileSet ts
     const int i0 = bx * TX, j0 = by * TY;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int k0 = bz * ZC, k1 = min(k0 + ZC, nz);
-    const long sy = a.sy, sz = a.sz;
+    const long sz = a.sz;
     const int tid = threadIdx.x;
     const int hx = (i0 + TX == nx) ? 1 : 0;     // owns the x = nx row when nx % TX == 0
     const int hy = (j0 + TY == ny) ? 1 : 0;
     const bool last_z = (k1 == nz);
 
-    const R *vx = a.it[F_VX], *vy = a.it[F_VY], *vz = a.it[F_VZ];
-    const R *txz_k = a.it[F_TXZ], *tyz_k = a.it[F_TYZ], *txy_k = a.it[F_TXY];
-    const R *txz_o = a.old[O_TXZ], *tyz_o = a.old[O_TYZ], *txy_o = a.old[O_TXY];
-    const R *p_k = a.it[F_P], *txx_k = a.it[F_TXX], *tyy_k = a.it[F_TYY];
-    const R *p_o = a.old[O_P], *txx_o = a.old[O_TXX], *tyy_o = a.old[O_TYY], *coh = a.coh;
+    // Fields are addressed from the first field of their group (iteration
+    // k, k+1, increment start) and the uniform field stride fs, and points
+    // as a uniform plane address plus a 32-bit in-plane byte offset: the
+    // loads and stores take a scalar base and one vector offset, and the 26
+    // field pointers need not stay in scalar registers.  fs is made opaque
+    // to the compiler once per march step so that the field addresses are
+    // formed where they are used rather than hoisted out of the loop and
+    // kept live (spilled) over it.
+    const R* const itb = a.it[0];
+    R* const nxb = a.nx_[0];
+    const R* const olb = a.old[0];
+    long fs = a.fs;
+    auto ld = [](const R* pl, unsigned o) -> R { return *(const R*)((const char*)pl + o); };
+    auto st = [](R* pl, unsigned o, R v) { *(R*)((char*)pl + o) = v; };
+    auto off = [&](int i, int j) -> unsigned { return (unsigned)(i + a.sy * j) * (unsigned)sizeof(R); };
     const R idx = a.idx, idy = a.idy, idz = a.idz, igt = a.igt, igd = a.igd, ikt = a.ikt, ikd = a.ikd;
     const R D = a.D;
 
     // per-thread positions: plane points q (S1, S2) and centre points r (S3)
     int qi[NQ], qj[NQ];
+    unsigned qo[NQ];
     bool qok[NQ];
     for (int u = 0; u < NQ; ++u) {
         const int q = tid + NT * u;
         qok[u] = q < N;
         qi[u] = i0 - 2 + q % W;
         qj[u] = j0 - 2 + q / W;
+        qo[u] = off(qi[u], qj[u]);
     }
     int ri[NR], rj[NR];
+    unsigned ro[NR];
     bool rok[NR];
     for (int u = 0; u < NR; ++u) {
         const int r = tid + NT * u;
         rok[u] = r < CN;
         ri[u] = i0 - 1 + r % CW;
         rj[u] = j0 - 1 + r / CW;
+        ro[u] = off(ri[u], rj[u]);
     }
 
     // prefetch registers (step g)
@@ -104,36 +119,37 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, TileSet ts
     auto prefetch = [&](int g) {
         const bool pl = g >= 0 && g < nz, lv = g >= 0 && g <= nz, inner = g >= 1 && g <= nz - 1;
         const bool pm = g - 1 >= 0 && g - 1 < nz;
+        const long pg = sz * g, pg1 = pg - sz;
 #pragma unroll
         for (int u = 0; u < NQ; ++u) {
             const int i = qi[u], j = qj[u];
-            const long e = i + sy * j + sz * g;
+            const unsigned o = qo[u];
             const bool ok = qok[u];
-            fvx[u] = (ok && pl && (INT || (i >= 0 && i <= nx && j >= 0 && j < ny))) ? vx[e] : R(0);
-            fvy[u] = (ok && pl && (INT || (i >= 0 && i < nx && j >= 0 && j <= ny))) ? vy[e] : R(0);
-            fvz[u] = (ok && lv && (INT || (i >= 0 && i < nx && j >= 0 && j < ny))) ? vz[e] : R(0);
+            fvx[u] = (ok && pl && (INT || (i >= 0 && i <= nx && j >= 0 && j < ny))) ? ld(itb + F_VX * fs + pg, o) : R(0);
+            fvy[u] = (ok && pl && (INT || (i >= 0 && i < nx && j >= 0 && j <= ny))) ? ld(itb + F_VY * fs + pg, o) : R(0);
+            fvz[u] = (ok && lv && (INT || (i >= 0 && i < nx && j >= 0 && j < ny))) ? ld(itb + F_VZ * fs + pg, o) : R(0);
             const bool exz = ok && inner && (INT || (i >= 1 && i <= nx - 1 && j >= 0 && j < ny));
             const bool eyz = ok && inner && (INT || (j >= 1 && j <= ny - 1 && i >= 0 && i < nx));
-            fxz[u] = exz ? txz_k[e] : R(0);
-            fxzo[u] = exz ? txz_o[e] : R(0);
-            fyz[u] = eyz ? tyz_k[e] : R(0);
-            fyzo[u] = eyz ? tyz_o[e] : R(0);
+            fxz[u] = exz ? ld(itb + F_TXZ * fs + pg, o) : R(0);
+            fxzo[u] = exz ? ld(olb + O_TXZ * fs + pg, o) : R(0);
+            fyz[u] = eyz ? ld(itb + F_TYZ * fs + pg, o) : R(0);
+            fyzo[u] = eyz ? ld(olb + O_TYZ * fs + pg, o) : R(0);
             const bool exy = ok && pm && (INT || (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1));
-            fxy[u] = exy ? txy_k[e - sz] : R(0);
-            fxyo[u] = exy ? txy_o[e - sz] : R(0);
+            fxy[u] = exy ? ld(itb + F_TXY * fs + pg1, o) : R(0);
+            fxyo[u] = exy ? ld(olb + O_TXY * fs + pg1, o) : R(0);
         }
 #pragma unroll
         for (int u = 0; u < NR; ++u) {
             const int i = ri[u], j = rj[u];
-            const long e = i + sy * j + sz * (g - 1);
+            const unsigned o = ro[u];
             const bool ok = rok[u] && pm && (INT || (i >= 0 && i < nx && j >= 0 && j < ny));
-            fp[u] = ok ? p_k[e] : R(0);
-            fpo[u] = ok ? p_o[e] : R(0);
-            fsx[u] = ok ? txx_k[e] : R(0);
-            fsxo[u] = ok ? txx_o[e] : R(0);
-            fsy[u] = ok ? tyy_k[e] : R(0);
-            fsyo[u] = ok ? tyy_o[e] : R(0);
-            fc[u] = ok ? coh[e] : R(0);
+            fp[u] = ok ? ld(itb + F_P * fs + pg1, o) : R(0);
+            fpo[u] = ok ? ld(olb + O_P * fs + pg1, o) : R(0);
+            fsx[u] = ok ? ld(itb + F_TXX * fs + pg1, o) : R(0);
+            fsxo[u] = ok ? ld(olb + O_TXX * fs + pg1, o) : R(0);
+            fsy[u] = ok ? ld(itb + F_TYY * fs + pg1, o) : R(0);
+            fsyo[u] = ok ? ld(olb + O_TYY * fs + pg1, o) : R(0);
+            fc[u] = ok ? ld(a.coh + pg1, o) : R(0);
         }
     };
 
@@ -141,6 +157,7 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, TileSet ts
 
     prefetch(k0 - 2);
     for (int f = k0 - 2; f <= k1 + 1; ++f) {
+        asm volatile("" : "+s"(fs));
         // take over the data of step f, start loading step f+1
         R cvx[NQ], cvy[NQ], cvz[NQ], cxz[NQ], cxzo[NQ], cyz[NQ], cyzo[NQ], cxy[NQ], cxyo[NQ];
         R cp[NR], cpo[NR], csx[NR], csxo[NR], csy[NR], csyo[NR], cc[NR];
@@ -244,12 +261,11 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, TileSet ts
                 R sc_ = return_scale(J2, D, a.invD, pn, cc[u], a.A, a.B, lam);
                 const bool own = la >= 2 && la < TX + 2 && lbb >= 2 && lbb < TY + 2 && c >= k0 && c < k1;
                 if (a.lam_mode != LAM_COMPUTE) {                 // frozen plasticity
-                    const long ec = i + sy * j + sz * c;
                     if (a.lam_mode == LAM_FROZEN) {
-                        lam = a.lam[ec];
+                        lam = ld(a.lam + sz * c, ro[u]);
                         sc_ = R(1) / (D + lam);
                     } else if (own) {
-                        a.lam[ec] = lam;
+                        st(a.lam + sz * c, ro[u], lam);
                     }
                 }
                 R txx = Txx * sc_, tyy = Tyy * sc_;
@@ -258,10 +274,10 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, TileSet ts
                 s_sxx[sc][q] = txx;
                 s_syy[sc][q] = tyy;
                 if (own) {
-                    const long e = i + sy * j + sz * c;
-                    a.nx_[F_P][e] = pn;
-                    a.nx_[F_TXX][e] = txx;
-                    a.nx_[F_TYY][e] = tyy;
+                    const long pc = sz * c;
+                    st(nxb + F_P * fs + pc, ro[u], pn);
+                    st(nxb + F_TXX * fs + pc, ro[u], txx);
+                    st(nxb + F_TYY * fs + pc, ro[u], tyy);
                     if (MODE == MODE_CHECK) {
                         R dp = fabs(pn - pk) * a.rK;
                         R dtx = fabs(txx - txk), dty = fabs(tyy - tyk), dtz = fabs((txx + tyy) - (txk + tyk));
@@ -289,9 +305,9 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, TileSet ts
                     }
                     s_nxy[sp][q] = t;
                     if (la < TX + 2 + hx && lbb < TY + 2 + hy && (INT || (i <= nx && j <= ny))) {
-                        const long e = i + sy * j + sz * p;
-                        a.nx_[F_TXY][e] = t;
-                        if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)(fabs(t - a.it[F_TXY][e]) * a.rG));
+                        const unsigned o = off(i, j);
+                        st(nxb + F_TXY * fs + sz * p, o, t);
+                        if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)(fabs(t - ld(itb + F_TXY * fs + sz * p, o)) * a.rG));
                     }
                 }
             }
@@ -305,7 +321,8 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, TileSet ts
                     const int la = 2 + r % EW, lbb = 2 + r / EW;
                     const int q = la + W * lbb;
                     const int i = i0 - 2 + la, j = j0 - 2 + lbb;
-                    const long e = i + sy * j + sz * l;
+                    const unsigned o = off(i, j);
+                    const long pl = sz * l;
                     // xz edge (i, j) at level l: x-extent nx+1, y-extent ny
                     if (lbb < TY + 2) {
                         R t = R(0);
@@ -315,8 +332,8 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, TileSet ts
                         }
                         s_nxz[sl][q] = t;
                         if (own_l && la < TX + 2 + hx && (INT || (i <= nx && j < ny))) {
-                            a.nx_[F_TXZ][e] = t;
-                            if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)(fabs(t - a.it[F_TXZ][e]) * a.rG));
+                            st(nxb + F_TXZ * fs + pl, o, t);
+                            if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)(fabs(t - ld(itb + F_TXZ * fs + pl, o)) * a.rG));
                         }
                     }
                     // yz edge (i, j) at level l: x-extent nx, y-extent ny+1
@@ -328,8 +345,8 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, TileSet ts
                         }
                         s_nyz[sl][q] = t;
                         if (own_l && lbb < TY + 2 + hy && (INT || (i < nx && j <= ny))) {
-                            a.nx_[F_TYZ][e] = t;
-                            if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)(fabs(t - a.it[F_TYZ][e]) * a.rG));
+                            st(nxb + F_TYZ * fs + pl, o, t);
+                            if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)(fabs(t - ld(itb + F_TYZ * fs + pl, o)) * a.rG));
                         }
                     }
                 }
@@ -346,7 +363,8 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, TileSet ts
                     const int la = 2 + r % FW, lbb = 2 + r / FW;
                     const int q = la + W * lbb;
                     const int i = i0 - 2 + la, j = j0 - 2 + lbb;
-                    const long e = i + sy * j + sz * p;
+                    const unsigned o = off(i, j);
+                    const long pp = sz * p;
                     if (la < TX + 2 + hx && lbb < TY + 2 && (INT || (i <= nx && j < ny))) {      // x-face
                         R v = s_vx[cm][q];
                         if (INT || (i >= 1 && i <= nx - 1)) {
@@ -355,7 +373,7 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, TileSet ts
                             v = v + a.dtrho * Rx;
                             mmax = nmax(mmax, (double)fabs(Rx));
                         }
-                        if (MODE != MODE_PHYS) a.nx_[F_VX][e] = v;
+                        if (MODE != MODE_PHYS) st(nxb + F_VX * fs + pp, o, v);
                         vmax = nmax(vmax, (double)fabs(v));
                     }
                     if (la < TX + 2 && lbb < TY + 2 + hy && (INT || (i < nx && j <= ny))) {      // y-face
@@ -367,7 +385,7 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, TileSet ts
                             v = v + a.dtrho * Ry;
                             mmax = nmax(mmax, (double)fabs(Ry));
                         }
-                        if (MODE != MODE_PHYS) a.nx_[F_VY][e] = v;
+                        if (MODE != MODE_PHYS) st(nxb + F_VY * fs + pp, o, v);
                         vmax = nmax(vmax, (double)fabs(v));
                     }
                 }
@@ -376,12 +394,11 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, TileSet ts
             if (l >= 0 && ((l >= k0 && l < k1) || (l == nz && last_z))) {
                 const int sl = mod2(l), sm = mod2(l - 1);
                 const bool inner_l = l >= 1 && l <= nz - 1;
-                for (int r = tid; r < NT; r += NT) {
+                for (int r = tid; r < TX * TY; r += NT) {
                     const int la = 2 + r % TX, lbb = 2 + r / TX;
                     const int q = la + W * lbb;
                     const int i = i0 - 2 + la, j = j0 - 2 + lbb;
                     if (!INT && (i >= nx || j >= ny)) continue;
-                    const long e = i + sy * j + sz * l;
                     R v = s_vz[sl][q];
                     if (inner_l) {
                         R szu = -(s_sxx[sl][q] + s_syy[sl][q]) - s_p[sl][q];
@@ -391,7 +408,7 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, TileSet ts
                         v = v + a.dtrho * Rz;
                         mmax = nmax(mmax, (double)fabs(Rz));
                     }
-                    if (MODE != MODE_PHYS) a.nx_[F_VZ][e] = v;
+                    if (MODE != MODE_PHYS) st(nxb + F_VZ * fs + sz * l, off(i, j), v);
                     vmax = nmax(vmax, (double)fabs(v));
                 }
             }
@@ -411,13 +428,13 @@ __global__ __launch_bounds__(TX * TY) void k_fused_3d(SweepArgs<R> a, TileSet ts
     else body(std::false_type{});
 }
 
-// tile shapes
-constexpr int T3X = 32, T3Y = 16, T3Z = 32;         // FP32 3D
-constexpr int D3X = 32, D3Y = 4, D3Z = 32;          // FP64 3D (LDS-limited)
-
+// Tile shapes and workgroup sizes.  FP32: 768 threads cover the 36 x 20
+// halo plane (720 points) and every later stage in a single pass, so no
+// wave does a second round while the others wait at the stage barrier.
 template <typename R> struct Tile3;
-template <> struct Tile3<float> { static constexpr int X = T3X, Y = T3Y, Z = T3Z; };
-template <> struct Tile3<double> { static constexpr int X = D3X, Y = D3Y, Z = D3Z; };
+// E: waves per SIMD to fit in registers (two FP32 workgroups per CU).
+template <> struct Tile3<float> { static constexpr int X = 32, Y = 16, Z = 32, T = 768, E = 6; };
+template <> struct Tile3<double> { static constexpr int X = 32, Y = 4, Z = 32, T = 128, E = 1; };   // LDS-limited
 
 // first and one-past-last tile index along an axis whose tiles lie strictly
 // inside with their 2-point halo: 3 <= i0 and i0 + T + 2 <= n
@@ -432,14 +449,14 @@ inline void interior_range(int n, int T, int nb, int& b0, int& b1)
 template <typename R, int MODE>
 void run_3d(const SweepArgs<R>& a, hipStream_t s)
 {
-    constexpr int TX = Tile3<R>::X, TY = Tile3<R>::Y, ZC = Tile3<R>::Z;
+    constexpr int TX = Tile3<R>::X, TY = Tile3<R>::Y, ZC = Tile3<R>::Z, NT = Tile3<R>::T, WPE = Tile3<R>::E;
     TileSet ts;
     ts.nbx = (a.nx + TX - 1) / TX;
     ts.nby = (a.ny + TY - 1) / TY;
     ts.nbz = (a.nz + ZC - 1) / ZC;
     interior_range(a.nx, TX, ts.nbx, ts.bx0, ts.bx1);
     interior_range(a.ny, TY, ts.nby, ts.by0, ts.by1);
-    k_fused_3d<R, TX, TY, ZC, MODE><<<ts.nbx * ts.nby * ts.nbz, TX * TY, 0, s>>>(a, ts);
+    k_fused_3d<R, TX, TY, ZC, MODE, NT, WPE><<<ts.nbx * ts.nby * ts.nbz, NT, 0, s>>>(a, ts);
 }
 
 
