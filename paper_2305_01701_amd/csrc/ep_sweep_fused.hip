@@ -250,8 +250,8 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
                 R div = dvx + dvy + dvz;
                 const R pk = cp[u], txk = csx[u], tyk = csy[u];
                 R pn = (pk * ikt + cpo[u] * ikd - div) * a.ikk;
-                R Txx = txk * igt + csxo[u] * igd + R(2) * (dvx - div / R(3));
-                R Tyy = tyk * igt + csyo[u] * igd + R(2) * (dvy - div / R(3));
+                R Txx = txk * igt + csxo[u] * igd + R(2) * (dvx - div * R(1.0 / 3.0));
+                R Tyy = tyk * igt + csyo[u] * igd + R(2) * (dvy - div * R(1.0 / 3.0));
                 R Tzz = -(Txx + Tyy);
                 R Txyb = R(0.25) * (s_Txy[q] + s_Txy[q + 1] + s_Txy[q + W] + s_Txy[q + W + 1]);
                 R Txzb = R(0.25) * (s_Txz[sc][q] + s_Txz[sc][q + 1] + s_Txz[sc1][q] + s_Txz[sc1][q + 1]);
