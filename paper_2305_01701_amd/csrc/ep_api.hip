@@ -122,8 +122,8 @@ size_t carve(const ep_params* p, ep_handle* h, char* base)
         if (h) h->vguess64[d] = (double*)q;
     }
     if (p->ndim == 2) {
-        const long nt = (long)((nx + kBatchTiles[0][0] - 1) / kBatchTiles[0][0]) *
-                        ((ny + kBatchTiles[0][1] - 1) / kBatchTiles[0][1]);
+        const long nt = (long)((nx + kBatchTiles[SINGLE_SHAPE][0] - 1) / kBatchTiles[SINGLE_SHAPE][0]) *
+                        ((ny + kBatchTiles[SINGLE_SHAPE][1] - 1) / kBatchTiles[SINGLE_SHAPE][1]);
         q = take(8 * sizeof(SweepArgs<double>)); if (h) h->tab64 = (SweepArgs<double>*)q;
         q = take(6 * sizeof(SweepArgs<float>)); if (h) h->tab32 = (SweepArgs<float>*)q;
         q = take(nt * sizeof(TileRef)); if (h) h->tiles = (TileRef*)q;
@@ -260,11 +260,11 @@ void launch_sweep(const ep_handle* h, bool physical, int from, int mode, int lam
     const bool fused = sizeof(R) == 4 ? h->fused32 : h->fused64;
     if (h->ndim == 2 && fused) {
         if (sizeof(R) == 4)
-            launch_sweep_batch_2d<float>(0, h->tab32 + 2 * lam_mode + from, h->tiles, h->tcount, mode, h->grid2[1],
-                                         h->st);
+            launch_sweep_batch_2d<float>(SINGLE_SHAPE, h->tab32 + 2 * lam_mode + from, h->tiles, h->tcount, mode,
+                                         h->grid2[1], h->st);
         else
-            launch_sweep_batch_2d<double>(0, h->tab64 + (physical ? 6 : 2 * lam_mode) + from, h->tiles, h->tcount,
-                                          mode, h->grid2[0], h->st);
+            launch_sweep_batch_2d<double>(SINGLE_SHAPE, h->tab64 + (physical ? 6 : 2 * lam_mode) + from, h->tiles,
+                                          h->tcount, mode, h->grid2[0], h->st);
         return;
     }
     SweepArgs<R> a;
@@ -750,7 +750,7 @@ int handle_create(const ep_params* p, const double* cohesion, char* d_workspace,
     h->old32_valid = false;
     if (h->ndim == 2) {
         // tile list of the whole model and the persistent grid sizes
-        const int tx = kBatchTiles[0][0], ty = kBatchTiles[0][1];
+        const int tx = kBatchTiles[SINGLE_SHAPE][0], ty = kBatchTiles[SINGLE_SHAPE][1];
         const int nbx = (h->nx + tx - 1) / tx;
         std::vector<TileRef> tl(h->ntiles);
         for (long t = 0; t < h->ntiles; ++t) tl[t] = TileRef{0, (short)(t % nbx), (short)(t / nbx)};
@@ -762,8 +762,10 @@ int handle_create(const ep_params* p, const double* cohesion, char* d_workspace,
             return fail(EP_EDEVICE);
         int ncu = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, 0) != hipSuccess || ncu <= 0) ncu = 256;
-        h->grid2[0] = (int)std::min<long>(h->ntiles, (long)ncu * std::min(8, batch_blocks_per_cu<double>(0)));
-        h->grid2[1] = (int)std::min<long>(h->ntiles, (long)ncu * std::min(8, batch_blocks_per_cu<float>(0)));
+        h->grid2[0] =
+            (int)std::min<long>(h->ntiles, (long)ncu * std::min(8, batch_blocks_per_cu<double>(SINGLE_SHAPE)));
+        h->grid2[1] =
+            (int)std::min<long>(h->ntiles, (long)ncu * std::min(8, batch_blocks_per_cu<float>(SINGLE_SHAPE)));
         if (upload_tables(h) != EP_OK) return fail(EP_EDEVICE);
     }
     if (hipGetLastError() != hipSuccess) return fail(EP_EDEVICE);

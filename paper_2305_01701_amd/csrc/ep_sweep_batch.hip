@@ -16,8 +16,8 @@ namespace ep {
 
 namespace {
 
-template <typename R, int TX, int TY, int MODE>
-__global__ __launch_bounds__(TX * TY) void k_batch_2d(const SweepArgs<R>* __restrict__ table,
+template <typename R, int TX, int TY, int MODE, int NT = tile_threads_2d<TX, TY>()>
+__global__ __launch_bounds__(NT) void k_batch_2d(const SweepArgs<R>* __restrict__ table,
                                                       const TileRef* __restrict__ list,
                                                       const int* __restrict__ count)
 {
@@ -28,27 +28,28 @@ __global__ __launch_bounds__(TX * TY) void k_batch_2d(const SweepArgs<R>* __rest
     for (int t = g; t < n; t += gridDim.x) {
         if (t != g) __syncthreads();        // LDS of the previous tile is still being read
         const TileRef r = list[t];
-        sweep_tile_2d<R, TX, TY, MODE>(table[r.model], r.bx, r.by);
+        sweep_tile_2d<R, TX, TY, MODE, NT>(table[r.model], r.bx, r.by);
     }
 }
 
-template <typename R, int TX, int TY>
+template <typename R, int TX, int TY, int NT = tile_threads_2d<TX, TY>()>
 void run(const SweepArgs<R>* table, const TileRef* list, const int* count, int mode, int grid, hipStream_t s)
 {
     if (mode == MODE_CHECK)
-        k_batch_2d<R, TX, TY, MODE_CHECK><<<grid, TX * TY, 0, s>>>(table, list, count);
+        k_batch_2d<R, TX, TY, MODE_CHECK, NT><<<grid, NT, 0, s>>>(table, list, count);
     else if (mode == MODE_PHYS) {
-        // physical evaluations run only on single models, with the default shape
-        if constexpr (TX == 64 && TY == 8) k_batch_2d<R, TX, TY, MODE_PHYS><<<grid, TX * TY, 0, s>>>(table, list, count);
+        // physical evaluations run only on single models, with their shape
+        if constexpr (TX == 64 && TY == 8 && NT == 512)
+            k_batch_2d<R, TX, TY, MODE_PHYS, NT><<<grid, NT, 0, s>>>(table, list, count);
     } else
-        k_batch_2d<R, TX, TY, MODE_UPDATE><<<grid, TX * TY, 0, s>>>(table, list, count);
+        k_batch_2d<R, TX, TY, MODE_UPDATE, NT><<<grid, NT, 0, s>>>(table, list, count);
 }
 
-template <typename R, int TX, int TY>
+template <typename R, int TX, int TY, int NT = tile_threads_2d<TX, TY>()>
 int occupancy()
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_2d<R, TX, TY, MODE_CHECK>, TX * TY, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_2d<R, TX, TY, MODE_CHECK, NT>, NT, 0) !=
         hipSuccess)
         return 1;
     return n > 0 ? n : 1;
@@ -56,7 +57,10 @@ int occupancy()
 
 }  // namespace
 
-const int kBatchTiles[BATCH_SHAPES][2] = {{64, 8}, {64, 4}, {32, 8}, {128, 4}, {64, 16}, {32, 16}};
+const int kBatchTiles[BATCH_SHAPES][3] = {
+    {64, 8, tile_threads_2d<64, 8>()},   {64, 4, tile_threads_2d<64, 4>()},   {32, 8, tile_threads_2d<32, 8>()},
+    {128, 4, tile_threads_2d<128, 4>()}, {64, 16, tile_threads_2d<64, 16>()}, {32, 16, tile_threads_2d<32, 16>()},
+    {64, 8, 512}};
 
 template <typename R>
 void launch_sweep_batch_2d(int shape, const SweepArgs<R>* table, const TileRef* list, const int* count, int mode,
@@ -68,7 +72,8 @@ void launch_sweep_batch_2d(int shape, const SweepArgs<R>* table, const TileRef* 
     case 2: run<R, 32, 8>(table, list, count, mode, grid, s); break;
     case 3: run<R, 128, 4>(table, list, count, mode, grid, s); break;
     case 4: run<R, 64, 16>(table, list, count, mode, grid, s); break;
-    default: run<R, 32, 16>(table, list, count, mode, grid, s); break;
+    case 5: run<R, 32, 16>(table, list, count, mode, grid, s); break;
+    default: run<R, 64, 8, 512>(table, list, count, mode, grid, s); break;
     }
 }
 
@@ -81,7 +86,8 @@ int batch_blocks_per_cu(int shape)
     case 2: return occupancy<R, 32, 8>();
     case 3: return occupancy<R, 128, 4>();
     case 4: return occupancy<R, 64, 16>();
-    default: return occupancy<R, 32, 16>();
+    case 5: return occupancy<R, 32, 16>();
+    default: return occupancy<R, 64, 8, 512>();
     }
 }
 

@@ -14,13 +14,23 @@
 
 namespace ep {
 
-template <typename R, int TX, int TY, int MODE>
+// Workgroup size of a tile: enough threads for one pass over the halo plane
+// (W x H points), so that no wave does a second round of a stage while the
+// others wait at its barrier; two balanced passes when that exceeds 1024.
+template <int TX, int TY>
+constexpr int tile_threads_2d()
+{
+    constexpr int n = (TX + 4) * (TY + 4);
+    return n <= 1024 ? (n + 63) / 64 * 64 : ((n + 1) / 2 + 63) / 64 * 64;
+}
+
+template <typename R, int TX, int TY, int MODE, int NT>
 __device__ __forceinline__ void sweep_tile_2d(const SweepArgs<R>& a, int bx, int by)
 {
     // multiply-adds are fused only within one expression, so that every
     // caller (single-model or batched kernel) rounds each point identically
 #pragma clang fp contract(on)
-    constexpr int W = TX + 4, H = TY + 4, N = W * H, NT = TX * TY;
+    constexpr int W = TX + 4, H = TY + 4, N = W * H;
     __shared__ R s_vx[N], s_vy[N], s_Txy[N], s_lam[N], s_p[N], s_sxx[N], s_syy[N], s_nxy[N];
     __shared__ double s_red[NT / 64 > 0 ? NT / 64 : 1];
 
