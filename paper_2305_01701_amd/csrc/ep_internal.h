@@ -70,12 +70,9 @@ struct TileRef {
     int model;             // index into the model table
     short bx, by;          // tile coordinates in the model's grid
 };
-constexpr int BATCH_SHAPES = 7;
-// (TX, TY, threads) of each tile shape.  Shapes 0-5 take one pass over the
-// halo plane per stage; shape 6 is 64 x 8 with 512 threads (two passes),
-// the shape of single 2D models.
-extern const int kBatchTiles[BATCH_SHAPES][3];
-constexpr int SINGLE_SHAPE = 6;
+constexpr int BATCH_SHAPES = 6;
+extern const int kBatchTiles[BATCH_SHAPES][3];   // (TX, TY, threads) of each tile shape
+constexpr int SINGLE_SHAPE = 4;                   // 64 x 16: the shape of single 2D models
 // One sweep of every tile in list[0 .. *count) with the tile shape `shape`;
 // table[model] holds the model's arguments (reads of iteration k, writes of
 // k+1).  `grid` workgroups walk the list (persistent grid).

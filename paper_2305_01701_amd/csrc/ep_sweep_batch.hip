@@ -39,7 +39,7 @@ void run(const SweepArgs<R>* table, const TileRef* list, const int* count, int m
         k_batch_2d<R, TX, TY, MODE_CHECK, NT><<<grid, NT, 0, s>>>(table, list, count);
     else if (mode == MODE_PHYS) {
         // physical evaluations run only on single models, with their shape
-        if constexpr (TX == 64 && TY == 8 && NT == 512)
+        if constexpr (TX == 64 && TY == 16)
             k_batch_2d<R, TX, TY, MODE_PHYS, NT><<<grid, NT, 0, s>>>(table, list, count);
     } else
         k_batch_2d<R, TX, TY, MODE_UPDATE, NT><<<grid, NT, 0, s>>>(table, list, count);
@@ -59,8 +59,7 @@ int occupancy()
 
 const int kBatchTiles[BATCH_SHAPES][3] = {
     {64, 8, tile_threads_2d<64, 8>()},   {64, 4, tile_threads_2d<64, 4>()},   {32, 8, tile_threads_2d<32, 8>()},
-    {128, 4, tile_threads_2d<128, 4>()}, {64, 16, tile_threads_2d<64, 16>()}, {32, 16, tile_threads_2d<32, 16>()},
-    {64, 8, 512}};
+    {128, 4, tile_threads_2d<128, 4>()}, {64, 16, tile_threads_2d<64, 16>()}, {32, 16, tile_threads_2d<32, 16>()}};
 
 template <typename R>
 void launch_sweep_batch_2d(int shape, const SweepArgs<R>* table, const TileRef* list, const int* count, int mode,
@@ -72,8 +71,7 @@ void launch_sweep_batch_2d(int shape, const SweepArgs<R>* table, const TileRef* 
     case 2: run<R, 32, 8>(table, list, count, mode, grid, s); break;
     case 3: run<R, 128, 4>(table, list, count, mode, grid, s); break;
     case 4: run<R, 64, 16>(table, list, count, mode, grid, s); break;
-    case 5: run<R, 32, 16>(table, list, count, mode, grid, s); break;
-    default: run<R, 64, 8, 512>(table, list, count, mode, grid, s); break;
+    default: run<R, 32, 16>(table, list, count, mode, grid, s); break;
     }
 }
 
@@ -86,8 +84,7 @@ int batch_blocks_per_cu(int shape)
     case 2: return occupancy<R, 32, 8>();
     case 3: return occupancy<R, 128, 4>();
     case 4: return occupancy<R, 64, 16>();
-    case 5: return occupancy<R, 32, 16>();
-    default: return occupancy<R, 64, 8, 512>();
+    default: return occupancy<R, 32, 16>();
     }
 }
 
