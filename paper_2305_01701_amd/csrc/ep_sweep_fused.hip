@@ -153,7 +153,9 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
         }
     };
 
-    double rmax = 0.0, mmax = 0.0, vmax = 0.0, smax = 0.0;   // combined, momentum-only, |v|, |stress|
+    // combined, momentum-only, |v|, |stress| maxima, kept in the field type
+    // (maxima are exact) and widened for the block reduction
+    R rmax = R(0), mmax = R(0), vmax = R(0), smax = R(0);
 
     prefetch(k0 - 2);
     for (int f = k0 - 2; f <= k1 + 1; ++f) {
@@ -281,8 +283,8 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
                     if (MODE == MODE_CHECK) {
                         R dp = fabs(pn - pk) * a.rK;
                         R dtx = fabs(txx - txk), dty = fabs(tyy - tyk), dtz = fabs((txx + tyy) - (txk + tyk));
-                        rmax = nmax(rmax, nmax((double)dp, (double)(nmax(nmax(dtx, dty), dtz) * a.rG)));
-                        smax = nmax(smax, (double)nmax(nmax(fabs(pn), fabs(txx)), nmax(fabs(tyy), fabs(txx + tyy))));
+                        rmax = nmax(rmax, nmax(dp, nmax(nmax(dtx, dty), dtz) * a.rG));
+                        smax = nmax(smax, nmax(nmax(fabs(pn), fabs(txx)), nmax(fabs(tyy), fabs(txx + tyy))));
                     }
                 }
             }
@@ -307,7 +309,7 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
                     if (la < TX + 2 + hx && lbb < TY + 2 + hy && (INT || (i <= nx && j <= ny))) {
                         const unsigned o = off(i, j);
                         st(nxb + F_TXY * fs + sz * p, o, t);
-                        if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)(fabs(t - ld(itb + F_TXY * fs + sz * p, o)) * a.rG));
+                        if (MODE == MODE_CHECK) rmax = nmax(rmax, fabs(t - ld(itb + F_TXY * fs + sz * p, o)) * a.rG);
                     }
                 }
             }
@@ -333,7 +335,7 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
                         s_nxz[sl][q] = t;
                         if (own_l && la < TX + 2 + hx && (INT || (i <= nx && j < ny))) {
                             st(nxb + F_TXZ * fs + pl, o, t);
-                            if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)(fabs(t - ld(itb + F_TXZ * fs + pl, o)) * a.rG));
+                            if (MODE == MODE_CHECK) rmax = nmax(rmax, fabs(t - ld(itb + F_TXZ * fs + pl, o)) * a.rG);
                         }
                     }
                     // yz edge (i, j) at level l: x-extent nx, y-extent ny+1
@@ -346,7 +348,7 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
                         s_nyz[sl][q] = t;
                         if (own_l && lbb < TY + 2 + hy && (INT || (i < nx && j <= ny))) {
                             st(nxb + F_TYZ * fs + pl, o, t);
-                            if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)(fabs(t - ld(itb + F_TYZ * fs + pl, o)) * a.rG));
+                            if (MODE == MODE_CHECK) rmax = nmax(rmax, fabs(t - ld(itb + F_TYZ * fs + pl, o)) * a.rG);
                         }
                     }
                 }
@@ -371,10 +373,10 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
                             R Rx = ((s_sxx[sp][q] - s_p[sp][q]) - (s_sxx[sp][q - 1] - s_p[sp][q - 1])) * idx
                                  + (s_nxy[sp][q + W] - s_nxy[sp][q]) * idy + (s_nxz[sp1][q] - s_nxz[sp][q]) * idz;
                             v = v + a.dtrho * Rx;
-                            mmax = nmax(mmax, (double)fabs(Rx));
+                            mmax = nmax(mmax, fabs(Rx));
                         }
                         if (MODE != MODE_PHYS) st(nxb + F_VX * fs + pp, o, v);
-                        vmax = nmax(vmax, (double)fabs(v));
+                        vmax = nmax(vmax, fabs(v));
                     }
                     if (la < TX + 2 && lbb < TY + 2 + hy && (INT || (i < nx && j <= ny))) {      // y-face
                         R v = s_vy[cm][q];
@@ -383,10 +385,10 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
                                  + ((s_syy[sp][q] - s_p[sp][q]) - (s_syy[sp][q - W] - s_p[sp][q - W])) * idy
                                  + (s_nyz[sp1][q] - s_nyz[sp][q]) * idz;
                             v = v + a.dtrho * Ry;
-                            mmax = nmax(mmax, (double)fabs(Ry));
+                            mmax = nmax(mmax, fabs(Ry));
                         }
                         if (MODE != MODE_PHYS) st(nxb + F_VY * fs + pp, o, v);
-                        vmax = nmax(vmax, (double)fabs(v));
+                        vmax = nmax(vmax, fabs(v));
                     }
                 }
             }
@@ -406,21 +408,21 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
                         R Rz = (s_nxz[sl][q + 1] - s_nxz[sl][q]) * idx + (s_nyz[sl][q + W] - s_nyz[sl][q]) * idy
                              + (szu - szd) * idz;
                         v = v + a.dtrho * Rz;
-                        mmax = nmax(mmax, (double)fabs(Rz));
+                        mmax = nmax(mmax, fabs(Rz));
                     }
                     if (MODE != MODE_PHYS) st(nxb + F_VZ * fs + sz * l, off(i, j), v);
-                    vmax = nmax(vmax, (double)fabs(v));
+                    vmax = nmax(vmax, fabs(v));
                 }
             }
         }
         __syncthreads();
     }
     if (MODE != MODE_UPDATE) {
-        block_max_to<NT>(mmax, a.red + RED_MOM, s_red);
+        block_max_to<NT>((double)mmax, a.red + RED_MOM, s_red);
         if (MODE == MODE_CHECK) {
-            block_max_to<NT>(fmax(rmax, mmax), a.red + RED_RESID, s_red);
-            block_max_to<NT>(vmax, a.red + RED_VMAX, s_red);
-            block_max_to<NT>(smax, a.red + RED_SMAX, s_red);
+            block_max_to<NT>((double)fmax(rmax, mmax), a.red + RED_RESID, s_red);
+            block_max_to<NT>((double)vmax, a.red + RED_VMAX, s_red);
+            block_max_to<NT>((double)smax, a.red + RED_SMAX, s_red);
         }
     }
     };
