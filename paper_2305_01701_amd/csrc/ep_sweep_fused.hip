@@ -6,15 +6,17 @@
 //
 //   3D: a workgroup owns a TX x TY column of cells over a chunk of ZC
 //   z-planes and marches up the chunk.  Every quantity lives in LDS as 2D
-//   planes of (TX+4) x (TY+4) points (a 2-point x-y halo) in small ring
-//   buffers over z.  Step f of the march loads the velocity planes at z = f,
-//   forms the shear trials on the z-level f (xz, yz edges) and the plane
-//   f-1 (xy edges), the centre update of plane f-1 (pressure, deviator,
-//   return mapping), the new edge stresses of plane/level f-1, and the new
-//   velocities of plane f-2 (vx, vy) and level f-1 (vz).  Each field is read
-//   from and written to HBM once per sweep; the halo reads of neighbouring
-//   tiles are served by L2 (blocks are remapped so that spatial neighbours
-//   run on the same XCD).
+//   planes of (TX+4) x (TY+4) points (a 2-point x-y halo) in two-slot ring
+//   buffers over z.  Step f of the march forms the shear trials on the
+//   z-level f (xz, yz edges) and the plane f-1 (xy edges), the centre update
+//   of plane f-1 (pressure, deviator, return mapping), the new edge stresses
+//   of plane/level f-1, and the new velocities of plane f-2 (vx, vy) and
+//   level f-1 (vz), then stores the velocity planes of step f+1 to LDS: four
+//   workgroup barriers per step.  The velocity stage updates each thread's
+//   own plane points, whose old values the thread keeps in registers.  Each
+//   field is read from and written to HBM once per sweep; the halo reads of
+//   neighbouring tiles are served by L2 (blocks are remapped so that spatial
+//   neighbours run on the same XCD).
 //   2D: the same stages on a single TX x TY tile (ep_tile2d.h, run by the
 //   tile-list kernel of ep_sweep_batch.hip for single models and batches).
 //
@@ -28,7 +30,6 @@ namespace ep {
 
 namespace {
 
-__device__ __forceinline__ int mod3(int f) { int r = f % 3; return r < 0 ? r + 3 : r; }
 __device__ __forceinline__ int mod2(int f) { return f & 1; }
 
 // Tile grid of a 3D sweep and its interior rectangle [bx0, bx1) x [by0,
@@ -52,7 +53,7 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
     constexpr int NQ = (N + NT - 1) / NT;                  // plane positions per thread
     constexpr int CW = TX + 2, CN = (TX + 2) * (TY + 2);   // centre region (1-cell halo)
     constexpr int NR = (CN + NT - 1) / NT;
-    __shared__ R s_vx[3][N], s_vy[3][N], s_vz[2][N];
+    __shared__ R s_vx[2][N], s_vy[2][N], s_vz[2][N];
     __shared__ R s_Txy[N], s_Txz[2][N], s_Tyz[2][N];
     __shared__ R s_lam[2][N], s_p[2][N], s_sxx[2][N], s_syy[2][N];
     __shared__ R s_nxy[2][N], s_nxz[2][N], s_nyz[2][N];
@@ -157,15 +158,45 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
     // (maxima are exact) and widened for the block reduction
     R rmax = R(0), mmax = R(0), vmax = R(0), smax = R(0);
 
+    // S1 of step g: the prefetched velocities of plane g (vx, vy) and level
+    // g (vz) go to LDS and into this thread's register history, from which
+    // S5 takes the old velocities of its own points (vx, vy of plane g-2, vz
+    // of level g-1 at step g)
+    R hvx1[NQ], hvx2[NQ], hvx3[NQ], hvy1[NQ], hvy2[NQ], hvy3[NQ], hvz1[NQ], hvz2[NQ];
+    auto stage_velocities = [&](int g) {
+        const bool ld_xy = g >= 0 && g < nz;
+        const bool ld_z = g >= 0 && g <= nz;
+        const int s2 = mod2(g);
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {
+            hvx3[u] = hvx2[u]; hvx2[u] = hvx1[u]; hvx1[u] = fvx[u];
+            hvy3[u] = hvy2[u]; hvy2[u] = hvy1[u]; hvy1[u] = fvy[u];
+            hvz2[u] = hvz1[u]; hvz1[u] = fvz[u];
+            if (!qok[u]) continue;
+            const int q = tid + NT * u;
+            if (ld_xy) {
+                s_vx[s2][q] = fvx[u];
+                s_vy[s2][q] = fvy[u];
+            }
+            if (ld_z) s_vz[s2][q] = fvz[u];
+        }
+    };
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+        hvx1[u] = hvx2[u] = hvx3[u] = R(0);
+        hvy1[u] = hvy2[u] = hvy3[u] = R(0);
+        hvz1[u] = hvz2[u] = R(0);
+    }
     prefetch(k0 - 2);
+    stage_velocities(k0 - 2);
+    __syncthreads();
     for (int f = k0 - 2; f <= k1 + 1; ++f) {
         asm volatile("" : "+s"(fs));
         // take over the data of step f, start loading step f+1
-        R cvx[NQ], cvy[NQ], cvz[NQ], cxz[NQ], cxzo[NQ], cyz[NQ], cyzo[NQ], cxy[NQ], cxyo[NQ];
+        R cxz[NQ], cxzo[NQ], cyz[NQ], cyzo[NQ], cxy[NQ], cxyo[NQ];
         R cp[NR], cpo[NR], csx[NR], csxo[NR], csy[NR], csyo[NR], cc[NR];
 #pragma unroll
         for (int u = 0; u < NQ; ++u) {
-            cvx[u] = fvx[u]; cvy[u] = fvy[u]; cvz[u] = fvz[u];
             cxz[u] = fxz[u]; cxzo[u] = fxzo[u]; cyz[u] = fyz[u]; cyzo[u] = fyzo[u];
             cxy[u] = fxy[u]; cxyo[u] = fxyo[u];
         }
@@ -176,28 +207,11 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
         }
         if (f + 1 <= k1 + 1) prefetch(f + 1);
 
-        // ---- S1: velocities of plane f (vx, vy) and level f (vz) -------------
-        {
-            const bool ld_xy = f >= 0 && f < nz;
-            const bool ld_z = f >= 0 && f <= nz;
-            const int s3 = mod3(f), s2 = mod2(f);
-#pragma unroll
-            for (int u = 0; u < NQ; ++u) {
-                if (!qok[u]) continue;
-                const int q = tid + NT * u;
-                if (ld_xy) {
-                    s_vx[s3][q] = cvx[u];
-                    s_vy[s3][q] = cvy[u];
-                }
-                if (ld_z) s_vz[s2][q] = cvz[u];
-            }
-        }
-        __syncthreads();
         // ---- S2: shear trials: xz, yz at level f; xy at plane f-1 ----------
         {
             const bool do_l = f >= k0 - 1 && f >= 0 && f <= nz;
             const bool do_p = f - 1 >= k0 - 1 && f - 1 >= 0 && f - 1 < nz;
-            const int l = f, sl = mod2(l), cm = mod3(l), cp3 = mod3(l - 1), pm = mod3(f - 1);
+            const int l = f, sl = mod2(l), cm = mod2(l), cp3 = mod2(l - 1), pm = mod2(f - 1);
             const bool inner_l = l >= 1 && l <= nz - 1;
 #pragma unroll
             for (int u = 0; u < NQ; ++u) {
@@ -231,7 +245,7 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
         // ---- S3: centres of plane c = f-1 -----------------------------------
         const int c = f - 1;
         if (c >= k0 - 1 && c >= 0 && c < nz && c <= k1) {
-            const int cm = mod3(c), sc = mod2(c), sc1 = mod2(c + 1);
+            const int cm = mod2(c), sc = mod2(c), sc1 = mod2(c + 1);
 #pragma unroll
             for (int u = 0; u < NR; ++u) {
                 if (!rok[u]) continue;
@@ -355,31 +369,34 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
             }
         }
         __syncthreads();
-        // ---- S5: velocities: vx, vy at plane f-2, vz at level f-1 -----------
+        // ---- S5: velocities: vx, vy at plane f-2, vz at level f-1, at this
+        //      thread's own plane points; then S1 of step f+1 ----------------
         {
-            const int p = f - 2;
-            if (p >= k0 && p < k1) {
-                const int cm = mod3(p), sp = mod2(p), sp1 = mod2(p + 1);
-                constexpr int FW = TX + 1, FN = (TX + 1) * (TY + 1);
-                for (int r = tid; r < FN; r += NT) {
-                    const int la = 2 + r % FW, lbb = 2 + r / FW;
-                    const int q = la + W * lbb;
-                    const int i = i0 - 2 + la, j = j0 - 2 + lbb;
-                    const unsigned o = off(i, j);
+            const int p = f - 2, l = f - 1;
+            const bool do_xy = p >= k0 && p < k1;
+            const bool do_z = l >= 0 && ((l >= k0 && l < k1) || (l == nz && last_z));
+            const int sp = mod2(p), sp1 = mod2(p + 1), sl = mod2(l), sm = mod2(l - 1);
+            const bool inner_l = l >= 1 && l <= nz - 1;
+#pragma unroll
+            for (int u = 0; u < NQ; ++u) {
+                const int q = tid + NT * u;
+                const int la = q % W, lbb = q / W, i = qi[u], j = qj[u];
+                if (!qok[u] || la < 2 || lbb < 2) continue;
+                if (do_xy) {
                     const long pp = sz * p;
                     if (la < TX + 2 + hx && lbb < TY + 2 && (INT || (i <= nx && j < ny))) {      // x-face
-                        R v = s_vx[cm][q];
+                        R v = hvx3[u];
                         if (INT || (i >= 1 && i <= nx - 1)) {
                             R Rx = ((s_sxx[sp][q] - s_p[sp][q]) - (s_sxx[sp][q - 1] - s_p[sp][q - 1])) * idx
                                  + (s_nxy[sp][q + W] - s_nxy[sp][q]) * idy + (s_nxz[sp1][q] - s_nxz[sp][q]) * idz;
                             v = v + a.dtrho * Rx;
                             mmax = nmax(mmax, fabs(Rx));
                         }
-                        if (MODE != MODE_PHYS) st(nxb + F_VX * fs + pp, o, v);
+                        if (MODE != MODE_PHYS) st(nxb + F_VX * fs + pp, qo[u], v);
                         vmax = nmax(vmax, fabs(v));
                     }
                     if (la < TX + 2 && lbb < TY + 2 + hy && (INT || (i < nx && j <= ny))) {      // y-face
-                        R v = s_vy[cm][q];
+                        R v = hvy3[u];
                         if (INT || (j >= 1 && j <= ny - 1)) {
                             R Ry = (s_nxy[sp][q + 1] - s_nxy[sp][q]) * idx
                                  + ((s_syy[sp][q] - s_p[sp][q]) - (s_syy[sp][q - W] - s_p[sp][q - W])) * idy
@@ -387,21 +404,12 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
                             v = v + a.dtrho * Ry;
                             mmax = nmax(mmax, fabs(Ry));
                         }
-                        if (MODE != MODE_PHYS) st(nxb + F_VY * fs + pp, o, v);
+                        if (MODE != MODE_PHYS) st(nxb + F_VY * fs + pp, qo[u], v);
                         vmax = nmax(vmax, fabs(v));
                     }
                 }
-            }
-            const int l = f - 1;
-            if (l >= 0 && ((l >= k0 && l < k1) || (l == nz && last_z))) {
-                const int sl = mod2(l), sm = mod2(l - 1);
-                const bool inner_l = l >= 1 && l <= nz - 1;
-                for (int r = tid; r < TX * TY; r += NT) {
-                    const int la = 2 + r % TX, lbb = 2 + r / TX;
-                    const int q = la + W * lbb;
-                    const int i = i0 - 2 + la, j = j0 - 2 + lbb;
-                    if (!INT && (i >= nx || j >= ny)) continue;
-                    R v = s_vz[sl][q];
+                if (do_z && la < TX + 2 && lbb < TY + 2 && (INT || (i < nx && j < ny))) {
+                    R v = hvz2[u];
                     if (inner_l) {
                         R szu = -(s_sxx[sl][q] + s_syy[sl][q]) - s_p[sl][q];
                         R szd = -(s_sxx[sm][q] + s_syy[sm][q]) - s_p[sm][q];
@@ -410,11 +418,12 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
                         v = v + a.dtrho * Rz;
                         mmax = nmax(mmax, fabs(Rz));
                     }
-                    if (MODE != MODE_PHYS) st(nxb + F_VZ * fs + sz * l, off(i, j), v);
+                    if (MODE != MODE_PHYS) st(nxb + F_VZ * fs + sz * l, qo[u], v);
                     vmax = nmax(vmax, fabs(v));
                 }
             }
         }
+        if (f + 1 <= k1 + 1) stage_velocities(f + 1);
         __syncthreads();
     }
     if (MODE != MODE_UPDATE) {
