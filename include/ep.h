@@ -254,8 +254,10 @@ int ep_batch_init(int n, const ep_params* p, const double* const* cohesion, void
 
 /* Autotuner: picks the tile shape of each model size (models with equal
  * nx, ny share one) by timing `reps` batched sweeps of all models per
- * candidate, coordinate descent over the size classes.  The timed sweeps
- * leave the state unchanged.  Optional; the default shape is 64 x 8. */
+ * candidate, coordinate descent over the size classes; FP32-field batches
+ * get a second shape per size for their FP64 finishing sweeps, tuned the
+ * same way.  The timed sweeps leave the state unchanged.  Optional; the
+ * default shape is 64 x 8. */
 int ep_batch_tune(ep_batch* b, int reps);
 
 /* Tile shape used for model i. */

@@ -38,7 +38,8 @@ struct ep_batch {
     int n_check;
     std::vector<ep_handle*> m;
     std::vector<long> cells;
-    std::vector<int> shape;             // tile shape per model
+    std::vector<int> shape;             // tile shape per model (sweeps in the batch precision)
+    std::vector<int> shape64;           // FP32-field batches: tile shape of the FP64 finishing sweeps
     unsigned long long* red;            // n x RED_N
     double* cols;                       // n x 4
     SweepArgs<double>* tab64;           // 2 x n (parity of the ping-pong buffers)
@@ -161,8 +162,9 @@ void fill_tables(ep_batch* b)
 }
 
 // Tile lists of the running models (precision of each model's current
-// sweeps), or of all models in the batch precision when all_models is set.
-void fill_lists(ep_batch* b, bool all_models)
+// sweeps), or of all models when all_models is set, in FP32 when all32 (the
+// batch precision) else in FP64.
+void fill_lists(ep_batch* b, bool all_models, bool all32 = true)
 {
     for (int q = 0; q < 2; ++q)
         for (int s = 0; s < BATCH_SHAPES; ++s) b->h_list[q][s].clear();
@@ -171,12 +173,12 @@ void fill_lists(ep_batch* b, bool all_models)
         ep_handle* h = b->m[i];
         bool use32;
         if (all_models) {
-            use32 = b->fp32;
+            use32 = b->fp32 && all32;
         } else {
             if (!h->ctl.running) continue;
             use32 = h->ctl.use32;
         }
-        const int s = b->shape[i];
+        const int s = (use32 || !b->fp32) ? b->shape[i] : b->shape64[i];
         const int tx = kBatchTiles[s][0], ty = kBatchTiles[s][1];
         const int nbx = (h->nx + tx - 1) / tx, nby = (h->ny + ty - 1) / ty;
         auto& L = b->h_list[use32 ? 1 : 0][s];
@@ -209,7 +211,7 @@ int upload(ep_batch* b)
 bool shape_used(const ep_batch* b, int s)
 {
     for (int i = 0; i < b->n; ++i)
-        if (b->shape[i] == s) return true;
+        if (b->shape[i] == s || b->shape64[i] == s) return true;
     return false;
 }
 
@@ -350,6 +352,7 @@ int ep_batch_init(int n, const ep_params* p, const double* const* cohesion, void
         b->m.push_back(h);
         b->cells.push_back((long)p[i].nx * p[i].ny);
         b->shape.push_back(0);
+        b->shape64.push_back(0);
     }
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, 0) != hipSuccess || ncu <= 0) ncu = 256;
@@ -400,41 +403,54 @@ int ep_batch_tune(ep_batch* b, int reps)
     // models grouped by size: one tile shape per size class
     std::map<std::pair<int, int>, std::vector<int>> classes;
     for (int i = 0; i < b->n; ++i) classes[{b->m[i]->nx, b->m[i]->ny}].push_back(i);
-    auto time_config = [&](double* ms) -> int {
-        fill_lists(b, true);
-        int rc = upload(b);
+    // coordinate descent over the size classes for one precision's shapes
+    auto descend = [&](std::vector<int>& shape, bool all32) -> int {
+        auto time_config = [&](double* ms) -> int {
+            fill_lists(b, true, all32);
+            int rc = upload(b);
+            if (rc) return rc;
+            const unsigned mask = list_mask(b);
+            enqueue_sweeps(b, 1, false, false, false, mask, b->st);    // warm-up
+            BCHK(b, hipEventRecord(b->ev0, b->st));
+            enqueue_sweeps(b, reps, false, false, false, mask, b->st);
+            BCHK(b, hipEventRecord(b->ev1, b->st));
+            BCHK(b, hipEventSynchronize(b->ev1));
+            BCHK(b, hipGetLastError());
+            float t = 0.f;
+            BCHK(b, hipEventElapsedTime(&t, b->ev0, b->ev1));
+            *ms = t / reps;
+            return EP_OK;
+        };
+        double best = 0;
+        int rc = time_config(&best);
         if (rc) return rc;
-        const unsigned mask = list_mask(b);
-        enqueue_sweeps(b, 1, false, false, false, mask, b->st);    // warm-up
-        BCHK(b, hipEventRecord(b->ev0, b->st));
-        enqueue_sweeps(b, reps, false, false, false, mask, b->st);
-        BCHK(b, hipEventRecord(b->ev1, b->st));
-        BCHK(b, hipEventSynchronize(b->ev1));
-        BCHK(b, hipGetLastError());
-        float t = 0.f;
-        BCHK(b, hipEventElapsedTime(&t, b->ev0, b->ev1));
-        *ms = t / reps;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (auto& cl : classes) {
+                const int keep = shape[cl.second[0]];
+                int best_s = keep;
+                for (int s = 0; s < BATCH_SHAPES; ++s) {
+                    if (s == keep) continue;
+                    for (int i : cl.second) shape[i] = s;
+                    double t;
+                    if ((rc = time_config(&t))) return rc;
+                    if (t < best) {
+                        best = t;
+                        best_s = s;
+                    }
+                }
+                for (int i : cl.second) shape[i] = best_s;
+            }
+        }
         return EP_OK;
     };
-    double best = 0;
-    int rc = time_config(&best);
+    int rc = descend(b->shape, true);
     if (rc) return rc;
-    for (int pass = 0; pass < 2; ++pass) {
-        for (auto& cl : classes) {
-            const int keep = b->shape[cl.second[0]];
-            int best_s = keep;
-            for (int s = 0; s < BATCH_SHAPES; ++s) {
-                if (s == keep) continue;
-                for (int i : cl.second) b->shape[i] = s;
-                double t;
-                if ((rc = time_config(&t))) return rc;
-                if (t < best) {
-                    best = t;
-                    best_s = s;
-                }
-            }
-            for (int i : cl.second) b->shape[i] = best_s;
-        }
+    if (b->fp32) {
+        // the FP64 finishing sweeps have their own best shapes (8-byte LDS
+        // planes limit the workgroups per CU differently)
+        for (ep_handle* h : b->m) ensure_it64(h);
+        fill_tables(b);
+        if ((rc = descend(b->shape64, false))) return rc;
     }
     drop_graphs(b);                     // recaptured for the new shapes when used
     return EP_OK;
