@@ -46,6 +46,7 @@ class Model:
     r: float = 0.5               # Ktilde / Gtilde
     cfl: float = 0.0             # 0 -> 0.9 / sqrt(ndim)
     freeze_iter: int = 0         # 0: off; else freeze the plastic multiplier after this many iterations
+    objective: int = 0           # 1: objective (Jaumann) stress update at the start of every increment
     # weak inclusion in cohesion
     c0: float = 1.75e-3
     incl_radius: float = 0.1

@@ -654,6 +654,248 @@ double orc_sweep(orc_state* s, int mode)
 /* ------------------------------------------------------------ increment */
 static void copy_n(double* dst, const double* src, long n) { if (n > 0) memcpy(dst, src, (size_t)n * sizeof(double)); }
 
+/* ------------------------------------------------- objective stress update */
+/* Paper: Jaumann rate of stress (equations j1-j14) and the appendix on the
+ * objective stress terms.  Over one increment, explicitly, with the current
+ * velocities v:
+ *     tau <- tau + dt (tau^R - v . grad tau),     p <- p - dt v . grad p,
+ * tau^R_ij = w_ik tau_jk + w_jk tau_ik in the appendix's component form, with
+ * w_ij = (dv_i/dx_j - dv_j/dx_i) / 2 (the reading of the paper's index
+ * convention under which a rigid rotation leaves the rate zero).
+ * Discretisation (a reading; the paper gives none): w at its natural shear
+ * points (2D vertices, 3D xy/xz/yz edges) from the adjacent face
+ * velocities, zero on wall points (where the free-slip shear stress is zero
+ * too); centre terms are 4-point means of the shear products; shear-point
+ * terms use 4-point means of the centre stresses and of the other shear
+ * components; advection is first-order upwind with the velocity averaged to
+ * the point, zero gradient where the upwind neighbour lies outside the
+ * grid.  Wall shear points keep their (zero) stresses. */
+
+/* value of a field stored with extents ex x ey (x fastest) */
+static double fat(const double* f, int ex, int ey, int i, int j, int k) { return f[i + (long)ex * (j + (long)ey * k)]; }
+
+/* first-order upwind derivative of f along axis d at (i, j, k) for the
+ * advecting velocity u; 0 when the upwind neighbour does not exist */
+static double upwind(const double* f, int ex, int ey, int ez, int i, int j, int k, int d, double u, double h)
+{
+    int n[3] = {ex, ey, ez}, q[3] = {i, j, k};
+    q[d] += (u > 0.0) ? -1 : 1;
+    if (q[d] < 0 || q[d] >= n[d]) return 0.0;
+    double f0 = fat(f, ex, ey, i, j, k), f1 = fat(f, ex, ey, q[0], q[1], q[2]);
+    return (u > 0.0) ? (f0 - f1) / h : (f1 - f0) / h;
+}
+
+static void objective2d(orc_state* s)
+{
+    const int nx = s->nx, ny = s->ny;
+    const double dx = s->dx, dy = s->dy, dt = s->prm.dt;
+    const long nc = n_cells(s), nv = n_xy(s);
+    double* w = zalloc(nv);
+    double *pn = zalloc(nc), *xx = zalloc(nc), *yy = zalloc(nc), *xy = zalloc(nv);
+    for (int j = 1; j < ny; ++j)
+        for (int i = 1; i < nx; ++i)
+            w[XY2(i, j)] = 0.5 * ((s->vx[VX2(i, j)] - s->vx[VX2(i, j - 1)]) / dy
+                                - (s->vy[VY2(i, j)] - s->vy[VY2(i - 1, j)]) / dx);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const double ux = 0.5 * (s->vx[VX2(i, j)] + s->vx[VX2(i + 1, j)]);
+            const double uy = 0.5 * (s->vy[VY2(i, j)] + s->vy[VY2(i, j + 1)]);
+            double pxy = 0.0;   /* mean of tau_xy w_xy over the 4 vertices */
+            for (int b = 0; b < 2; ++b)
+                for (int a = 0; a < 2; ++a) pxy += s->txy[XY2(i + a, j + b)] * w[XY2(i + a, j + b)];
+            pxy *= 0.25;
+            const double rxx = 2.0 * pxy, ryy = -2.0 * pxy;
+#define ADV2(f) (ux * upwind(f, nx, ny, 1, i, j, 0, 0, ux, dx) + uy * upwind(f, nx, ny, 1, i, j, 0, 1, uy, dy))
+            pn[C2(i, j)] = s->p[C2(i, j)] - dt * ADV2(s->p);
+            xx[C2(i, j)] = s->txx[C2(i, j)] + dt * (rxx - ADV2(s->txx));
+            yy[C2(i, j)] = s->tyy[C2(i, j)] + dt * (ryy - ADV2(s->tyy));
+#undef ADV2
+        }
+    for (int j = 0; j <= ny; ++j)
+        for (int i = 0; i <= nx; ++i) {
+            if (i == 0 || i == nx || j == 0 || j == ny) { xy[XY2(i, j)] = s->txy[XY2(i, j)]; continue; }
+            const double ux = 0.5 * (s->vx[VX2(i, j - 1)] + s->vx[VX2(i, j)]);
+            const double uy = 0.5 * (s->vy[VY2(i - 1, j)] + s->vy[VY2(i, j)]);
+            double d = 0.0;     /* mean of tau_yy - tau_xx over the 4 centres */
+            for (int b = -1; b < 1; ++b)
+                for (int a = -1; a < 1; ++a) d += s->tyy[C2(i + a, j + b)] - s->txx[C2(i + a, j + b)];
+            d *= 0.25;
+            const double rxy = w[XY2(i, j)] * d;
+            const double adv = ux * upwind(s->txy, nx + 1, ny + 1, 1, i, j, 0, 0, ux, dx)
+                             + uy * upwind(s->txy, nx + 1, ny + 1, 1, i, j, 0, 1, uy, dy);
+            xy[XY2(i, j)] = s->txy[XY2(i, j)] + dt * (rxy - adv);
+        }
+    copy_n(s->p, pn, nc);
+    copy_n(s->txx, xx, nc);
+    copy_n(s->tyy, yy, nc);
+    copy_n(s->txy, xy, nv);
+    free(w); free(pn); free(xx); free(yy); free(xy);
+}
+
+static void objective3d(orc_state* s)
+{
+    const int nx = s->nx, ny = s->ny, nz = s->nz;
+    const double dx = s->dx, dy = s->dy, dz = s->dz, dt = s->prm.dt;
+    const long nc = n_cells(s), nxy = n_xy(s), nxz = n_xz(s), nyz = n_yz(s);
+    const double *vx = s->vx, *vy = s->vy, *vz = s->vz;
+    double *wxy = zalloc(nxy), *wxz = zalloc(nxz), *wyz = zalloc(nyz);
+    double *pn = zalloc(nc), *xx = zalloc(nc), *yy = zalloc(nc), *zz = zalloc(nc);
+    double *xy = zalloc(nxy), *xz = zalloc(nxz), *yz = zalloc(nyz);
+    /* vorticity at the interior shear points */
+    for (int k = 0; k < nz; ++k)
+        for (int j = 1; j < ny; ++j)
+            for (int i = 1; i < nx; ++i)
+                wxy[XY3(i, j, k)] = 0.5 * ((vx[VX3(i, j, k)] - vx[VX3(i, j - 1, k)]) / dy
+                                         - (vy[VY3(i, j, k)] - vy[VY3(i - 1, j, k)]) / dx);
+    for (int k = 1; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 1; i < nx; ++i)
+                wxz[XZ3(i, j, k)] = 0.5 * ((vx[VX3(i, j, k)] - vx[VX3(i, j, k - 1)]) / dz
+                                         - (vz[VZ3(i, j, k)] - vz[VZ3(i - 1, j, k)]) / dx);
+    for (int k = 1; k < nz; ++k)
+        for (int j = 1; j < ny; ++j)
+            for (int i = 0; i < nx; ++i)
+                wyz[YZ3(i, j, k)] = 0.5 * ((vy[VY3(i, j, k)] - vy[VY3(i, j, k - 1)]) / dz
+                                         - (vz[VZ3(i, j, k)] - vz[VZ3(i, j - 1, k)]) / dy);
+    /* centres */
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const double ux = 0.5 * (vx[VX3(i, j, k)] + vx[VX3(i + 1, j, k)]);
+                const double uy = 0.5 * (vy[VY3(i, j, k)] + vy[VY3(i, j + 1, k)]);
+                const double uz = 0.5 * (vz[VZ3(i, j, k)] + vz[VZ3(i, j, k + 1)]);
+                double pxy = 0.0, pxz = 0.0, pyz = 0.0;   /* 4-point means of tau_ab w_ab */
+                for (int b = 0; b < 2; ++b)
+                    for (int a = 0; a < 2; ++a) {
+                        pxy += s->txy[XY3(i + a, j + b, k)] * wxy[XY3(i + a, j + b, k)];
+                        pxz += s->txz[XZ3(i + a, j, k + b)] * wxz[XZ3(i + a, j, k + b)];
+                        pyz += s->tyz[YZ3(i, j + a, k + b)] * wyz[YZ3(i, j + a, k + b)];
+                    }
+                pxy *= 0.25; pxz *= 0.25; pyz *= 0.25;
+                const double rxx = 2.0 * (pxy + pxz);
+                const double ryy = -2.0 * (pxy - pyz);
+                const double rzz = -2.0 * (pxz + pyz);
+#define ADV3(f) (ux * upwind(f, nx, ny, nz, i, j, k, 0, ux, dx) + uy * upwind(f, nx, ny, nz, i, j, k, 1, uy, dy) \
+               + uz * upwind(f, nx, ny, nz, i, j, k, 2, uz, dz))
+                const long c = C3(i, j, k);
+                pn[c] = s->p[c] - dt * ADV3(s->p);
+                xx[c] = s->txx[c] + dt * (rxx - ADV3(s->txx));
+                yy[c] = s->tyy[c] + dt * (ryy - ADV3(s->tyy));
+                zz[c] = s->tzz[c] + dt * (rzz - ADV3(s->tzz));
+#undef ADV3
+            }
+    /* xy edges (x_i, y_j, z_k+1/2) */
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j <= ny; ++j)
+            for (int i = 0; i <= nx; ++i) {
+                const long e = XY3(i, j, k);
+                if (i == 0 || i == nx || j == 0 || j == ny) { xy[e] = s->txy[e]; continue; }
+                const double ux = 0.5 * (vx[VX3(i, j - 1, k)] + vx[VX3(i, j, k)]);
+                const double uy = 0.5 * (vy[VY3(i - 1, j, k)] + vy[VY3(i, j, k)]);
+                double uz = 0.0, d = 0.0, tyz = 0.0, w_yz = 0.0, txz = 0.0, w_xz = 0.0;
+                for (int c = 0; c < 2; ++c)
+                    for (int b = -1; b < 1; ++b)
+                        for (int a = -1; a < 1; ++a) uz += vz[VZ3(i + a, j + b, k + c)];
+                uz *= 0.125;
+                for (int b = -1; b < 1; ++b)
+                    for (int a = -1; a < 1; ++a) d += s->tyy[C3(i + a, j + b, k)] - s->txx[C3(i + a, j + b, k)];
+                for (int c = 0; c < 2; ++c)
+                    for (int a = -1; a < 1; ++a) {        /* yz edges (x_i+a+1/2, y_j, z_k+c) */
+                        tyz += s->tyz[YZ3(i + a, j, k + c)];
+                        w_yz += wyz[YZ3(i + a, j, k + c)];
+                    }
+                for (int c = 0; c < 2; ++c)
+                    for (int b = -1; b < 1; ++b) {        /* xz edges (x_i, y_j+b+1/2, z_k+c) */
+                        txz += s->txz[XZ3(i, j + b, k + c)];
+                        w_xz += wxz[XZ3(i, j + b, k + c)];
+                    }
+                d *= 0.25; tyz *= 0.25; w_yz *= 0.25; txz *= 0.25; w_xz *= 0.25;
+                const double r = wxy[e] * d + tyz * w_xz + txz * w_yz;
+                const double adv = ux * upwind(s->txy, nx + 1, ny + 1, nz, i, j, k, 0, ux, dx)
+                                 + uy * upwind(s->txy, nx + 1, ny + 1, nz, i, j, k, 1, uy, dy)
+                                 + uz * upwind(s->txy, nx + 1, ny + 1, nz, i, j, k, 2, uz, dz);
+                xy[e] = s->txy[e] + dt * (r - adv);
+            }
+    /* xz edges (x_i, y_j+1/2, z_k) */
+    for (int k = 0; k <= nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i <= nx; ++i) {
+                const long e = XZ3(i, j, k);
+                if (i == 0 || i == nx || k == 0 || k == nz) { xz[e] = s->txz[e]; continue; }
+                const double ux = 0.5 * (vx[VX3(i, j, k - 1)] + vx[VX3(i, j, k)]);
+                const double uz = 0.5 * (vz[VZ3(i - 1, j, k)] + vz[VZ3(i, j, k)]);
+                double uy = 0.0, d = 0.0, tyz = 0.0, w_yz = 0.0, txy = 0.0, w_xy = 0.0;
+                for (int c = -1; c < 1; ++c)
+                    for (int b = 0; b < 2; ++b)
+                        for (int a = -1; a < 1; ++a) uy += vy[VY3(i + a, j + b, k + c)];
+                uy *= 0.125;
+                for (int c = -1; c < 1; ++c)
+                    for (int a = -1; a < 1; ++a) d += s->tzz[C3(i + a, j, k + c)] - s->txx[C3(i + a, j, k + c)];
+                for (int b = 0; b < 2; ++b)
+                    for (int a = -1; a < 1; ++a) {        /* yz edges (x_i+a+1/2, y_j+b, z_k) */
+                        tyz += s->tyz[YZ3(i + a, j + b, k)];
+                        w_yz += wyz[YZ3(i + a, j + b, k)];
+                    }
+                for (int c = -1; c < 1; ++c)
+                    for (int b = 0; b < 2; ++b) {         /* xy edges (x_i, y_j+b, z_k+c+1/2) */
+                        txy += s->txy[XY3(i, j + b, k + c)];
+                        w_xy += wxy[XY3(i, j + b, k + c)];
+                    }
+                d *= 0.25; tyz *= 0.25; w_yz *= 0.25; txy *= 0.25; w_xy *= 0.25;
+                const double r = wxz[e] * d + tyz * w_xy - txy * w_yz;
+                const double adv = ux * upwind(s->txz, nx + 1, ny, nz + 1, i, j, k, 0, ux, dx)
+                                 + uy * upwind(s->txz, nx + 1, ny, nz + 1, i, j, k, 1, uy, dy)
+                                 + uz * upwind(s->txz, nx + 1, ny, nz + 1, i, j, k, 2, uz, dz);
+                xz[e] = s->txz[e] + dt * (r - adv);
+            }
+    /* yz edges (x_i+1/2, y_j, z_k) */
+    for (int k = 0; k <= nz; ++k)
+        for (int j = 0; j <= ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const long e = YZ3(i, j, k);
+                if (j == 0 || j == ny || k == 0 || k == nz) { yz[e] = s->tyz[e]; continue; }
+                const double uy = 0.5 * (vy[VY3(i, j, k - 1)] + vy[VY3(i, j, k)]);
+                const double uz = 0.5 * (vz[VZ3(i, j - 1, k)] + vz[VZ3(i, j, k)]);
+                double ux = 0.0, d = 0.0, txy = 0.0, w_xy = 0.0, txz = 0.0, w_xz = 0.0;
+                for (int c = -1; c < 1; ++c)
+                    for (int b = -1; b < 1; ++b)
+                        for (int a = 0; a < 2; ++a) ux += vx[VX3(i + a, j + b, k + c)];
+                ux *= 0.125;
+                for (int c = -1; c < 1; ++c)
+                    for (int b = -1; b < 1; ++b) d += s->tzz[C3(i, j + b, k + c)] - s->tyy[C3(i, j + b, k + c)];
+                for (int c = -1; c < 1; ++c)
+                    for (int a = 0; a < 2; ++a) {         /* xy edges (x_i+a, y_j, z_k+c+1/2) */
+                        txy += s->txy[XY3(i + a, j, k + c)];
+                        w_xy += wxy[XY3(i + a, j, k + c)];
+                    }
+                for (int b = -1; b < 1; ++b)
+                    for (int a = 0; a < 2; ++a) {         /* xz edges (x_i+a, y_j+b+1/2, z_k) */
+                        txz += s->txz[XZ3(i + a, j + b, k)];
+                        w_xz += wxz[XZ3(i + a, j + b, k)];
+                    }
+                d *= 0.25; txy *= 0.25; w_xy *= 0.25; txz *= 0.25; w_xz *= 0.25;
+                const double r = wyz[e] * d - txy * w_xz - txz * w_xy;
+                const double adv = ux * upwind(s->tyz, nx, ny + 1, nz + 1, i, j, k, 0, ux, dx)
+                                 + uy * upwind(s->tyz, nx, ny + 1, nz + 1, i, j, k, 1, uy, dy)
+                                 + uz * upwind(s->tyz, nx, ny + 1, nz + 1, i, j, k, 2, uz, dz);
+                yz[e] = s->tyz[e] + dt * (r - adv);
+            }
+    copy_n(s->p, pn, nc);
+    copy_n(s->txx, xx, nc);
+    copy_n(s->tyy, yy, nc);
+    copy_n(s->tzz, zz, nc);
+    copy_n(s->txy, xy, nxy);
+    copy_n(s->txz, xz, nxz);
+    copy_n(s->tyz, yz, nyz);
+    free(wxy); free(wxz); free(wyz); free(pn); free(xx); free(yy); free(zz); free(xy); free(xz); free(yz);
+}
+
+void orc_objective_update(orc_state* s)
+{
+    if (s->ndim == 2) objective2d(s);
+    else objective3d(s);
+}
+
 static void save_start(orc_state* s)
 {
     long nc = n_cells(s);
@@ -775,6 +1017,9 @@ int orc_load_step(orc_state* s, orc_stats* st)
     if (!st) st = &dummy;
     memset(st, 0, sizeof(*st));
     s->hist_len = 0;
+    /* objective stress update of the carried stresses with the velocities
+     * of the previous increment; the result is this increment's start */
+    if (s->prm.objective) orc_objective_update(s);
     save_start(s);
     set_wall_velocities(s);
 

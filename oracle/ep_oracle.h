@@ -34,6 +34,8 @@ typedef struct orc_params {
     double re, r, cfl;       /* PT numerical Reynolds number, Ktilde/Gtilde, Courant number */
     int    freeze_iter;      /* 0: off; else freeze Lambda at the first check at or after
                                 this iteration that has not converged */
+    int    objective;        /* 1: objective (Jaumann) stress update at the start of every
+                                increment (orc_objective_update); 0: off */
 } orc_params;
 
 typedef struct orc_stats {
@@ -65,6 +67,15 @@ enum {
 typedef struct orc_state orc_state;
 
 orc_state* orc_create(const orc_params* prm, const double* cohesion);
+/* Objective stress update (paper: Jaumann rate of stress, equations j1-j14,
+ * and the appendix on the objective stress terms), explicit over one
+ * increment with the current velocities:
+ *   tau <- tau + dt (tau^R - v.grad tau),  p <- p - dt v.grad p,
+ * tau^R from the vorticity w_ij = (dv_i/dx_j - dv_j/dx_i)/2 (the reading of
+ * the paper's index convention under which the rate is objective);
+ * first-order upwind advection.  orc_load_step applies it to the carried
+ * stresses before the increment when prm.objective is set. */
+void orc_objective_update(orc_state* s);
 void   orc_free(orc_state* s);
 long   orc_field_size(const orc_state* s, int field);
 int    orc_get(const orc_state* s, int field, double* out);

@@ -34,7 +34,7 @@ class OrcParams(C.Structure):
         ("erate", C.c_double * 3), ("tol", C.c_double),
         ("max_iter", C.c_int), ("n_check", C.c_int),
         ("re", C.c_double), ("r", C.c_double), ("cfl", C.c_double),
-        ("freeze_iter", C.c_int),
+        ("freeze_iter", C.c_int), ("objective", C.c_int),
     ]
 
 
@@ -74,6 +74,7 @@ def lib():
         L.orc_scalars.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
         L.orc_history.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int]
         L.orc_history_len.argtypes = [C.c_void_p]
+        L.orc_objective_update.argtypes = [C.c_void_p]
         L.orc_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -91,6 +92,7 @@ def params_from_model(m) -> OrcParams:
     p.tol, p.max_iter, p.n_check = m.tol, m.max_iter, m.n_check
     p.re, p.r, p.cfl = m.re, m.r, m.cfl
     p.freeze_iter = m.freeze_iter
+    p.objective = m.objective
     return p
 
 
@@ -144,6 +146,12 @@ class Oracle:
     def fields(self, names=None) -> Dict[str, np.ndarray]:
         names = names or [n for n in FIELDS if lib().orc_field_size(self._h, FIELD_ID[n]) > 0]
         return {n: self.get(n) for n in names}
+
+    def objective_update(self) -> None:
+        """Objective (Jaumann) update of the current stresses with the current
+        velocities over one increment (what load_step applies first when the
+        model's objective flag is set)."""
+        lib().orc_objective_update(self._h)
 
     def sweep(self, physical: bool = False) -> float:
         return lib().orc_sweep(self._h, 1 if physical else 0)

@@ -1,0 +1,233 @@
+"""Pins of the oracle's objective (Jaumann) stress update (paper: Jaumann rate
+of stress, equations j1-j14, and the appendix on the objective stress terms).
+
+Each check is against something other than the oracle's own formulas:
+  - a rigid rotation of a homogeneous stress: the stress must co-rotate, so the
+    update divided by dt equals the time derivative of Q(t) tau Q(t)^T with
+    Q = expm(W t) (central difference of the exact rotation); in 3D about a
+    general axis and with all six components set, so every term of every
+    component (and its sign) is exercised;
+  - uniform translation of linear fields: first-order upwind transport is
+    exact for a linear profile (away from the inflow edge);
+  - pure shear (no vorticity) and zero velocity leave a homogeneous state
+    unchanged; the update keeps the stress deviator trace-free.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.linalg import expm
+
+from ep_workloads import Model
+from oracle.oracle import Oracle
+
+pytestmark = pytest.mark.filterwarnings("ignore")
+
+
+def coords(m):
+    """Face, centre and node coordinates of the centred domain."""
+    dx, dy = m.lx / m.nx, m.ly / m.ny
+    xn = -m.lx / 2 + dx * np.arange(m.nx + 1)
+    yn = -m.ly / 2 + dy * np.arange(m.ny + 1)
+    xc, yc = xn[:-1] + dx / 2, yn[:-1] + dy / 2
+    if m.ndim == 2:
+        return xn, yn, xc, yc
+    dz = m.lz / m.nz
+    zn = -m.lz / 2 + dz * np.arange(m.nz + 1)
+    return xn, yn, zn, xc, yc, xn[:-1] + dx / 2, zn[:-1] + dz / 2
+
+
+def grid(*axes):
+    """Arrays over the given 1D axes, x fastest (index order z, y, x)."""
+    g = np.meshgrid(*axes[::-1], indexing="ij")
+    return g[::-1]
+
+
+def set_velocity(o, m, fx, fy, fz=None):
+    if m.ndim == 2:
+        xn, yn, xc, yc = coords(m)
+        X, Y = grid(xn, yc)
+        o.set("vx", fx(X, Y, 0 * X))
+        X, Y = grid(xc, yn)
+        o.set("vy", fy(X, Y, 0 * X))
+        return
+    xn, yn, zn, xc, yc, _, zc = coords(m)
+    X, Y, Z = grid(xn, yc, zc)
+    o.set("vx", fx(X, Y, Z))
+    X, Y, Z = grid(xc, yn, zc)
+    o.set("vy", fy(X, Y, Z))
+    X, Y, Z = grid(xc, yc, zn)
+    o.set("vz", fz(X, Y, Z))
+
+
+def rot_rate(W, tau, h=1e-4):
+    """d/dt of expm(W t) tau expm(W t)^T at t = 0 (central difference of the
+    exact rotation; error O(h^2 |W|^3 |tau|))."""
+    qp, qm = expm(W * h), expm(-W * h)
+    return (qp @ tau @ qp.T - qm @ tau @ qm.T) / (2 * h)
+
+
+def test_rigid_rotation_2d_corotates_the_stress():
+    m = Model(ndim=2, nx=12, ny=10, dt=1e-3)
+    om = 0.7
+    o = Oracle(m)
+    set_velocity(o, m, lambda x, y, z: -om * y, lambda x, y, z: om * x)
+    sxx, syy, sxy = 0.3, -0.1, 0.25
+    nc, nv = m.nx * m.ny, (m.nx + 1) * (m.ny + 1)
+    o.set("txx", np.full(nc, sxx))
+    o.set("tyy", np.full(nc, syy))
+    o.set("txy", np.full(nv, sxy))
+    o.set("p", np.full(nc, 0.4))
+    o.objective_update()
+    # spin of v = omega x r: W = [[0, -om], [om, 0]]
+    W = np.array([[0.0, -om], [om, 0.0]])
+    rate = rot_rate(W, np.array([[sxx, sxy], [sxy, syy]]))
+    txx = o.get("txx").reshape(m.ny, m.nx)[1:-1, 1:-1]
+    tyy = o.get("tyy").reshape(m.ny, m.nx)[1:-1, 1:-1]
+    txy = o.get("txy").reshape(m.ny + 1, m.nx + 1)[1:-1, 1:-1]
+    np.testing.assert_allclose((txx - sxx) / m.dt, rate[0, 0], rtol=1e-6, atol=1e-9)
+    np.testing.assert_allclose((tyy - syy) / m.dt, rate[1, 1], rtol=1e-6, atol=1e-9)
+    np.testing.assert_allclose((txy - sxy) / m.dt, rate[0, 1], rtol=1e-6, atol=1e-9)
+    assert np.allclose(o.get("p"), 0.4, rtol=0, atol=1e-15)    # a scalar does not rotate
+    o.close()
+
+
+@pytest.mark.parametrize("axis", [(0.0, 0.0, 1.0), (1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.3, -0.5, 0.8)],
+                         ids=["z", "x", "y", "general"])
+def test_rigid_rotation_3d_corotates_the_stress(axis):
+    m = Model(ndim=3, nx=8, ny=7, nz=9, dt=1e-3)
+    Om = 0.9 * np.array(axis) / np.linalg.norm(axis)
+    ox, oy, oz = Om
+    o = Oracle(m)
+    # v = Omega x r
+    set_velocity(o, m, lambda x, y, z: oy * z - oz * y, lambda x, y, z: oz * x - ox * z,
+                 lambda x, y, z: ox * y - oy * x)
+    tau = np.array([[0.3, 0.21, -0.13], [0.21, -0.1, 0.17], [-0.13, 0.17, -0.2]])
+    nc = m.nx * m.ny * m.nz
+    sizes = {"txy": (m.nx + 1) * (m.ny + 1) * m.nz, "txz": (m.nx + 1) * m.ny * (m.nz + 1),
+             "tyz": m.nx * (m.ny + 1) * (m.nz + 1)}
+    o.set("txx", np.full(nc, tau[0, 0]))
+    o.set("tyy", np.full(nc, tau[1, 1]))
+    o.set("tzz", np.full(nc, tau[2, 2]))
+    o.set("txy", np.full(sizes["txy"], tau[0, 1]))
+    o.set("txz", np.full(sizes["txz"], tau[0, 2]))
+    o.set("tyz", np.full(sizes["tyz"], tau[1, 2]))
+    o.objective_update()
+    W = np.array([[0.0, -oz, oy], [oz, 0.0, -ox], [-oy, ox, 0.0]])   # grad v, antisymmetric
+    rate = rot_rate(W, tau)
+    nx, ny, nz = m.nx, m.ny, m.nz
+    inner = (slice(2, -2), slice(2, -2), slice(2, -2))
+    got = {
+        "txx": o.get("txx").reshape(nz, ny, nx)[inner], "tyy": o.get("tyy").reshape(nz, ny, nx)[inner],
+        "tzz": o.get("tzz").reshape(nz, ny, nx)[inner],
+        "txy": o.get("txy").reshape(nz, ny + 1, nx + 1)[inner],
+        "txz": o.get("txz").reshape(nz + 1, ny, nx + 1)[inner],
+        "tyz": o.get("tyz").reshape(nz + 1, ny + 1, nx)[inner],
+    }
+    for name, (a, b) in {"txx": (0, 0), "tyy": (1, 1), "tzz": (2, 2), "txy": (0, 1), "txz": (0, 2),
+                         "tyz": (1, 2)}.items():
+        np.testing.assert_allclose((got[name] - tau[a, b]) / m.dt, rate[a, b], rtol=1e-6, atol=1e-9,
+                                   err_msg=name)
+    o.close()
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+@pytest.mark.parametrize("sign", [1.0, -1.0], ids=["pos", "neg"])
+def test_uniform_translation_transports_linear_fields_exactly(ndim, sign):
+    m = Model(ndim=ndim, nx=10, ny=9, nz=8, dt=2e-3)
+    U, V, Wz = sign * 0.6, sign * -0.4, sign * 0.5
+    o = Oracle(m)
+    set_velocity(o, m, lambda x, y, z: U + 0 * x, lambda x, y, z: V + 0 * x, lambda x, y, z: Wz + 0 * x)
+    if ndim == 2:
+        xn, yn, xc, yc = coords(m)
+        X, Y = grid(xc, yc)
+        Z = 0 * X
+    else:
+        xn, yn, zn, xc, yc, _, zc = coords(m)
+        X, Y, Z = grid(xc, yc, zc)
+    a, b, c = 0.7, -0.3, 0.45
+    f = 0.1 + a * X + b * Y + c * Z
+    o.set("p", f)
+    o.set("txx", 2 * f)
+    o.objective_update()
+    drift = U * a + V * b + (Wz * c if ndim == 3 else 0.0)
+    sl = tuple([slice(1, -1)] * ndim)
+    got_p = o.get("p").reshape(f.shape)[sl]
+    got_t = o.get("txx").reshape(f.shape)[sl]
+    np.testing.assert_allclose(got_p, f[sl] - m.dt * drift, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(got_t, 2 * f[sl] - 2 * m.dt * drift, rtol=0, atol=1e-13)
+    o.close()
+
+
+def test_xy_shear_point_transport_2d():
+    """Interior vertices carry tau_xy with the vertex-averaged velocity."""
+    m = Model(ndim=2, nx=10, ny=9, dt=2e-3)
+    U, V = 0.5, 0.3
+    o = Oracle(m)
+    set_velocity(o, m, lambda x, y, z: U + 0 * x, lambda x, y, z: V + 0 * x)
+    xn, yn, xc, yc = coords(m)
+    X, Y = grid(xn, yn)
+    f = 0.2 + 0.6 * X - 0.8 * Y
+    o.set("txy", f)
+    o.objective_update()
+    got = o.get("txy").reshape(f.shape)
+    inner = (slice(2, -1), slice(2, -1))
+    np.testing.assert_allclose(got[inner], f[inner] - m.dt * (U * 0.6 + V * -0.8), rtol=0, atol=1e-13)
+    # wall vertices keep their values (free-slip walls carry no shear stress)
+    assert np.array_equal(got[0, :], f[0, :]) and np.array_equal(got[:, -1], f[:, -1])
+    o.close()
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_pure_shear_and_rest_leave_homogeneous_state(ndim):
+    m = Model(ndim=ndim, nx=9, ny=8, nz=7, dt=1e-3)
+    for vel in ("rest", "pure shear"):
+        o = Oracle(m)
+        if vel == "pure shear":
+            set_velocity(o, m, lambda x, y, z: 1.0 * x, lambda x, y, z: -1.0 * y, lambda x, y, z: 0 * z)
+        before = {}
+        for k in (["p", "txx", "tyy", "txy"] + (["tzz", "txz", "tyz"] if ndim == 3 else [])):
+            n = o.get(k).size
+            val = {"p": 0.3, "txx": 0.2, "tyy": -0.15, "tzz": -0.05, "txy": 0.1, "txz": -0.07, "tyz": 0.04}[k]
+            o.set(k, np.full(n, val))
+            before[k] = val
+        o.objective_update()
+        for k, val in before.items():
+            assert np.allclose(o.get(k), val, rtol=0, atol=1e-15), (vel, k)
+        o.close()
+
+
+def test_update_keeps_the_3d_deviator_trace_free():
+    m = Model(ndim=3, nx=7, ny=6, nz=8, dt=1e-3)
+    r = np.random.Generator(np.random.PCG64(11))
+    o = Oracle(m)
+    for k in ("vx", "vy", "vz", "txy", "txz", "tyz", "p"):
+        o.set(k, r.standard_normal(o.get(k).size))
+    txx = r.standard_normal(o.get("txx").size)
+    tyy = r.standard_normal(txx.size)
+    o.set("txx", txx)
+    o.set("tyy", tyy)
+    o.set("tzz", -(txx + tyy))
+    o.objective_update()
+    tr = o.get("txx") + o.get("tyy") + o.get("tzz")
+    assert np.abs(tr).max() < 1e-13
+    o.close()
+
+
+def test_load_step_applies_the_update_to_the_carried_stresses():
+    """With the objective flag, an increment starts from the updated stresses:
+    the increment-start copies equal one update of the previous state."""
+    m = Model(ndim=2, nx=15, ny=13, dt=1e-4, tol=1e-8, steps=3, objective=1, incl_radius=0.2)
+    a, b = Oracle(m), Oracle(m.with_(objective=0))
+    for _ in range(2):
+        a.load_step()
+    names = ["vx", "vy", "p", "txx", "tyy", "txy"]
+    st = a.fields(names)
+    for k in names:
+        b.set(k, st[k])
+    b.objective_update()
+    a.load_step()
+    for k in ("p", "txx", "tyy", "txy"):
+        np.testing.assert_allclose(a.get(k + "_old"), b.get(k), rtol=0, atol=1e-15, err_msg=k)
+    a.close()
+    b.close()
