@@ -308,6 +308,8 @@ def main():
     ap.add_argument("--sweep", default="auto", choices=["auto", "fused", "unfused"])
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-objective", action="store_true",
+                    help="skip timing the objective stress update (outside the timed region)")
     ap.add_argument("--no-warm-compare", action="store_true",
                     help="skip the small plain vs learned-warm-start comparison of 3D workloads")
     args = ap.parse_args()
@@ -369,6 +371,29 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": ("fp32" if use32 else "fp64") + " PT sweep", "sweeps_timed": nsw,
             "avg_sweep_ms": round(ms, 4), "algorithmic_bytes_per_sweep": a_dom}
+
+    # objective (Jaumann) stress update of the carried state, once per
+    # increment when enabled (off in this workload): timed on its own, after
+    # the timed region, on the state the increments left
+    obj = None
+    if not args.no_objective:
+        reps = 10
+        s.objective_update()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(s.stream)
+        for _ in range(reps):
+            s.objective_update()
+        ev1.record(s.stream)
+        ev1.synchronize()
+        t_obj = ev0.elapsed_time(ev1) / reps
+        # update kernel: 3 velocities + 6 (3D) / 4 (2D) stresses read, the
+        # stresses written, FP64; then the copy into the iteration fields
+        nst = 6 if m.ndim == 3 else 4
+        a_obj = (m.ndim + 2 * nst) * 8 * m.n_cells
+        obj = {"ms": round(t_obj, 4), "algorithmic_bytes": a_obj, "copy_bytes": 2 * nst * 8 * m.n_cells,
+               "GB/s": round((a_obj + 2 * nst * 8 * m.n_cells) / (t_obj * 1e-3) / 1e9, 1),
+               "frac": round((a_obj + 2 * nst * 8 * m.n_cells) / (t_obj * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        log("objective update", obj)
     s.close()
 
     cpu = None
@@ -399,7 +424,7 @@ def main():
         "iters_per_step": round(iters / max(args.steps, 1), 1),
         "iters_fp32_per_step": round(it32 / max(args.steps, 1), 1),
         "failed_steps": sum(1 for st in stats if st["status"] != 0),
-        "roofline": roof, "cpu_baseline": cpu, "warm_start": warm,
+        "roofline": roof, "cpu_baseline": cpu, "warm_start": warm, "objective_update": obj,
     }
     print(json.dumps(out), flush=True)
 

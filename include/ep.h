@@ -94,6 +94,13 @@ typedef struct ep_params {
                                 iteration removes rough errors of a guess within few sweeps,
                                 so a larger value can pay off; an increment that fails from
                                 the guess is redone from the plain guess */
+    int    objective;        /* 1: objective stress update at the start of every increment
+                                (Jaumann rate of stress, equations j1-j14 and the appendix
+                                on the objective stress terms): the carried stresses become
+                                tau + dt (tau^R - v.grad tau) and p - dt v.grad p with the
+                                previous increment's velocities, vorticity
+                                w_ij = (dv_i/dx_j - dv_j/dx_i)/2 at the shear points,
+                                first-order upwind advection, explicit over dt; 0: off */
 } ep_params;
 
 typedef struct ep_step_stats {
@@ -195,6 +202,17 @@ int ep_sweep(ep_handle* h, int n, double* resid);
 
 /* FP64 norms of the current state (no state change).  Synchronous. */
 int ep_residual(ep_handle* h, ep_residual_info* r);
+
+/* Objective stress update of the current state with its current velocities,
+ * in place (paper: Jaumann rate of stress, equations j1-j14, and the
+ * appendix on the objective stress terms; the discretisation of the
+ * `objective` parameter): tau <- tau + dt (tau^R - v.grad tau),
+ * p <- p - dt v.grad p.  ep_load_step applies the same update first when
+ * the handle's `objective` parameter is set; here it runs whatever that
+ * parameter.  The increment-start fields (EP_F_*_OLD) then hold the updated
+ * stresses, as after an increment prologue.  Asynchronous on the handle's
+ * stream. */
+int ep_objective_update(ep_handle* h);
 
 /* Copy one field between the device state and a host FP64 array of exactly
  * ep_field_shape() elements.  dir = EP_GET or EP_SET.  EP_SET of TZZ(_OLD) is

@@ -60,6 +60,7 @@ int validate(const ep_params* p)
     if (p->precision != EP_FP64 && p->precision != EP_FP32_FIELDS) return EP_EINVAL;
     if (p->sweep < EP_SWEEP_AUTO || p->sweep > EP_SWEEP_UNFUSED) return EP_EINVAL;
     if (p->freeze_iter < 0 || p->guess_accept < 0) return EP_EINVAL;
+    if (p->objective != 0 && p->objective != 1) return EP_EINVAL;
     return EP_OK;
 }
 
@@ -433,6 +434,27 @@ double seconds_since(const StepCtl& c)
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - c.t0).count();
 }
 
+// Objective update of the FP64 state in place, through the increment-start
+// arrays (which end up holding the updated stresses too).
+void objective_update(ep_handle* h)
+{
+    ensure_it64(h);
+    double** it = h->it64[h->cur64];
+    const int map[O_N] = {F_P, F_TXX, F_TYY, F_TXY, F_TXZ, F_TYZ};
+    ObjectiveArgs oa{};
+    for (int f = 0; f < F_NIT; ++f) oa.in[f] = it[f];
+    for (int o = 0; o < O_N; ++o) oa.out[map[o]] = h->old64[o];
+    oa.dx = h->dx;
+    oa.dy = h->dy;
+    oa.dz = h->dz;
+    oa.dt = h->prm.dt;
+    launch_objective(h->g, oa, h->st);
+    for (int o = 0; o < O_N; ++o)
+        if (h->old64[o]) launch_copy(it[map[o]], h->old64[o], h->nelem, h->st);
+    h->it32_valid = false;
+    h->old32_valid = false;
+}
+
 void step_begin(ep_handle* h, ep_step_stats* st)
 {
     StepCtl& c = h->ctl;
@@ -451,8 +473,14 @@ void step_begin(ep_handle* h, ep_step_stats* st)
     ensure_it64(h);
     double** it = h->it64[h->cur64];
     const int map[O_N] = {F_P, F_TXX, F_TYY, F_TXY, F_TXZ, F_TYZ};
-    for (int o = 0; o < O_N; ++o)
-        if (h->old64[o]) launch_copy(h->old64[o], it[map[o]], h->nelem, h->st);
+    if (h->prm.objective) {
+        // objective update of the carried stresses with the previous
+        // increment's velocities: the result is this increment's start
+        objective_update(h);
+    } else {
+        for (int o = 0; o < O_N; ++o)
+            if (h->old64[o]) launch_copy(h->old64[o], it[map[o]], h->nelem, h->st);
+    }
     launch_set_walls(h->g, it[F_VX], it[F_VY], it[F_VZ], h->prm.erate, h->prm.lx, h->prm.ly, h->prm.lz, h->st);
     for (int d = 0; d < h->ndim; ++d) launch_copy(h->vstart64[d], it[F_VX + d], h->nelem, h->st);
     h->it32_valid = false;
@@ -867,6 +895,14 @@ int ep_residual(ep_handle* h, ep_residual_info* r)
     launch_sweep<double>(h, true, h->cur64, MODE_PHYS);
     if ((rc = read_red(h, red))) return rc;
     r->physical = red[RED_MOM];
+    return EP_OK;
+}
+
+int ep_objective_update(ep_handle* h)
+{
+    if (!h) return EP_EINVAL;
+    objective_update(h);
+    HIPCHK(h, hipGetLastError());
     return EP_OK;
 }
 

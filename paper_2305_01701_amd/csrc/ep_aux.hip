@@ -225,6 +225,205 @@ __global__ void k_columns(AuxGrid g, const double* p, const double* txx, double 
     if (threadIdx.x == 0) out[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
+// ------------------------------------------------ objective stress update
+// tau^R in the component form of the paper's appendix with the vorticity
+// w_ab = (dv_a/dx_b - dv_b/dx_a)/2 at its natural shear points (2D
+// vertices, 3D xy/xz/yz edges), zero on wall points; centre terms are
+// 4-point means of the shear products, shear-point terms use 4-point means
+// of the centre stresses and of the other shear components; first-order
+// upwind advection with the velocity averaged to the point, zero gradient
+// where the upwind neighbour lies outside the field's grid.  Wall shear
+// points keep their stresses.  All points share the padded index
+// i + sy j + sz k.
+
+// first-order upwind derivative along one axis: n = extent of the field on
+// that axis, st = index stride, idx = the point's index on the axis
+__device__ __forceinline__ double upwind(const double* f, long e, int idx, int n, long st, double u, double h)
+{
+    const int m = idx + (u > 0.0 ? -1 : 1);
+    if (m < 0 || m >= n) return 0.0;
+    const double f0 = f[e], f1 = f[e + (m - idx) * st];
+    return u > 0.0 ? (f0 - f1) / h : (f1 - f0) / h;
+}
+
+__global__ void k_objective_2d(AuxGrid g, ObjectiveArgs a)
+{
+    const int nx = g.nx, ny = g.ny;
+    const long sy = g.sy;
+    const double *vx = a.in[F_VX], *vy = a.in[F_VY], *p = a.in[F_P], *txx = a.in[F_TXX], *tyy = a.in[F_TYY],
+                 *txy = a.in[F_TXY];
+    const double dx = a.dx, dy = a.dy, dt = a.dt;
+    auto w = [&](int i, int j) -> double {        // vertex vorticity, 0 on walls
+        if (i <= 0 || i >= nx || j <= 0 || j >= ny) return 0.0;
+        const long q = i + sy * j;
+        return 0.5 * ((vx[q] - vx[q - sy]) / dy - (vy[q] - vy[q - 1]) / dx);
+    };
+    const long n = (long)(nx + 1) * (ny + 1);
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(t % (nx + 1)), j = (int)(t / (nx + 1));
+        const long e = i + sy * j;
+        if (i < nx && j < ny) {                   // centre
+            const double ux = 0.5 * (vx[e] + vx[e + 1]), uy = 0.5 * (vy[e] + vy[e + sy]);
+            const double pxy = 0.25 * (txy[e] * w(i, j) + txy[e + 1] * w(i + 1, j) + txy[e + sy] * w(i, j + 1)
+                                       + txy[e + sy + 1] * w(i + 1, j + 1));
+            auto adv = [&](const double* f) {
+                return ux * upwind(f, e, i, nx, 1, ux, dx) + uy * upwind(f, e, j, ny, sy, uy, dy);
+            };
+            a.out[F_P][e] = p[e] - dt * adv(p);
+            a.out[F_TXX][e] = txx[e] + dt * (2.0 * pxy - adv(txx));
+            a.out[F_TYY][e] = tyy[e] + dt * (-2.0 * pxy - adv(tyy));
+        }
+        if (i == 0 || i == nx || j == 0 || j == ny) {
+            a.out[F_TXY][e] = txy[e];
+        } else {                                  // interior vertex
+            const double ux = 0.5 * (vx[e - sy] + vx[e]), uy = 0.5 * (vy[e - 1] + vy[e]);
+            const double d = 0.25 * ((tyy[e - sy - 1] - txx[e - sy - 1]) + (tyy[e - sy] - txx[e - sy])
+                                     + (tyy[e - 1] - txx[e - 1]) + (tyy[e] - txx[e]));
+            const double adv = ux * upwind(txy, e, i, nx + 1, 1, ux, dx) + uy * upwind(txy, e, j, ny + 1, sy, uy, dy);
+            a.out[F_TXY][e] = txy[e] + dt * (w(i, j) * d - adv);
+        }
+    }
+}
+
+__global__ void k_objective_3d(AuxGrid g, ObjectiveArgs a)
+{
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const long sy = g.sy, sz = g.sz;
+    const double *vx = a.in[F_VX], *vy = a.in[F_VY], *vz = a.in[F_VZ], *p = a.in[F_P], *txx = a.in[F_TXX],
+                 *tyy = a.in[F_TYY], *txy = a.in[F_TXY], *txz = a.in[F_TXZ], *tyz = a.in[F_TYZ];
+    const double dx = a.dx, dy = a.dy, dz = a.dz, dt = a.dt;
+    // vorticity at the shear points, 0 on wall points
+    auto wxy = [&](int i, int j, int k) -> double {
+        if (i <= 0 || i >= nx || j <= 0 || j >= ny) return 0.0;
+        const long q = i + sy * j + sz * k;
+        return 0.5 * ((vx[q] - vx[q - sy]) / dy - (vy[q] - vy[q - 1]) / dx);
+    };
+    auto wxz = [&](int i, int j, int k) -> double {
+        if (i <= 0 || i >= nx || k <= 0 || k >= nz) return 0.0;
+        const long q = i + sy * j + sz * k;
+        return 0.5 * ((vx[q] - vx[q - sz]) / dz - (vz[q] - vz[q - 1]) / dx);
+    };
+    auto wyz = [&](int i, int j, int k) -> double {
+        if (j <= 0 || j >= ny || k <= 0 || k >= nz) return 0.0;
+        const long q = i + sy * j + sz * k;
+        return 0.5 * ((vy[q] - vy[q - sz]) / dz - (vz[q] - vz[q - sy]) / dy);
+    };
+    auto tzz = [&](long q) { return -(txx[q] + tyy[q]); };
+    auto at = [&](int i, int j, int k) -> long { return i + sy * j + sz * k; };
+    const long n = (long)(nx + 1) * (ny + 1) * (nz + 1);
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(t % (nx + 1)), j = (int)((t / (nx + 1)) % (ny + 1)), k = (int)(t / ((long)(nx + 1) * (ny + 1)));
+        const long e = at(i, j, k);
+        if (i < nx && j < ny && k < nz) {         // centre
+            const double ux = 0.5 * (vx[e] + vx[e + 1]), uy = 0.5 * (vy[e] + vy[e + sy]), uz = 0.5 * (vz[e] + vz[e + sz]);
+            double pxy = 0.0, pxz = 0.0, pyz = 0.0;
+            for (int b = 0; b < 2; ++b)
+                for (int c = 0; c < 2; ++c) {
+                    pxy += txy[at(i + c, j + b, k)] * wxy(i + c, j + b, k);
+                    pxz += txz[at(i + c, j, k + b)] * wxz(i + c, j, k + b);
+                    pyz += tyz[at(i, j + c, k + b)] * wyz(i, j + c, k + b);
+                }
+            pxy *= 0.25;
+            pxz *= 0.25;
+            pyz *= 0.25;
+            auto adv = [&](const double* f) {
+                return ux * upwind(f, e, i, nx, 1, ux, dx) + uy * upwind(f, e, j, ny, sy, uy, dy)
+                     + uz * upwind(f, e, k, nz, sz, uz, dz);
+            };
+            a.out[F_P][e] = p[e] - dt * adv(p);
+            a.out[F_TXX][e] = txx[e] + dt * (2.0 * (pxy + pxz) - adv(txx));
+            a.out[F_TYY][e] = tyy[e] + dt * (-2.0 * (pxy - pyz) - adv(tyy));
+        }
+        if (k < nz) {                             // xy edge (x_i, y_j, z_k+1/2)
+            if (i == 0 || i == nx || j == 0 || j == ny) {
+                a.out[F_TXY][e] = txy[e];
+            } else {
+                const double ux = 0.5 * (vx[e - sy] + vx[e]), uy = 0.5 * (vy[e - 1] + vy[e]);
+                double uz = 0.0, d = 0.0, tb = 0.0, wb = 0.0, sb = 0.0, vb = 0.0;
+                for (int c = 0; c < 2; ++c)
+                    for (int b = -1; b < 1; ++b)
+                        for (int a2 = -1; a2 < 1; ++a2) uz += vz[at(i + a2, j + b, k + c)];
+                for (int b = -1; b < 1; ++b)
+                    for (int a2 = -1; a2 < 1; ++a2) d += tyy[at(i + a2, j + b, k)] - txx[at(i + a2, j + b, k)];
+                for (int c = 0; c < 2; ++c)
+                    for (int a2 = -1; a2 < 1; ++a2) {   // yz edges around
+                        tb += tyz[at(i + a2, j, k + c)];
+                        wb += wyz(i + a2, j, k + c);
+                    }
+                for (int c = 0; c < 2; ++c)
+                    for (int b = -1; b < 1; ++b) {      // xz edges around
+                        sb += txz[at(i, j + b, k + c)];
+                        vb += wxz(i, j + b, k + c);
+                    }
+                uz *= 0.125;
+                d *= 0.25; tb *= 0.25; wb *= 0.25; sb *= 0.25; vb *= 0.25;
+                const double r = wxy(i, j, k) * d + tb * vb + sb * wb;
+                const double adv = ux * upwind(txy, e, i, nx + 1, 1, ux, dx) + uy * upwind(txy, e, j, ny + 1, sy, uy, dy)
+                                 + uz * upwind(txy, e, k, nz, sz, uz, dz);
+                a.out[F_TXY][e] = txy[e] + dt * (r - adv);
+            }
+        }
+        if (j < ny) {                             // xz edge (x_i, y_j+1/2, z_k)
+            if (i == 0 || i == nx || k == 0 || k == nz) {
+                a.out[F_TXZ][e] = txz[e];
+            } else {
+                const double ux = 0.5 * (vx[e - sz] + vx[e]), uz = 0.5 * (vz[e - 1] + vz[e]);
+                double uy = 0.0, d = 0.0, tb = 0.0, wb = 0.0, sb = 0.0, vb = 0.0;
+                for (int c = -1; c < 1; ++c)
+                    for (int b = 0; b < 2; ++b)
+                        for (int a2 = -1; a2 < 1; ++a2) uy += vy[at(i + a2, j + b, k + c)];
+                for (int c = -1; c < 1; ++c)
+                    for (int a2 = -1; a2 < 1; ++a2) d += tzz(at(i + a2, j, k + c)) - txx[at(i + a2, j, k + c)];
+                for (int b = 0; b < 2; ++b)
+                    for (int a2 = -1; a2 < 1; ++a2) {   // yz edges around
+                        tb += tyz[at(i + a2, j + b, k)];
+                        wb += wyz(i + a2, j + b, k);
+                    }
+                for (int c = -1; c < 1; ++c)
+                    for (int b = 0; b < 2; ++b) {       // xy edges around
+                        sb += txy[at(i, j + b, k + c)];
+                        vb += wxy(i, j + b, k + c);
+                    }
+                uy *= 0.125;
+                d *= 0.25; tb *= 0.25; wb *= 0.25; sb *= 0.25; vb *= 0.25;
+                const double r = wxz(i, j, k) * d + tb * vb - sb * wb;
+                const double adv = ux * upwind(txz, e, i, nx + 1, 1, ux, dx) + uy * upwind(txz, e, j, ny, sy, uy, dy)
+                                 + uz * upwind(txz, e, k, nz + 1, sz, uz, dz);
+                a.out[F_TXZ][e] = txz[e] + dt * (r - adv);
+            }
+        }
+        if (i < nx) {                             // yz edge (x_i+1/2, y_j, z_k)
+            if (j == 0 || j == ny || k == 0 || k == nz) {
+                a.out[F_TYZ][e] = tyz[e];
+            } else {
+                const double uy = 0.5 * (vy[e - sz] + vy[e]), uz = 0.5 * (vz[e - sy] + vz[e]);
+                double ux = 0.0, d = 0.0, sb = 0.0, vb = 0.0, tb = 0.0, wb = 0.0;
+                for (int c = -1; c < 1; ++c)
+                    for (int b = -1; b < 1; ++b)
+                        for (int a2 = 0; a2 < 2; ++a2) ux += vx[at(i + a2, j + b, k + c)];
+                for (int c = -1; c < 1; ++c)
+                    for (int b = -1; b < 1; ++b) d += tzz(at(i, j + b, k + c)) - tyy[at(i, j + b, k + c)];
+                for (int c = -1; c < 1; ++c)
+                    for (int a2 = 0; a2 < 2; ++a2) {    // xy edges around
+                        sb += txy[at(i + a2, j, k + c)];
+                        vb += wxy(i + a2, j, k + c);
+                    }
+                for (int b = -1; b < 1; ++b)
+                    for (int a2 = 0; a2 < 2; ++a2) {    // xz edges around
+                        tb += txz[at(i + a2, j + b, k)];
+                        wb += wxz(i + a2, j + b, k);
+                    }
+                ux *= 0.125;
+                d *= 0.25; sb *= 0.25; vb *= 0.25; tb *= 0.25; wb *= 0.25;
+                const double r = wyz(i, j, k) * d - sb * wb - tb * vb;
+                const double adv = ux * upwind(tyz, e, i, nx, 1, ux, dx) + uy * upwind(tyz, e, j, ny + 1, sy, uy, dy)
+                                 + uz * upwind(tyz, e, k, nz + 1, sz, uz, dz);
+                a.out[F_TYZ][e] = tyz[e] + dt * (r - adv);
+            }
+        }
+    }
+}
+
 }  // namespace
 
 void launch_fill(double* p, double v, long n, hipStream_t s) { k_fill<<<blocks_for(n), NT1, 0, s>>>(p, v, n); }
@@ -283,6 +482,13 @@ void launch_column_integrals(const AuxGrid& g, const double* p, const double* tx
                              double* out3, hipStream_t s)
 {
     k_columns<<<3, 256, 0, s>>>(g, p, txx, g.ndim == 3 ? dy * dz : dy, out3);
+}
+
+void launch_objective(const AuxGrid& g, const ObjectiveArgs& a, hipStream_t s)
+{
+    const long n = (long)(g.nx + 1) * (g.ny + 1) * (g.ndim == 3 ? g.nz + 1 : 1);
+    if (g.ndim == 3) k_objective_3d<<<blocks_for(n), NT1, 0, s>>>(g, a);
+    else k_objective_2d<<<blocks_for(n), NT1, 0, s>>>(g, a);
 }
 
 }  // namespace ep

@@ -119,6 +119,17 @@ void launch_accumulate(const AuxGrid& g, double dt, double idx, double idy, doub
 template <typename R>
 void launch_diagnostics(const SweepArgs<R>& a, double* lamdot, double* tii, double* yld,
                         hipStream_t s);
+// Objective (Jaumann) update of the stresses carried into an increment
+// (paper: Jaumann rate of stress and the appendix on the objective stress
+// terms), explicit over dt with the velocities in `in`: out = tau + dt (tau^R
+// - v.grad tau), p - dt v.grad p.  `in` and `out` hold the fields F_* (only
+// the stress entries of `out` are written); out must not alias in.
+struct ObjectiveArgs {
+    const double* in[F_NIT];
+    double* out[F_NIT];
+    double dx, dy, dz, dt;
+};
+void launch_objective(const AuxGrid& g, const ObjectiveArgs& a, hipStream_t s);
 // Column integrals of sigma_xx at columns i = 0, nx/2, nx-1 (3 doubles).
 void launch_column_integrals(const AuxGrid& g, const double* p, const double* txx, double dy,
                              double dz, double* out3, hipStream_t s);

@@ -34,7 +34,7 @@ FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
 # every symbol include/ep.h declares
 SYMBOLS = ["ep_abi_version", "ep_workspace_size", "ep_init", "ep_load_step", "ep_sweep",
            "ep_residual", "ep_fields", "ep_field_shape", "ep_destroy", "ep_last_error",
-           "ep_enable_timing", "ep_sweep_timing", "ep_step_history", "ep_set_guess",
+           "ep_enable_timing", "ep_sweep_timing", "ep_step_history", "ep_set_guess", "ep_objective_update",
            "ep_batch_workspace_size", "ep_batch_init", "ep_batch_tune", "ep_batch_tile_shape",
            "ep_batch_load_step", "ep_batch_model", "ep_batch_enable_timing", "ep_batch_timing",
            "ep_batch_destroy", "ep_batch_last_error",
@@ -54,6 +54,7 @@ class ep_params(C.Structure):
         ("re", C.c_double), ("r", C.c_double), ("cfl", C.c_double),
         ("precision", C.c_int), ("sweep", C.c_int), ("fp32_switch", C.c_double),
         ("fp32_stall", C.c_int), ("freeze_iter", C.c_int), ("guess_accept", C.c_double),
+        ("objective", C.c_int),
     ]
 
 
@@ -110,6 +111,7 @@ def lib():
         L.ep_sweep_timing.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_long)]
         L.ep_step_history.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_int]
         L.ep_set_guess.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.ep_objective_update.argtypes = [vp]
         L.ep_batch_workspace_size.argtypes = [C.c_int, C.POINTER(ep_params), C.POINTER(C.c_size_t)]
         L.ep_batch_init.argtypes = [C.c_int, C.POINTER(ep_params), C.POINTER(C.POINTER(C.c_double)), vp,
                                     C.c_size_t, vp, C.POINTER(vp)]
@@ -285,6 +287,7 @@ def params_from_model(m, precision: int = EP_FP64, sweep: int = EP_SWEEP_AUTO,
     p.precision, p.sweep, p.fp32_switch, p.fp32_stall = precision, sweep, fp32_switch, fp32_stall
     p.freeze_iter = m.freeze_iter
     p.guess_accept = guess_accept
+    p.objective = getattr(m, "objective", 0)
     return p
 
 
@@ -339,6 +342,12 @@ class ModelView:
         arrs.append(None if vz is None else np.ascontiguousarray(vz, dtype=np.float64))
         ptr = lambda a: None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
         self._check(lib().ep_set_guess(self.h, ptr(arrs[0]), ptr(arrs[1]), ptr(arrs[2])), "ep_set_guess")
+
+    def objective_update(self) -> None:
+        """Objective (Jaumann) update of the current stresses with the current
+        velocities, in place (what load_step applies first when the model's
+        objective flag is set)."""
+        self._check(lib().ep_objective_update(self.h), "ep_objective_update")
 
 
 class Solver(ModelView):

@@ -55,7 +55,7 @@ def test_workspace_size_scales_with_grid_and_precision(E):
 
 @pytest.mark.parametrize("change", [
     dict(psi_deg=5.0), dict(nx=2), dict(bulk=0.0), dict(shear=-1.0), dict(dt=0.0), dict(tol=0.0),
-    dict(cfl=0.75), dict(ndim=4), dict(max_iter=0), dict(visc=0.0), dict(freeze_iter=-1),
+    dict(cfl=0.75), dict(ndim=4), dict(max_iter=0), dict(visc=0.0), dict(freeze_iter=-1), dict(objective=2),
 ])
 def test_invalid_parameters_rejected(E, change):
     m = c1_small_2d().with_(**change)
