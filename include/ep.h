@@ -63,7 +63,10 @@ typedef struct ep_params {
     int    ndim;             /* 2 or 3 */
     int    nx, ny, nz;       /* cells per direction, each >= 3 (nz ignored in 2D) */
     double lx, ly, lz;       /* domain extents; the domain is centred at the origin */
-    double bulk;             /* K > 0 */
+    double bulk;             /* K > 0; +inf: incompressible (pseudo-transient pressure equation
+                                A2ssP2, 1/(K dt) = 0): the pressure term of the residual then
+                                takes the visco-elastic viscosity in place of K dt, and a
+                                physical evaluation keeps the pressure's pseudo-time term */
     double shear;            /* G > 0 (uniform) */
     double visc;             /* mu_s > 0; +INFINITY gives the elasto-plastic limit */
     double phi_deg;          /* friction angle */

@@ -332,13 +332,22 @@ static double centre_lambda(double J2, double D, double p, double c, double A, d
 }
 
 /* ------------------------------------------------------------------ 2D */
+/* Pressure term of the residual: |p^{k+1} - p^k| times K dt / (K~dtau L),
+ * the distance of p from its local fixed point per unit length.  In the
+ * incompressible limit (K = +inf, equation A2ssP2: 1/(K dt) = 0) the
+ * pressure rate is the divergence, and the factor takes the visco-elastic
+ * viscosity in place of K dt, as the deviator term does (a reading). */
+static double p_res_visc(const orc_state* s) { return isinf(s->prm.bulk) ? s->eta : s->prm.bulk * s->prm.dt; }
+
 static double sweep2d(orc_state* s, int mode)
 {
     const int physical = mode == 1;
     const int nx = s->nx, ny = s->ny;
     const double dx = s->dx, dy = s->dy;
     const double igt = physical ? 0.0 : 1.0 / s->gdtau;
-    const double ikt = physical ? 0.0 : 1.0 / s->kdtau;
+    /* incompressible limit (K = +inf): the pressure has no local physical
+     * law, so the physical evaluation keeps its pseudo-time term (a reading) */
+    const double ikt = (physical && !isinf(s->prm.bulk)) ? 0.0 : 1.0 / s->kdtau;
     const double igd = 1.0 / (s->prm.shear * s->prm.dt);
     const double ikd = 1.0 / (s->prm.bulk * s->prm.dt);
     const double D = igt + igd + s->inv_mus;
@@ -432,7 +441,7 @@ static double sweep2d(orc_state* s, int mode)
     s->vmax = vmax;
     if (nbad) rmax = NAN;
     if (physical) return rmax;
-    rmax = fmax(rmax, fmax(dpm * s->prm.bulk * s->prm.dt / s->kdtau, dtm * s->eta / s->gdtau) / s->L);
+    rmax = fmax(rmax, fmax(dpm * p_res_visc(s) / s->kdtau, dtm * s->eta / s->gdtau) / s->L);
     if (nbad) rmax = NAN;
     if (mode == 2) return rmax;
     /* commit (Jacobi: every update above read only old values) */
@@ -452,7 +461,9 @@ static double sweep3d(orc_state* s, int mode)
     const int nx = s->nx, ny = s->ny, nz = s->nz;
     const double dx = s->dx, dy = s->dy, dz = s->dz;
     const double igt = physical ? 0.0 : 1.0 / s->gdtau;
-    const double ikt = physical ? 0.0 : 1.0 / s->kdtau;
+    /* incompressible limit (K = +inf): the pressure has no local physical
+     * law, so the physical evaluation keeps its pseudo-time term (a reading) */
+    const double ikt = (physical && !isinf(s->prm.bulk)) ? 0.0 : 1.0 / s->kdtau;
     const double igd = 1.0 / (s->prm.shear * s->prm.dt);
     const double ikd = 1.0 / (s->prm.bulk * s->prm.dt);
     const double D = igt + igd + s->inv_mus;
@@ -626,7 +637,7 @@ static double sweep3d(orc_state* s, int mode)
     s->vmax = vmax;
     if (nbad) rmax = NAN;
     if (physical) return rmax;
-    rmax = fmax(rmax, fmax(dpm * s->prm.bulk * s->prm.dt / s->kdtau, dtm * s->eta / s->gdtau) / s->L);
+    rmax = fmax(rmax, fmax(dpm * p_res_visc(s) / s->kdtau, dtm * s->eta / s->gdtau) / s->L);
     if (nbad) rmax = NAN;
     if (mode == 2) return rmax;
     for (int k = 0; k < nz; ++k) for (int j = 0; j < ny; ++j) for (int i = 1; i < nx; ++i)

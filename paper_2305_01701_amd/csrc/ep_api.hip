@@ -205,7 +205,10 @@ SweepArgs<R> make_args(const ep_handle* h, R* const* from, R* const* to, R* cons
     a.idy = (R)(1.0 / h->dy);
     a.idz = (R)(1.0 / h->dz);
     const double igt = physical ? 0.0 : 1.0 / h->gdtau;
-    const double ikt = physical ? 0.0 : 1.0 / h->kdtau;
+    // incompressible limit (K = +inf, 1/(K dt) = 0): the pressure has no local
+    // physical law, so a physical evaluation keeps its pseudo-time term
+    const bool incompressible = std::isinf(h->prm.bulk);
+    const double ikt = (physical && !incompressible) ? 0.0 : 1.0 / h->kdtau;
     const double igd = 1.0 / (h->prm.shear * h->prm.dt);
     const double ikd = 1.0 / (h->prm.bulk * h->prm.dt);
     a.igt = (R)igt;
@@ -218,7 +221,9 @@ SweepArgs<R> make_args(const ep_handle* h, R* const* from, R* const* to, R* cons
     a.dtrho = (R)h->dtrho;
     a.A = (R)h->A;
     a.B = (R)h->B;
-    a.rK = (R)(h->prm.bulk * h->prm.dt / (h->kdtau * h->L));
+    // pressure residual factor: K dt, or the visco-elastic viscosity in the
+    // incompressible limit (the pressure rate is then the divergence)
+    a.rK = (R)((incompressible ? h->eta : h->prm.bulk * h->prm.dt) / (h->kdtau * h->L));
     a.rG = (R)(h->eta / (h->gdtau * h->L));
     // FP32 velocity fields store the deviation from the background field
     const bool bg = sizeof(R) == 4;

@@ -111,3 +111,4 @@ def test_3d_trajectory_with_objective_update():
     compare_accumulators(m, g.fields(accum_names(m)), o.fields(accum_names(m)), 1e-6)
     g.close()
     o.close()
+
