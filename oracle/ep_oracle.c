@@ -59,6 +59,7 @@ struct orc_state {
     int nx, ny, nz, ndim;
     double dx, dy, dz;
     double gdtau, kdtau, dtrho, eta, A, B, h, L, inv_mus;
+    double C;                 /* plastic potential Q = sqrt(J2) - C p (dilatancy) */
     /* state */
     double *vx, *vy, *vz;
     double *p, *txx, *tyy, *tzz, *txy, *txz, *tyz;
@@ -157,7 +158,7 @@ orc_state* orc_create(const orc_params* prm, const double* cohesion)
     if (!prm || (prm->ndim != 2 && prm->ndim != 3)) return NULL;
     if (prm->nx < 3 || prm->ny < 3 || (prm->ndim == 3 && prm->nz < 3)) return NULL;
     if (!(prm->bulk > 0) || !(prm->shear > 0) || !(prm->dt > 0) || !(prm->tol > 0)) return NULL;
-    if (prm->psi_deg != 0.0) return NULL;
+    if (!(prm->psi_deg >= 0.0) || prm->psi_deg > prm->phi_deg) return NULL;
     if (!(prm->visc > 0)) return NULL;
     orc_state* s = (orc_state*)calloc(1, sizeof(orc_state));
     s->prm = *prm;
@@ -168,6 +169,10 @@ orc_state* orc_create(const orc_params* prm, const double* cohesion)
     s->dz = prm->ndim == 3 ? prm->lz / prm->nz : 1.0;
     s->inv_mus = isinf(prm->visc) ? 0.0 : 1.0 / prm->visc;
     dp_constants(s->ndim, prm->phi_deg, &s->A, &s->B);
+    {   /* C of the plastic potential: the friction-angle expression of A with psi */
+        double dummy;
+        dp_constants(s->ndim, prm->psi_deg, &s->C, &dummy);
+    }
 
     double re = prm->re > 0 ? prm->re : 3.0 * sqrt(10.0) * PI_D / 2.0;
     double cfl = prm->cfl > 0 ? prm->cfl : 0.9 / sqrt((double)s->ndim);
@@ -337,6 +342,29 @@ static double centre_lambda(double J2, double D, double p, double c, double A, d
  * incompressible limit (K = +inf, equation A2ssP2: 1/(K dt) = 0) the
  * pressure rate is the divergence, and the factor takes the visco-elastic
  * viscosity in place of K dt, as the deviator term does (a reading). */
+/* Dilatant return (psi > 0; Plasticity section, potential Q = sqrt(J2) - C p).
+ * The plastic strain rate lambda_dot dQ/dsigma has the volumetric part
+ * lambda_dot C, which enters the pressure equation like a source:
+ *     p = p_tr + lambda_dot C k,   k = 1 / (1/(K~dtau) + 1/(K dt)),
+ * with p_tr the pressure update without it.  With the deviatoric update
+ * tauII D + lambda_dot = sqrt(J2(T)) and the yield condition tauII = A p + B c
+ * this is linear in lambda_dot:
+ *     lambda_dot = (sqrt(J2) - D (A p_tr + B c)) / (1 + D A C k).
+ * Returns Lambda = lambda_dot / tauII (+inf at the apex, tauII = 0); *p gets
+ * the corrected pressure.  Called for yielding centres only. */
+static double dilatant_lambda(double J2, double D, double p_tr, double c, double A, double B, double C, double k,
+                              double* p, double* tII_ret, double* Y_out, double* lamdot)
+{
+    double ld = (sqrt(J2) - D * (A * p_tr + B * c)) / (1.0 + D * A * C * k);
+    *p = p_tr + ld * C * k;
+    double Y = A * (*p) + B * c;
+    if (Y < 0.0) Y = 0.0;
+    *lamdot = ld;
+    *tII_ret = Y;
+    *Y_out = Y;
+    return Y > 0.0 ? ld / Y : INFINITY;
+}
+
 static double p_res_visc(const orc_state* s) { return isinf(s->prm.bulk) ? s->eta : s->prm.bulk * s->prm.dt; }
 
 static double sweep2d(orc_state* s, int mode)
@@ -350,6 +378,7 @@ static double sweep2d(orc_state* s, int mode)
     const double ikt = (physical && !isinf(s->prm.bulk)) ? 0.0 : 1.0 / s->kdtau;
     const double igd = 1.0 / (s->prm.shear * s->prm.dt);
     const double ikd = 1.0 / (s->prm.bulk * s->prm.dt);
+    const double kk = 1.0 / (ikt + ikd);      /* pressure compliance of one update */
     const double D = igt + igd + s->inv_mus;
     const double A = s->A, B = s->B;
 
@@ -387,13 +416,20 @@ static double sweep2d(orc_state* s, int mode)
                               + s->Txy[XY2(i, j + 1)] + s->Txy[XY2(i + 1, j + 1)]);
             double J2 = 0.5 * (Txx * Txx + Tyy * Tyy) + Tb * Tb;
             double tret, Y, ld;
-            double lam = centre_lambda(J2, D, s->pn[c], s->coh[c], A, B, &tret, &Y, &ld);
+            const double ptr = s->pn[c];
+            double lam = centre_lambda(J2, D, ptr, s->coh[c], A, B, &tret, &Y, &ld);
+            if (lam > 0.0 && s->C > 0.0)
+                lam = dilatant_lambda(J2, D, ptr, s->coh[c], A, B, s->C, kk, &s->pn[c], &tret, &Y, &ld);
             s->lamdot[c] = ld;
             s->tII[c] = tret;
             s->yld[c] = Y;
             if (lam > 0.0) ny_count++;
             if (mode == 0 && s->freeze == 1) s->lamf[c] = lam;
-            if (mode == 0 && s->freeze == 2) lam = s->lamf[c];
+            if (mode == 0 && s->freeze == 2) {
+                lam = s->lamf[c];
+                /* held Lambda: lambda_dot = Lambda tauII = Lambda sqrt(J2) / (D + Lambda) */
+                if (s->C > 0.0) s->pn[c] = ptr + lam * sqrt(J2) / (D + lam) * s->C * kk;
+            }
             s->lam[c] = lam;
             s->txxn[c] = Txx / (D + lam);
             s->tyyn[c] = Tyy / (D + lam);
@@ -466,6 +502,7 @@ static double sweep3d(orc_state* s, int mode)
     const double ikt = (physical && !isinf(s->prm.bulk)) ? 0.0 : 1.0 / s->kdtau;
     const double igd = 1.0 / (s->prm.shear * s->prm.dt);
     const double ikd = 1.0 / (s->prm.bulk * s->prm.dt);
+    const double kk = 1.0 / (ikt + ikd);      /* pressure compliance of one update */
     const double D = igt + igd + s->inv_mus;
     const double A = s->A, B = s->B;
 
@@ -536,13 +573,19 @@ static double sweep3d(orc_state* s, int mode)
                 double J2 = 0.5 * (Txx * Txx + Tyy * Tyy + Tzz * Tzz)
                           + Txyb * Txyb + Txzb * Txzb + Tyzb * Tyzb;
                 double tret, Y, ld;
-                double lam = centre_lambda(J2, D, s->pn[c], s->coh[c], A, B, &tret, &Y, &ld);
+                const double ptr = s->pn[c];
+                double lam = centre_lambda(J2, D, ptr, s->coh[c], A, B, &tret, &Y, &ld);
+                if (lam > 0.0 && s->C > 0.0)
+                    lam = dilatant_lambda(J2, D, ptr, s->coh[c], A, B, s->C, kk, &s->pn[c], &tret, &Y, &ld);
                 s->lamdot[c] = ld;
                 s->tII[c] = tret;
                 s->yld[c] = Y;
                 if (lam > 0.0) ny_count++;
                 if (mode == 0 && s->freeze == 1) s->lamf[c] = lam;
-                if (mode == 0 && s->freeze == 2) lam = s->lamf[c];
+                if (mode == 0 && s->freeze == 2) {
+                    lam = s->lamf[c];
+                    if (s->C > 0.0) s->pn[c] = ptr + lam * sqrt(J2) / (D + lam) * s->C * kk;
+                }
                 s->lam[c] = lam;
                 s->txxn[c] = Txx / (D + lam);
                 s->tyyn[c] = Tyy / (D + lam);
