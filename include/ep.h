@@ -70,7 +70,10 @@ typedef struct ep_params {
     double shear;            /* G > 0 (uniform) */
     double visc;             /* mu_s > 0; +INFINITY gives the elasto-plastic limit */
     double phi_deg;          /* friction angle */
-    double psi_deg;          /* dilation angle; must be 0 (non-dilatant flow) */
+    double psi_deg;          /* dilation angle, 0 <= psi <= phi: plastic potential
+                                Q = sqrt(J2) - C p with C from psi as A from phi (Plasticity
+                                section); psi > 0 adds the plastic volume rate lambda_dot C
+                                to the pressure equation (dilatant return) */
     double dt;               /* physical time increment per load step */
     double erate[3];         /* background strain rate (diagonal); pure shear = (1,-1,0) */
     double tol;              /* normalised residual tolerance (> 0) */
@@ -164,7 +167,7 @@ int ep_workspace_size(const ep_params* p, size_t* bytes);
  *  stream: hipStream_t (as void*) used for all work of the handle.
  * Initial state (model configuration section): p = tau = 0 and velocities
  * equal to the background pure-shear field v = erate * x (domain centred).
- * Errors: EP_EINVAL (psi != 0, cfl >= 1/sqrt(ndim), a size < 3, K, G, dt,
+ * Errors: EP_EINVAL (psi outside [0, phi], cfl >= 1/sqrt(ndim), a size < 3, K, G, dt,
  * tol or visc not > 0, NULL out), EP_ENOMEM (workspace too small),
  * EP_EDEVICE. */
 int ep_init(const ep_params* p, const double* cohesion, void* d_workspace, size_t ws_bytes,

@@ -53,7 +53,7 @@ int validate(const ep_params* p)
     if (p->nx < 3 || p->ny < 3 || (p->ndim == 3 && p->nz < 3)) return EP_EINVAL;
     if (!(p->lx > 0) || !(p->ly > 0) || (p->ndim == 3 && !(p->lz > 0))) return EP_EINVAL;
     if (!(p->bulk > 0) || !(p->shear > 0) || !(p->visc > 0) || !(p->dt > 0) || !(p->tol > 0)) return EP_EINVAL;
-    if (p->psi_deg != 0.0) return EP_EINVAL;
+    if (!(p->psi_deg >= 0.0) || p->psi_deg > p->phi_deg) return EP_EINVAL;
     if (p->max_iter <= 0 || p->n_check < 0) return EP_EINVAL;
     if (p->cfl < 0 || p->re < 0 || p->r < 0) return EP_EINVAL;
     if (p->cfl > 0 && p->cfl >= 1.0 / std::sqrt((double)p->ndim)) return EP_EINVAL;
@@ -150,14 +150,16 @@ void derive(ep_handle* h)
     h->dy = p.ly / p.ny;
     h->dz = p.ndim == 3 ? p.lz / p.nz : 1.0;
     h->inv_mus = std::isinf(p.visc) ? 0.0 : 1.0 / p.visc;
-    const double ph = p.phi_deg * PI / 180.0;
+    const double ph = p.phi_deg * PI / 180.0, ps = p.psi_deg * PI / 180.0;
     if (p.ndim == 2) {
         h->A = std::sin(ph);
         h->B = std::cos(ph);
+        h->C = std::sin(ps);
     } else {
         const double den = std::sqrt(3.0) * (3.0 - std::sin(ph));
         h->A = 6.0 * std::sin(ph) / den;
         h->B = 6.0 * std::cos(ph) / den;
+        h->C = 6.0 * std::sin(ps) / (std::sqrt(3.0) * (3.0 - std::sin(ps)));
     }
     const double re = p.re > 0 ? p.re : 3.0 * std::sqrt(10.0) * PI / 2.0;
     const double cfl = p.cfl > 0 ? p.cfl : 0.9 / std::sqrt((double)p.ndim);
@@ -221,6 +223,8 @@ SweepArgs<R> make_args(const ep_handle* h, R* const* from, R* const* to, R* cons
     a.dtrho = (R)h->dtrho;
     a.A = (R)h->A;
     a.B = (R)h->B;
+    // dilatancy (psi > 0): pressure change per unit plastic rate in this update
+    a.Cik = (R)(h->C / (ikt + ikd));
     // pressure residual factor: K dt, or the visco-elastic viscosity in the
     // incompressible limit (the pressure rate is then the divergence)
     a.rK = (R)((incompressible ? h->eta : h->prm.bulk * h->prm.dt) / (h->kdtau * h->L));

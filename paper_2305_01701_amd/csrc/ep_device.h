@@ -76,11 +76,26 @@ __device__ __forceinline__ void block_sum_to(double v, unsigned long long* dst, 
     __syncthreads();
 }
 
+// Dilatant return (psi > 0, potential sqrt(J2) - C p): the plastic rate
+// lamdot adds lamdot * Cik to the pressure of the update, and with
+// tauII D + lamdot = sqrt(J2) and tauII = A p + B c
+//     lamdot = (sqrt(J2) - D (A p + B c)) / (1 + D A Cik)
+// for the pressure p before the correction.  Returns lamdot; p is corrected.
+template <typename R>
+__device__ __forceinline__ R dilatant_rate(R sq, R D, R& p, R c, R A, R B, R Cik)
+{
+#pragma clang fp contract(on)
+    const R ld = (sq - D * (A * p + B * c)) / (R(1) + D * A * Cik);
+    p = p + ld * Cik;
+    return ld;
+}
+
 // Return mapping at a centre.  J2 is of the trial sums T; returns Lambda
 // (0 when elastic, +inf at the apex) and writes the plastic rate
-// D (tauII_tr - Y), the returned tauII and the bound Y.
+// D (tauII_tr - Y), the returned tauII and the bound Y; p gets the dilatant
+// pressure correction when Cik != 0.
 template <typename R>
-__device__ __forceinline__ R centre_lambda(R J2, R D, R p, R c, R A, R B, R& lamdot, R& tii, R& Y)
+__device__ __forceinline__ R centre_lambda(R J2, R D, R& p, R c, R A, R B, R Cik, R& lamdot, R& tii, R& Y)
 {
 #pragma clang fp contract(on)
     R tii_tr = sqrt(J2) / D;
@@ -90,6 +105,11 @@ __device__ __forceinline__ R centre_lambda(R J2, R D, R p, R c, R A, R B, R& lam
     lamdot = R(0);
     tii = tii_tr;
     if (tii_tr > Y) {
+        if (Cik != R(0)) {
+            dilatant_rate(sqrt(J2), D, p, c, A, B, Cik);
+            Y = A * p + B * c;
+            Y = Y > R(0) ? Y : R(0);
+        }
         lam = D * (tii_tr / Y - R(1));
         lamdot = D * (tii_tr - Y);
         tii = Y;
@@ -111,13 +131,18 @@ __device__ __forceinline__ double fast_sqrt(double x) { return sqrt(x); }
 // the yield surface.  Same quantities as centre_lambda, one root and one
 // reciprocal.
 template <typename R>
-__device__ __forceinline__ R return_scale(R J2, R D, R invD, R p, R c, R A, R B, R& lam)
+__device__ __forceinline__ R return_scale(R J2, R D, R invD, R& p, R c, R A, R B, R Cik, R& lam)
 {
 #pragma clang fp contract(on)   // same rounding in every kernel that inlines it
     R Y = A * p + B * c;
     Y = Y > R(0) ? Y : R(0);
     const R sq = fast_sqrt(J2);
     if (sq * invD > Y) {
+        if (Cik != R(0)) {                       // dilatant return: corrected pressure
+            dilatant_rate(sq, D, p, c, A, B, Cik);
+            Y = A * p + B * c;
+            Y = Y > R(0) ? Y : R(0);
+        }
         lam = sq * fast_rcp(Y) - D;
         return Y * fast_rcp(sq);
     }

@@ -34,7 +34,7 @@ struct ep_handle {
     ep::AuxGrid g;
     int ndim, nx, ny, nz, sy;
     long sz, nelem;
-    double dx, dy, dz, eta, gdtau, kdtau, dtrho, A, B, L, h, inv_mus, dsig_ref;
+    double dx, dy, dz, eta, gdtau, kdtau, dtrho, A, B, C, L, h, inv_mus, dsig_ref;
     int n_check;
     bool fp32, fused32, fused64;
     double* it64[2][ep::F_NIT];

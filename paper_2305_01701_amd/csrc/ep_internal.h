@@ -41,6 +41,8 @@ struct SweepArgs {
     R ikk;                 // 1 / (ikt + ikd)
     R dtrho;               // dtau / rho~
     R A, B;                // Drucker-Prager constants
+    R Cik;                 // dilatancy: C of the plastic potential / (ikt + ikd), the pressure
+                           // change per unit plastic rate (0 for psi = 0)
     R rK, rG;              // pseudo-rate -> residual factors: K dt/(K~dtau L), eta/(G~dtau L)
     R ebx, eby, ebz;       // background strain rate subtracted from the stored velocities
                            // (FP32 fields store v - erate * x; 0 when v is stored in full)

@@ -274,12 +274,15 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
                 R Tyzb = R(0.25) * (s_Tyz[sc][q] + s_Tyz[sc][q + W] + s_Tyz[sc1][q] + s_Tyz[sc1][q + W]);
                 R J2 = R(0.5) * (Txx * Txx + Tyy * Tyy + Tzz * Tzz) + Txyb * Txyb + Txzb * Txzb + Tyzb * Tyzb;
                 R lam;
-                R sc_ = return_scale(J2, D, a.invD, pn, cc[u], a.A, a.B, lam);
+                const R ptr = pn;
+                R sc_ = return_scale(J2, D, a.invD, pn, cc[u], a.A, a.B, a.Cik, lam);
                 const bool own = la >= 2 && la < TX + 2 && lbb >= 2 && lbb < TY + 2 && c >= k0 && c < k1;
                 if (a.lam_mode != LAM_COMPUTE) {                 // frozen plasticity
                     if (a.lam_mode == LAM_FROZEN) {
                         lam = ld(a.lam + sz * c, ro[u]);
                         sc_ = R(1) / (D + lam);
+                        // dilatancy of the held Lambda: lamdot = Lambda sqrt(J2) / (D + Lambda)
+                        if (a.Cik != R(0)) pn = ptr + lam * fast_sqrt(J2) * sc_ * a.Cik;
                     } else if (own) {
                         st(a.lam + sz * c, ro[u], lam);
                     }

@@ -52,9 +52,14 @@ __global__ __launch_bounds__(NT) void k_centre_2d(SweepArgs<R> a)
                         + vertex_T2(a, c + a.sy, i, j + 1) + vertex_T2(a, c + a.sy + 1, i + 1, j + 1));
         R J2 = R(0.5) * (Txx * Txx + Tyy * Tyy) + Tb * Tb;
         R ld, tii, Y;
-        R lam = centre_lambda(J2, a.D, pn, a.coh[c], a.A, a.B, ld, tii, Y);
-        if (a.lam_mode == LAM_FROZEN) lam = a.lam[c];    // frozen plasticity: Lambda held fixed
-        else a.lam[c] = lam;                             // read by the shear-point kernel
+        const R ptr = pn;
+        R lam = centre_lambda(J2, a.D, pn, a.coh[c], a.A, a.B, a.Cik, ld, tii, Y);
+        if (a.lam_mode == LAM_FROZEN) {                  // frozen plasticity: Lambda held fixed
+            lam = a.lam[c];
+            if (a.Cik != R(0)) pn = ptr + lam * sqrt(J2) / (a.D + lam) * a.Cik;   // its dilatancy
+        } else {
+            a.lam[c] = lam;                              // read by the shear-point kernel
+        }
         R txx = Txx / (a.D + lam), tyy = Tyy / (a.D + lam);
         a.nx_[F_P][c] = pn;
         a.nx_[F_TXX][c] = txx;
@@ -185,9 +190,14 @@ __global__ __launch_bounds__(NT) void k_centre_3d(SweepArgs<R> a)
                          + T_yz(a, c + sy + sz, j + 1, k + 1));
         R J2 = R(0.5) * (Txx * Txx + Tyy * Tyy + Tzz * Tzz) + Txy * Txy + Txz * Txz + Tyz * Tyz;
         R ld, tii, Y;
-        R lam = centre_lambda(J2, a.D, pn, a.coh[c], a.A, a.B, ld, tii, Y);
-        if (a.lam_mode == LAM_FROZEN) lam = a.lam[c];    // frozen plasticity: Lambda held fixed
-        else a.lam[c] = lam;                             // read by the shear-point kernel
+        const R ptr = pn;
+        R lam = centre_lambda(J2, a.D, pn, a.coh[c], a.A, a.B, a.Cik, ld, tii, Y);
+        if (a.lam_mode == LAM_FROZEN) {                  // frozen plasticity: Lambda held fixed
+            lam = a.lam[c];
+            if (a.Cik != R(0)) pn = ptr + lam * sqrt(J2) / (a.D + lam) * a.Cik;   // its dilatancy
+        } else {
+            a.lam[c] = lam;                              // read by the shear-point kernel
+        }
         R txx = Txx / (a.D + lam), tyy = Tyy / (a.D + lam);
         a.nx_[F_P][c] = pn;
         a.nx_[F_TXX][c] = txx;

@@ -125,11 +125,14 @@ __device__ __forceinline__ void sweep_tile_2d(const SweepArgs<R>& a, int bx, int
             R Tb = R(0.25) * (s_Txy[q] + s_Txy[q + 1] + s_Txy[q + W] + s_Txy[q + W + 1]);
             R J2 = R(0.5) * (Txx * Txx + Tyy * Tyy) + Tb * Tb;
             R lam;
-            R sc_ = return_scale(J2, D, a.invD, pn, gc[u], a.A, a.B, lam);
+            const R ptr = pn;
+            R sc_ = return_scale(J2, D, a.invD, pn, gc[u], a.A, a.B, a.Cik, lam);
             const bool own = la >= 2 && la < TX + 2 && lbb >= 2 && lbb < TY + 2;
             if (a.lam_mode == LAM_FROZEN) {
                 lam = a.lam[e];
                 sc_ = R(1) / (D + lam);
+                // dilatancy of the held Lambda: lamdot = Lambda sqrt(J2) / (D + Lambda)
+                if (a.Cik != R(0)) pn = ptr + lam * fast_sqrt(J2) * sc_ * a.Cik;
             } else if (a.lam_mode == LAM_STORE && own) {
                 a.lam[e] = lam;
             }

@@ -54,7 +54,7 @@ def test_workspace_size_scales_with_grid_and_precision(E):
 
 
 @pytest.mark.parametrize("change", [
-    dict(psi_deg=5.0), dict(nx=2), dict(bulk=0.0), dict(shear=-1.0), dict(dt=0.0), dict(tol=0.0),
+    dict(psi_deg=-1.0), dict(psi_deg=35.0), dict(nx=2), dict(bulk=0.0), dict(shear=-1.0), dict(dt=0.0), dict(tol=0.0),
     dict(cfl=0.75), dict(ndim=4), dict(max_iter=0), dict(visc=0.0), dict(freeze_iter=-1), dict(objective=2),
 ])
 def test_invalid_parameters_rejected(E, change):
@@ -109,7 +109,7 @@ def test_batch_rejects_invalid_sets(E, case):
         assert E.lib().ep_batch_workspace_size(0, None, C.byref(n)) == E.EP_EINVAL
         return
     else:
-        models = [a, b.with_(psi_deg=3.0)]
+        models = [a, b.with_(psi_deg=45.0)]          # psi > phi
     assert _batch_rc(E, models, precs)[0] == E.EP_EINVAL
 
 
