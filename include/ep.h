@@ -220,6 +220,15 @@ int ep_residual(ep_handle* h, ep_residual_info* r);
  * stream. */
 int ep_objective_update(ep_handle* h);
 
+/* Background strain rate (the pure-shear loading of the walls) of the next
+ * increments, e.g. a loading schedule of velocity increments (the viscous-
+ * limit runs of the paper's incompressible limits section raise the
+ * prescribed velocity from increment to increment).  Walls take the new rate
+ * at the next ep_load_step; the stopping rule's floor 2 G max|erate| dt / L
+ * follows it.  Single models only (EP_EINVAL for a batch model, a NULL or a
+ * non-finite rate). */
+int ep_set_strain_rate(ep_handle* h, const double erate[3]);
+
 /* Copy one field between the device state and a host FP64 array of exactly
  * ep_field_shape() elements.  dir = EP_GET or EP_SET.  EP_SET of TZZ(_OLD) is
  * rejected in 3D (the deviator is stored trace-free: tzz = -(txx + tyy));

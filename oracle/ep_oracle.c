@@ -944,6 +944,11 @@ static void objective3d(orc_state* s)
     free(wxy); free(wxz); free(wyz); free(pn); free(xx); free(yy); free(zz); free(xy); free(xz); free(yz);
 }
 
+void orc_set_strain_rate(orc_state* s, const double erate[3])
+{
+    for (int d = 0; d < 3; ++d) s->prm.erate[d] = (s->ndim == 3 || d < 2) ? erate[d] : 0.0;
+}
+
 void orc_objective_update(orc_state* s)
 {
     if (s->ndim == 2) objective2d(s);

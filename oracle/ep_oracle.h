@@ -76,6 +76,9 @@ orc_state* orc_create(const orc_params* prm, const double* cohesion);
  * first-order upwind advection.  orc_load_step applies it to the carried
  * stresses before the increment when prm.objective is set. */
 void orc_objective_update(orc_state* s);
+/* Background strain rate of the next increments (walls take it at the next
+ * orc_load_step). */
+void orc_set_strain_rate(orc_state* s, const double erate[3]);
 void   orc_free(orc_state* s);
 long   orc_field_size(const orc_state* s, int field);
 int    orc_get(const orc_state* s, int field, double* out);

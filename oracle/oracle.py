@@ -75,6 +75,7 @@ def lib():
         L.orc_history.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int]
         L.orc_history_len.argtypes = [C.c_void_p]
         L.orc_objective_update.argtypes = [C.c_void_p]
+        L.orc_set_strain_rate.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
         L.orc_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -146,6 +147,10 @@ class Oracle:
     def fields(self, names=None) -> Dict[str, np.ndarray]:
         names = names or [n for n in FIELDS if lib().orc_field_size(self._h, FIELD_ID[n]) > 0]
         return {n: self.get(n) for n in names}
+
+    def set_strain_rate(self, erate) -> None:
+        """Background strain rate of the next increments."""
+        lib().orc_set_strain_rate(self._h, (C.c_double * 3)(*[float(x) for x in erate]))
 
     def objective_update(self) -> None:
         """Objective (Jaumann) update of the current stresses with the current

@@ -907,6 +907,27 @@ int ep_residual(ep_handle* h, ep_residual_info* r)
     return EP_OK;
 }
 
+int ep_set_strain_rate(ep_handle* h, const double erate[3])
+{
+    if (!h || !erate || h->in_batch) return EP_EINVAL;
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(erate[d])) return set_err(h, EP_EINVAL, "strain rate %d not finite", d);
+    // FP32 velocities are stored relative to the background field of the
+    // old rate: make the FP64 state current, then re-derive FP32 from it
+    ensure_it64(h);
+    for (int d = 0; d < 3; ++d) h->prm.erate[d] = h->ndim == 3 || d < 2 ? erate[d] : 0.0;
+    const double emax = std::fmax(std::fabs(h->prm.erate[0]), std::fmax(std::fabs(h->prm.erate[1]),
+                                                                       std::fabs(h->prm.erate[2])));
+    h->dsig_ref = 2.0 * h->prm.shear * emax * h->prm.dt;
+    h->it32_valid = false;
+    if (h->ndim == 2) {
+        int rc = upload_tables(h);                  // the tables carry the background rate
+        if (rc) return rc;
+    }
+    HIPCHK(h, hipGetLastError());
+    return EP_OK;
+}
+
 int ep_objective_update(ep_handle* h)
 {
     if (!h) return EP_EINVAL;
