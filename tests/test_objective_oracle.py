@@ -231,3 +231,88 @@ def test_load_step_applies_the_update_to_the_carried_stresses():
         np.testing.assert_allclose(a.get(k + "_old"), b.get(k), rtol=0, atol=1e-15, err_msg=k)
     a.close()
     b.close()
+
+
+def test_rigid_rotation_of_linear_fields_2d_matches_the_continuum_rate():
+    """Linear stress fields under a rigid rotation: the 4-point means and the
+    upwind differences are exact for linear fields, so at interior points the
+    update divided by dt equals tau^R - v.grad tau of the continuum fields."""
+    m = Model(ndim=2, nx=14, ny=12, dt=1e-3)
+    om = 0.6
+    o = Oracle(m)
+    set_velocity(o, m, lambda x, y, z: -om * y, lambda x, y, z: om * x)
+    xn, yn, xc, yc = coords(m)
+    XC, YC = grid(xc, yc)
+    XN, YN = grid(xn, yn)
+    fxx = lambda x, y: 0.3 + 0.2 * x - 0.1 * y
+    fyy = lambda x, y: -0.2 + 0.05 * x + 0.15 * y
+    fxy = lambda x, y: 0.1 - 0.3 * x + 0.25 * y
+    o.set("txx", fxx(XC, YC))
+    o.set("tyy", fyy(XC, YC))
+    o.set("txy", fxy(XN, YN))
+    o.set("p", 0.5 + 0.4 * XC - 0.2 * YC)
+    o.objective_update()
+    w = -om                                      # w_xy = (dvx/dy - dvy/dx) / 2
+    vx, vy = -om * YC, om * XC
+    inner = (slice(1, -1), slice(1, -1))
+    rxx = 2 * fxy(XC, YC) * w - (vx * 0.2 + vy * -0.1)
+    ryy = -2 * fxy(XC, YC) * w - (vx * 0.05 + vy * 0.15)
+    rp = -(vx * 0.4 + vy * -0.2)
+    got = lambda k, shape: o.get(k).reshape(shape)
+    np.testing.assert_allclose(((got("txx", XC.shape) - fxx(XC, YC)) / m.dt)[inner], rxx[inner], rtol=1e-7, atol=1e-9)
+    np.testing.assert_allclose(((got("tyy", XC.shape) - fyy(XC, YC)) / m.dt)[inner], ryy[inner], rtol=1e-7, atol=1e-9)
+    np.testing.assert_allclose(((got("p", XC.shape) - (0.5 + 0.4 * XC - 0.2 * YC)) / m.dt)[inner], rp[inner],
+                               rtol=1e-7, atol=1e-9)
+    vxn, vyn = -om * YN, om * XN
+    rxy = w * (fyy(XN, YN) - fxx(XN, YN)) - (vxn * -0.3 + vyn * 0.25)
+    vin = (slice(2, -2), slice(2, -2))
+    np.testing.assert_allclose(((got("txy", XN.shape) - fxy(XN, YN)) / m.dt)[vin], rxy[vin], rtol=1e-7, atol=1e-9)
+    o.close()
+
+
+def test_rigid_rotation_of_linear_fields_3d_matches_the_continuum_rate():
+    m = Model(ndim=3, nx=10, ny=9, nz=11, dt=1e-3)
+    Om = np.array([0.3, -0.5, 0.7])
+    ox, oy, oz = Om
+    o = Oracle(m)
+    set_velocity(o, m, lambda x, y, z: oy * z - oz * y, lambda x, y, z: oz * x - ox * z,
+                 lambda x, y, z: ox * y - oy * x)
+    xn, yn, zn, xc, yc, _, zc = coords(m)
+    r = np.random.Generator(np.random.PCG64(5))
+    coef = {k: r.uniform(-0.3, 0.3, 4) for k in ("txx", "tyy", "txy", "txz", "tyz", "p")}
+    lin = lambda k, X, Y, Z: coef[k][0] + coef[k][1] * X + coef[k][2] * Y + coef[k][3] * Z
+    loc = {"c": (xc, yc, zc), "txy": (xn, yn, zc), "txz": (xn, yc, zn), "tyz": (xc, yn, zn)}
+    G = {k: grid(*v) for k, v in loc.items()}
+    for k in ("txx", "tyy", "p"):
+        o.set(k, lin(k, *G["c"]))
+    o.set("tzz", -(lin("txx", *G["c"]) + lin("tyy", *G["c"])))
+    for k in ("txy", "txz", "tyz"):
+        o.set(k, lin(k, *G[k]))
+    o.objective_update()
+    W = np.array([[0.0, -oz, oy], [oz, 0.0, -ox], [-oy, ox, 0.0]])   # w_ab = (dv_a/dx_b - dv_b/dx_a)/2
+
+    def expected(name, X, Y, Z):
+        tau = np.zeros(X.shape + (3, 3))
+        tau[..., 0, 0], tau[..., 1, 1] = lin("txx", X, Y, Z), lin("tyy", X, Y, Z)
+        tau[..., 2, 2] = -(tau[..., 0, 0] + tau[..., 1, 1])
+        for (a, b), k in {(0, 1): "txy", (0, 2): "txz", (1, 2): "tyz"}.items():
+            tau[..., a, b] = tau[..., b, a] = lin(k, X, Y, Z)
+        rot = W @ tau - tau @ W                 # tau^R = w tau - tau w
+        v = np.stack([oy * Z - oz * Y, oz * X - ox * Z, ox * Y - oy * X], -1)
+        idx = {"txx": (0, 0), "tyy": (1, 1), "tzz": (2, 2), "txy": (0, 1), "txz": (0, 2), "tyz": (1, 2)}
+        if name == "p":
+            grad = coef["p"][1:]
+            return -(v @ grad)
+        a, b = idx[name]
+        grad = coef[name][1:] if name != "tzz" else -(coef["txx"][1:] + coef["tyy"][1:])
+        return rot[..., a, b] - v @ grad
+
+    inner = (slice(2, -2), slice(2, -2), slice(2, -2))
+    for name, where in [("txx", "c"), ("tyy", "c"), ("tzz", "c"), ("p", "c"), ("txy", "txy"), ("txz", "txz"),
+                        ("tyz", "tyz")]:
+        X, Y, Z = G[where]
+        before = (lin(name, X, Y, Z) if name != "tzz" else -(lin("txx", X, Y, Z) + lin("tyy", X, Y, Z)))
+        got = (o.get(name).reshape(X.shape) - before) / m.dt
+        np.testing.assert_allclose(got[inner], expected(name, X, Y, Z)[inner], rtol=1e-7, atol=1e-9,
+                                   err_msg=name)
+    o.close()
