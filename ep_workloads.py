@@ -36,7 +36,7 @@ class Model:
     shear: float = 1.0           # G
     visc: float = math.inf       # mu_s (inf = elasto-plastic)
     phi_deg: float = 30.0        # friction angle
-    psi_deg: float = 0.0         # dilation angle (must be 0)
+    psi_deg: float = 0.0         # dilation angle (0 <= psi <= phi)
     dt: float = 1e-4             # load increment (time; a = 1 so also strain)
     erate: Tuple[float, float, float] = (1.0, -1.0, 0.0)
     tol: float = 1e-8
@@ -47,6 +47,7 @@ class Model:
     cfl: float = 0.0             # 0 -> 0.9 / sqrt(ndim)
     freeze_iter: int = 0         # 0: off; else freeze the plastic multiplier after this many iterations
     objective: int = 0           # 1: objective (Jaumann) stress update at the start of every increment
+    eta_vp: float = 0.0          # consistency regularisation viscosity of the return (0: perfect plasticity)
     # weak inclusion in cohesion
     c0: float = 1.75e-3
     incl_radius: float = 0.1

@@ -107,6 +107,11 @@ typedef struct ep_params {
                                 previous increment's velocities, vorticity
                                 w_ij = (dv_i/dx_j - dv_j/dx_i)/2 at the shear points,
                                 first-order upwind advection, explicit over dt; 0: off */
+    double eta_vp;           /* consistency regularisation of the return (the visco-plastic
+                                strain rate of the constitutive section): a yielding point
+                                returns to tauII = A p + B c + eta_vp lambda_dot, with
+                                lambda_dot = 2 eps_dot_p,II from the consistency condition
+                                (0: perfect plasticity, the paper's runs; >= 0, finite) */
 } ep_params;
 
 typedef struct ep_step_stats {

@@ -160,6 +160,7 @@ orc_state* orc_create(const orc_params* prm, const double* cohesion)
     if (!(prm->bulk > 0) || !(prm->shear > 0) || !(prm->dt > 0) || !(prm->tol > 0)) return NULL;
     if (!(prm->psi_deg >= 0.0) || prm->psi_deg > prm->phi_deg) return NULL;
     if (!(prm->visc > 0)) return NULL;
+    if (!(prm->eta_vp >= 0.0) || isinf(prm->eta_vp)) return NULL;
     orc_state* s = (orc_state*)calloc(1, sizeof(orc_state));
     s->prm = *prm;
     s->ndim = prm->ndim;
@@ -342,27 +343,41 @@ static double centre_lambda(double J2, double D, double p, double c, double A, d
  * incompressible limit (K = +inf, equation A2ssP2: 1/(K dt) = 0) the
  * pressure rate is the divergence, and the factor takes the visco-elastic
  * viscosity in place of K dt, as the deviator term does (a reading). */
-/* Dilatant return (psi > 0; Plasticity section, potential Q = sqrt(J2) - C p).
- * The plastic strain rate lambda_dot dQ/dsigma has the volumetric part
+/* Dilatant and/or regularised return.
+ * Dilatancy (psi > 0; Plasticity section, potential Q = sqrt(J2) - C p): the
+ * plastic strain rate lambda_dot dQ/dsigma has the volumetric part
  * lambda_dot C, which enters the pressure equation like a source:
  *     p = p_tr + lambda_dot C k,   k = 1 / (1/(K~dtau) + 1/(K dt)),
- * with p_tr the pressure update without it.  With the deviatoric update
- * tauII D + lambda_dot = sqrt(J2(T)) and the yield condition tauII = A p + B c
- * this is linear in lambda_dot:
- *     lambda_dot = (sqrt(J2) - D (A p_tr + B c)) / (1 + D A C k).
- * Returns Lambda = lambda_dot / tauII (+inf at the apex, tauII = 0); *p gets
- * the corrected pressure.  Called for yielding centres only. */
-static double dilatant_lambda(double J2, double D, double p_tr, double c, double A, double B, double C, double k,
-                              double* p, double* tII_ret, double* Y_out, double* lamdot)
+ * with p_tr the pressure update without it.
+ * Regularisation (eta_vp > 0; the visco-plastic strain rate of the
+ * constitutive section, with the consistency viscosity of the literature the
+ * introduction cites): the consistency condition becomes
+ * tauII = A p + B c + eta_vp lambda_dot, i.e. the stress may exceed the bound
+ * by a viscous overstress.
+ * With the deviatoric update tauII D + lambda_dot = sqrt(J2(T)) and the bound
+ * max(0, A p + B c) (nothing is carried beyond the apex), lambda_dot solves
+ *     D (max(0, A p + B c) + eta_vp lambda_dot) + lambda_dot = sqrt(J2),
+ * p = p_tr + lambda_dot C k, whose left side increases with lambda_dot and is
+ * linear on either side of the apex.  The root of the piece with a
+ * non-negative bound,
+ *     lambda_dot = (sqrt(J2) - D (A p_tr + B c)) / (1 + D A C k + D eta_vp),
+ * is the solution when its bound is non-negative; otherwise the solution lies
+ * on the apex piece, lambda_dot = sqrt(J2) / (1 + D eta_vp).
+ * Returns Lambda = lambda_dot / tauII (+inf when tauII = 0); *p gets the
+ * corrected pressure.  Called for yielding centres only. */
+static double consistent_lambda(double J2, double D, double p_tr, double c, double A, double B, double C,
+                                double k, double eta_vp, double* p, double* tII_ret, double* Y_out, double* lamdot)
 {
-    double ld = (sqrt(J2) - D * (A * p_tr + B * c)) / (1.0 + D * A * C * k);
+    double ld = (sqrt(J2) - D * (A * p_tr + B * c)) / (1.0 + D * A * C * k + D * eta_vp);
+    if (A * (p_tr + ld * C * k) + B * c < 0.0) ld = sqrt(J2) / (1.0 + D * eta_vp);
     *p = p_tr + ld * C * k;
     double Y = A * (*p) + B * c;
     if (Y < 0.0) Y = 0.0;
+    double tII = Y + eta_vp * ld;
     *lamdot = ld;
-    *tII_ret = Y;
+    *tII_ret = tII;
     *Y_out = Y;
-    return Y > 0.0 ? ld / Y : INFINITY;
+    return tII > 0.0 ? ld / tII : INFINITY;
 }
 
 static double p_res_visc(const orc_state* s) { return isinf(s->prm.bulk) ? s->eta : s->prm.bulk * s->prm.dt; }
@@ -418,8 +433,9 @@ static double sweep2d(orc_state* s, int mode)
             double tret, Y, ld;
             const double ptr = s->pn[c];
             double lam = centre_lambda(J2, D, ptr, s->coh[c], A, B, &tret, &Y, &ld);
-            if (lam > 0.0 && s->C > 0.0)
-                lam = dilatant_lambda(J2, D, ptr, s->coh[c], A, B, s->C, kk, &s->pn[c], &tret, &Y, &ld);
+            if (lam > 0.0 && (s->C > 0.0 || s->prm.eta_vp > 0.0))
+                lam = consistent_lambda(J2, D, ptr, s->coh[c], A, B, s->C, kk, s->prm.eta_vp, &s->pn[c], &tret, &Y,
+                                        &ld);
             s->lamdot[c] = ld;
             s->tII[c] = tret;
             s->yld[c] = Y;
@@ -575,8 +591,9 @@ static double sweep3d(orc_state* s, int mode)
                 double tret, Y, ld;
                 const double ptr = s->pn[c];
                 double lam = centre_lambda(J2, D, ptr, s->coh[c], A, B, &tret, &Y, &ld);
-                if (lam > 0.0 && s->C > 0.0)
-                    lam = dilatant_lambda(J2, D, ptr, s->coh[c], A, B, s->C, kk, &s->pn[c], &tret, &Y, &ld);
+                if (lam > 0.0 && (s->C > 0.0 || s->prm.eta_vp > 0.0))
+                    lam = consistent_lambda(J2, D, ptr, s->coh[c], A, B, s->C, kk, s->prm.eta_vp, &s->pn[c], &tret,
+                                            &Y, &ld);
                 s->lamdot[c] = ld;
                 s->tII[c] = tret;
                 s->yld[c] = Y;

@@ -25,7 +25,7 @@ typedef struct orc_params {
     double lx, ly, lz;       /* domain extents, domain centred at the origin */
     double bulk, shear;      /* K, G */
     double visc;             /* mu_s; +inf for the elasto-plastic limit */
-    double phi_deg, psi_deg; /* friction and dilation angles (psi must be 0) */
+    double phi_deg, psi_deg; /* friction and dilation angles, 0 <= psi <= phi */
     double dt;               /* physical time increment */
     double erate[3];         /* background strain rate, diagonal */
     double tol;              /* residual tolerance (normalised) */
@@ -36,6 +36,9 @@ typedef struct orc_params {
                                 this iteration that has not converged */
     int    objective;        /* 1: objective (Jaumann) stress update at the start of every
                                 increment (orc_objective_update); 0: off */
+    double eta_vp;           /* consistency regularisation of the return: yielding points
+                                carry tauII = A p + B c + eta_vp lambda_dot (0: perfect
+                                plasticity) */
 } orc_params;
 
 typedef struct orc_stats {

@@ -34,7 +34,7 @@ class OrcParams(C.Structure):
         ("erate", C.c_double * 3), ("tol", C.c_double),
         ("max_iter", C.c_int), ("n_check", C.c_int),
         ("re", C.c_double), ("r", C.c_double), ("cfl", C.c_double),
-        ("freeze_iter", C.c_int), ("objective", C.c_int),
+        ("freeze_iter", C.c_int), ("objective", C.c_int), ("eta_vp", C.c_double),
     ]
 
 
@@ -94,6 +94,7 @@ def params_from_model(m) -> OrcParams:
     p.re, p.r, p.cfl = m.re, m.r, m.cfl
     p.freeze_iter = m.freeze_iter
     p.objective = m.objective
+    p.eta_vp = m.eta_vp
     return p
 
 

@@ -61,6 +61,7 @@ int validate(const ep_params* p)
     if (p->sweep < EP_SWEEP_AUTO || p->sweep > EP_SWEEP_UNFUSED) return EP_EINVAL;
     if (p->freeze_iter < 0 || p->guess_accept < 0) return EP_EINVAL;
     if (p->objective != 0 && p->objective != 1) return EP_EINVAL;
+    if (!(p->eta_vp >= 0.0) || std::isinf(p->eta_vp)) return EP_EINVAL;
     return EP_OK;
 }
 
@@ -225,6 +226,7 @@ SweepArgs<R> make_args(const ep_handle* h, R* const* from, R* const* to, R* cons
     a.B = (R)h->B;
     // dilatancy (psi > 0): pressure change per unit plastic rate in this update
     a.Cik = (R)(h->C / (ikt + ikd));
+    a.vp = (R)h->prm.eta_vp;
     // pressure residual factor: K dt, or the visco-elastic viscosity in the
     // incompressible limit (the pressure rate is then the divergence)
     a.rK = (R)((incompressible ? h->eta : h->prm.bulk * h->prm.dt) / (h->kdtau * h->L));

@@ -190,7 +190,7 @@ __global__ __launch_bounds__(256) void k_diag(SweepArgs<R> a, double* lamdot, do
             tii_s = sqrt(R(0.5) * (txx_s * txx_s + tyy_s * tyy_s) + bxy * bxy);
         }
         R ld, tii, Y;
-        R lam = centre_lambda(J2, a.D, pn, a.coh[c], a.A, a.B, a.Cik, ld, tii, Y);
+        R lam = centre_lambda(J2, a.D, pn, a.coh[c], a.A, a.B, a.Cik, a.vp, ld, tii, Y);
         lamdot[c] = (double)ld;
         tii_out[c] = (double)tii;
         yld[c] = (double)Y;

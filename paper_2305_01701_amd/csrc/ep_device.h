@@ -76,26 +76,32 @@ __device__ __forceinline__ void block_sum_to(double v, unsigned long long* dst, 
     __syncthreads();
 }
 
-// Dilatant return (psi > 0, potential sqrt(J2) - C p): the plastic rate
-// lamdot adds lamdot * Cik to the pressure of the update, and with
-// tauII D + lamdot = sqrt(J2) and tauII = A p + B c
-//     lamdot = (sqrt(J2) - D (A p + B c)) / (1 + D A Cik)
-// for the pressure p before the correction.  Returns lamdot; p is corrected.
+// Plastic rate of a dilatant or regularised return.  Dilatancy (psi > 0,
+// potential sqrt(J2) - C p): the plastic rate lamdot adds lamdot * Cik to the
+// pressure of the update.  Consistency regularisation: the returned tauII
+// exceeds the bound by vp * lamdot.  With tauII D + lamdot = sqrt(J2) and
+// tauII = max(0, A p + B c) + vp lamdot, lamdot is
+//     (sqrt(J2) - D (A p + B c)) / (1 + D A Cik + D vp)
+// (p before the correction) when the corrected bound is non-negative, else
+// the apex root sqrt(J2) / (1 + D vp).  Returns lamdot; p is corrected.
 template <typename R>
-__device__ __forceinline__ R dilatant_rate(R sq, R D, R& p, R c, R A, R B, R Cik)
+__device__ __forceinline__ R consistent_rate(R sq, R D, R& p, R c, R A, R B, R Cik, R vp)
 {
 #pragma clang fp contract(on)
-    const R ld = (sq - D * (A * p + B * c)) / (R(1) + D * A * Cik);
+    R ld = (sq - D * (A * p + B * c)) / (R(1) + D * A * Cik + D * vp);
+    if (A * (p + ld * Cik) + B * c < R(0)) ld = sq / (R(1) + D * vp);
     p = p + ld * Cik;
     return ld;
 }
 
 // Return mapping at a centre.  J2 is of the trial sums T; returns Lambda
 // (0 when elastic, +inf at the apex) and writes the plastic rate
-// D (tauII_tr - Y), the returned tauII and the bound Y; p gets the dilatant
-// pressure correction when Cik != 0.
+// D (tauII_tr - tauII), the returned tauII and the bound Y; p gets the
+// dilatant pressure correction when Cik != 0, and tauII the overstress
+// vp lamdot when vp != 0.
 template <typename R>
-__device__ __forceinline__ R centre_lambda(R J2, R D, R& p, R c, R A, R B, R Cik, R& lamdot, R& tii, R& Y)
+__device__ __forceinline__ R centre_lambda(R J2, R D, R& p, R c, R A, R B, R Cik, R vp, R& lamdot, R& tii,
+                                           R& Y)
 {
 #pragma clang fp contract(on)
     R tii_tr = sqrt(J2) / D;
@@ -105,14 +111,15 @@ __device__ __forceinline__ R centre_lambda(R J2, R D, R& p, R c, R A, R B, R Cik
     lamdot = R(0);
     tii = tii_tr;
     if (tii_tr > Y) {
-        if (Cik != R(0)) {
-            dilatant_rate(sqrt(J2), D, p, c, A, B, Cik);
+        R ld = R(0);
+        if (Cik != R(0) || vp != R(0)) {
+            ld = consistent_rate(sqrt(J2), D, p, c, A, B, Cik, vp);
             Y = A * p + B * c;
             Y = Y > R(0) ? Y : R(0);
         }
-        lam = D * (tii_tr / Y - R(1));
-        lamdot = D * (tii_tr - Y);
-        tii = Y;
+        tii = Y + vp * ld;
+        lam = D * (tii_tr / tii - R(1));
+        lamdot = D * (tii_tr - tii);
     }
     return lam;
 }
@@ -128,20 +135,21 @@ __device__ __forceinline__ double fast_sqrt(double x) { return sqrt(x); }
 // Y = max(0, A p + B c): elastic (tauII_tr <= Y) gives Lambda = 0 and the
 // factor 1/(D + Lambda) = 1/D; yielding gives Lambda = sqrt(J2)/Y - D and
 // 1/(D + Lambda) = Y/sqrt(J2), so the returned deviator T Y/sqrt(J2) lies on
-// the yield surface.  Same quantities as centre_lambda, one root and one
-// reciprocal.
+// the yield surface (above it by vp lamdot with the regularisation).  Same
+// quantities as centre_lambda, one root and one reciprocal.
 template <typename R>
-__device__ __forceinline__ R return_scale(R J2, R D, R invD, R& p, R c, R A, R B, R Cik, R& lam)
+__device__ __forceinline__ R return_scale(R J2, R D, R invD, R& p, R c, R A, R B, R Cik, R vp, R& lam)
 {
 #pragma clang fp contract(on)   // same rounding in every kernel that inlines it
     R Y = A * p + B * c;
     Y = Y > R(0) ? Y : R(0);
     const R sq = fast_sqrt(J2);
     if (sq * invD > Y) {
-        if (Cik != R(0)) {                       // dilatant return: corrected pressure
-            dilatant_rate(sq, D, p, c, A, B, Cik);
+        if (Cik != R(0) || vp != R(0)) {         // dilatant and/or regularised return
+            const R ld = consistent_rate(sq, D, p, c, A, B, Cik, vp);
             Y = A * p + B * c;
             Y = Y > R(0) ? Y : R(0);
+            Y = Y + vp * ld;                     // returned tauII
         }
         lam = sq * fast_rcp(Y) - D;
         return Y * fast_rcp(sq);

@@ -275,7 +275,7 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
                 R J2 = R(0.5) * (Txx * Txx + Tyy * Tyy + Tzz * Tzz) + Txyb * Txyb + Txzb * Txzb + Tyzb * Tyzb;
                 R lam;
                 const R ptr = pn;
-                R sc_ = return_scale(J2, D, a.invD, pn, cc[u], a.A, a.B, a.Cik, lam);
+                R sc_ = return_scale(J2, D, a.invD, pn, cc[u], a.A, a.B, a.Cik, a.vp, lam);
                 const bool own = la >= 2 && la < TX + 2 && lbb >= 2 && lbb < TY + 2 && c >= k0 && c < k1;
                 if (a.lam_mode != LAM_COMPUTE) {                 // frozen plasticity
                     if (a.lam_mode == LAM_FROZEN) {

@@ -53,7 +53,7 @@ __global__ __launch_bounds__(NT) void k_centre_2d(SweepArgs<R> a)
         R J2 = R(0.5) * (Txx * Txx + Tyy * Tyy) + Tb * Tb;
         R ld, tii, Y;
         const R ptr = pn;
-        R lam = centre_lambda(J2, a.D, pn, a.coh[c], a.A, a.B, a.Cik, ld, tii, Y);
+        R lam = centre_lambda(J2, a.D, pn, a.coh[c], a.A, a.B, a.Cik, a.vp, ld, tii, Y);
         if (a.lam_mode == LAM_FROZEN) {                  // frozen plasticity: Lambda held fixed
             lam = a.lam[c];
             if (a.Cik != R(0)) pn = ptr + lam * sqrt(J2) / (a.D + lam) * a.Cik;   // its dilatancy
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(NT) void k_centre_3d(SweepArgs<R> a)
         R J2 = R(0.5) * (Txx * Txx + Tyy * Tyy + Tzz * Tzz) + Txy * Txy + Txz * Txz + Tyz * Tyz;
         R ld, tii, Y;
         const R ptr = pn;
-        R lam = centre_lambda(J2, a.D, pn, a.coh[c], a.A, a.B, a.Cik, ld, tii, Y);
+        R lam = centre_lambda(J2, a.D, pn, a.coh[c], a.A, a.B, a.Cik, a.vp, ld, tii, Y);
         if (a.lam_mode == LAM_FROZEN) {                  // frozen plasticity: Lambda held fixed
             lam = a.lam[c];
             if (a.Cik != R(0)) pn = ptr + lam * sqrt(J2) / (a.D + lam) * a.Cik;   // its dilatancy

@@ -126,7 +126,7 @@ __device__ __forceinline__ void sweep_tile_2d(const SweepArgs<R>& a, int bx, int
             R J2 = R(0.5) * (Txx * Txx + Tyy * Tyy) + Tb * Tb;
             R lam;
             const R ptr = pn;
-            R sc_ = return_scale(J2, D, a.invD, pn, gc[u], a.A, a.B, a.Cik, lam);
+            R sc_ = return_scale(J2, D, a.invD, pn, gc[u], a.A, a.B, a.Cik, a.vp, lam);
             const bool own = la >= 2 && la < TX + 2 && lbb >= 2 && lbb < TY + 2;
             if (a.lam_mode == LAM_FROZEN) {
                 lam = a.lam[e];

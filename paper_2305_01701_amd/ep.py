@@ -54,7 +54,7 @@ class ep_params(C.Structure):
         ("re", C.c_double), ("r", C.c_double), ("cfl", C.c_double),
         ("precision", C.c_int), ("sweep", C.c_int), ("fp32_switch", C.c_double),
         ("fp32_stall", C.c_int), ("freeze_iter", C.c_int), ("guess_accept", C.c_double),
-        ("objective", C.c_int),
+        ("objective", C.c_int), ("eta_vp", C.c_double),
     ]
 
 
@@ -289,6 +289,7 @@ def params_from_model(m, precision: int = EP_FP64, sweep: int = EP_SWEEP_AUTO,
     p.freeze_iter = m.freeze_iter
     p.guess_accept = guess_accept
     p.objective = getattr(m, "objective", 0)
+    p.eta_vp = getattr(m, "eta_vp", 0.0)
     return p
 
 
