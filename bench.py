@@ -52,6 +52,14 @@ def workload(name):
                       "phi U[20,40], c0 U[1e-3,3e-3], inclusion radius U[0.05,0.15] at seeded positions, "
                       "strain increment 1e-4, tol 1e-6, one persistent launch per sweep under graph replays, "
                       "autotuned tile shapes")
+    if name.startswith("e2-"):
+        from ep_workloads import e2_symmetry
+        n = int(name[3:])
+        # tol 1e-9: the FP64 rounding floor of the normalised residual of the
+        # small increments at this resolution lies near 1e-10
+        return e2_symmetry(n, tol=1e-9), (f"symmetry study: 2d-383x191 (2:1 domain) pure shear, uniform c=2e-3, G=1, "
+                                          f"K=2, phi=30, mu_s=1e6, central pressure anomaly p=c/2 (r=0.1), total "
+                                          f"strain 2e-3 in {n} increments, tol 1e-9, FP64")
     if name.startswith("3d-") and name.endswith("-warm"):
         n = int(name[3:-5])
         return c3_3d(n), (f"3d-{n}^3 pure shear, spherical weak inclusion, strain increment 5e-5, tol 1e-6; "
@@ -272,6 +280,63 @@ def warm_compare(E, base_model, T, t_from, prec, steps_train=1200):
     }
 
 
+def mirror_asymmetry(f):
+    """Largest difference between a centre field (ny, nx) and its x-mirror,
+    its y-mirror and its point reflection, relative to the field's maximum."""
+    import numpy as np
+    top = max(float(np.abs(f).max()), 1e-300)
+    return {"x_mirror": float(np.abs(f - f[:, ::-1]).max() / top),
+            "y_mirror": float(np.abs(f - f[::-1, :]).max() / top),
+            "point": float(np.abs(f - f[::-1, ::-1]).max() / top)}
+
+
+def run_e2(args, E, name):
+    """The symmetry study: the whole loading schedule from the pressure-anomaly
+    start is the timed work (steps = its increments, no warm-up).  Reports the
+    stress integral over the centre column per increment and the symmetry of
+    the accumulated plastic strain."""
+    import torch
+    from ep_workloads import cohesion_field, pressure_anomaly
+    m, desc = workload(name)
+    m = m.with_(max_iter=500_000)
+    s = E.Solver(m, cohesion_field(m), precision=E.EP_FP64)
+    s.set("p", pressure_anomaly(m, 0.5 * m.c0, 0.1))
+    s.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for n in range(m.steps):
+        st = s.load_step()
+        stats.append(st)
+        log(f"increment {n + 1}/{m.steps}: status {st['status']} iters {st['iters']} yield {st['n_yield']} "
+            f"sxx_centre {st['sxx_centre']:.5e} {st['seconds']:.3f}s")
+        if st["status"] != 0:
+            break                      # the schedule cannot continue from an unconverged increment
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    iters = sum(st["iters"] for st in stats)
+    a64 = bytes_per_cell(2, 8) * m.n_cells
+    ms, nsw = s.sweep_timing(E.EP_FP64)
+    achieved = a64 / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    eps_p = s.get("eps_p").reshape(m.ny, m.nx)
+    s.close()
+    return {
+        "metric": METRIC, "value": round(iters * a64 / wall / 1e9, 1), "unit": "GB/s", "n_gpus": 1,
+        "steps": len(stats), "warmup": 0, "ms_per_step": round(wall / len(stats) * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc, "cells": m.n_cells, "increments_timed": f"1..{len(stats)}", "precision": "fp64"},
+        "s_per_step": round(wall / len(stats), 4), "iters_per_step": round(iters / len(stats), 1),
+        "failed_steps": sum(1 for st in stats if st["status"] != 0),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "fp64 PT sweep",
+                     "sweeps_timed": nsw, "avg_sweep_ms": round(ms, 4), "algorithmic_bytes_per_sweep": a64},
+        "cpu_baseline": None,
+        "e2": {"iters": [st["iters"] for st in stats], "n_yield": [st["n_yield"] for st in stats],
+               "sxx_centre": [st["sxx_centre"] for st in stats],
+               "eps_p_max": float(eps_p.max()), "eps_p_asymmetry": mirror_asymmetry(eps_p)},
+    }
+
+
 def run_warm(args, E, name):
     """The warm-start workload: plain vs learned guess at the named size."""
     base_model, desc = workload(name)
@@ -328,6 +393,9 @@ def main():
         return
     if args.workload.endswith("-warm"):
         print(json.dumps(run_warm(args, E, args.workload)), flush=True)
+        return
+    if args.workload.startswith("e2-"):
+        print(json.dumps(run_e2(args, E, args.workload)), flush=True)
         return
     m, desc = workload(args.workload)
     m = m.with_(max_iter=2_000_000)

@@ -95,6 +95,20 @@ def cohesion_field(m: Model) -> np.ndarray:
 # production values are reused.
 # --------------------------------------------------------------------------
 
+def e2_symmetry(increments: int, nx: int = 383, ny: int = 191, total_strain: float = 2e-3,
+                tol: float = 1e-11) -> Model:
+    """The symmetry study (section "Symmetry versus non-symmetry"): 2D pure
+    shear of a 2:1 domain with uniform cohesion 2e-3, G = 1, the elastic limit
+    (Deborah number 1e6: mu_s = 1e6), no objective update; the only
+    perturbation is a central pressure anomaly p = c0/2 (pressure_anomaly).  The same
+    total strain is applied in `increments` equal increments (7 and 180 in the
+    paper).  The total strain and the anomaly radius are not given; 2e-3 takes
+    the model through the first yield (about 8e-4) and the stress drop."""
+    return Model(ndim=2, nx=nx, ny=ny, lx=2.0, ly=1.0, visc=1e6, c0=2e-3, incl_factor=1.0,
+                 dt=total_strain / increments, tol=tol, n_check=100, steps=increments,
+                 name=f"e2-{nx}x{ny}-{increments}")
+
+
 def c1_small_2d() -> Model:
     return Model(ndim=2, nx=63, ny=63, tol=1e-8, steps=10, name="2d-63x63-fp64")
 

@@ -1,0 +1,50 @@
+"""GPU parity on the symmetry study's setup (section "Symmetry versus
+non-symmetry"; 95x47 version of the 2:1 model, central pressure anomaly
+p = c/2, 7 increments, tol 1e-11, FP64).
+
+Once the model yields, rounding-level asymmetry selects one of two
+mirror-image single-band branches, and the GPU's rounding need not select
+the oracle's.  What is unique is compared: iteration counts, yielding cells
+and the stress integral over the centre column at every increment; the
+fields equal the oracle's or their x-mirror image; the band is symmetric
+under the point reflection."""
+import numpy as np
+import pytest
+
+from ep_workloads import cohesion_field, e2_symmetry, pressure_anomaly
+from gpu_common import say
+from oracle.oracle import Oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def test_symmetry_study_matches_oracle_up_to_the_branch():
+    from paper_2305_01701_amd.ep import EP_FP64, Solver
+    m = e2_symmetry(7, nx=95, ny=47)
+    say("symmetry study 95x47, 7 increments")
+    p0 = pressure_anomaly(m, 0.5 * m.c0, 0.1)
+    g = Solver(m, cohesion_field(m), precision=EP_FP64)
+    o = Oracle(m)
+    g.set("p", p0)
+    o.set("p", p0)
+    for n in range(m.steps):
+        sg, so = g.load_step(), o.load_step()
+        assert sg["status"] == 0 and so["status"] == 0, n
+        assert sg["iters"] == so["iters"] and sg["n_yield"] == so["n_yield"], (n, sg["iters"], so["iters"])
+        assert sg["sxx_centre"] == pytest.approx(so["sxx_centre"], rel=1e-8)
+    eg = g.get("eps_p").reshape(m.ny, m.nx)
+    eo = o.get("eps_p").reshape(m.ny, m.nx)
+    top = eo.max()
+    assert top > 0 and np.abs(eo - eo[:, ::-1]).max() > 0.5 * top       # a single band
+    same = np.abs(eg - eo).max() / top
+    mirror = np.abs(eg - eo[:, ::-1]).max() / top
+    assert min(same, mirror) <= 1e-6, (same, mirror)
+    assert np.abs(eg - eg[::-1, ::-1]).max() <= 1e-6 * top
+    flip = mirror < same
+    for k, shape, odd in (("p", (m.ny, m.nx), False), ("txx", (m.ny, m.nx), False),
+                          ("vx", (m.ny, m.nx + 1), True), ("txy", (m.ny + 1, m.nx + 1), True)):
+        a, b = g.get(k).reshape(shape), o.get(k).reshape(shape)
+        ref = (-b[:, ::-1] if odd else b[:, ::-1]) if flip else b
+        assert np.abs(a - ref).max() <= 1e-6 * np.abs(b).max(), k
+    g.close()
+    o.close()
