@@ -109,6 +109,33 @@ def e2_symmetry(increments: int, nx: int = 383, ny: int = 191, total_strain: flo
                  name=f"e2-{nx}x{ny}-{increments}")
 
 
+def gaussian_cohesion(m: Model, rise: float = 0.2, width: float = 0.2, wall: float = 0.05,
+                      wall_factor: float = 2.0, centre=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """Per-cell cohesion of the heterogeneous setups (section on the initial
+    conditions and heterogeneities), x fastest: c0 at the centre of the model,
+    rising as a Gaussian towards the walls,
+        c = c0 (1 + rise (1 - exp(-r^2 / (width L)^2))),
+    with a jump to wall_factor c0 in the cells whose centre lies within
+    wall L of a wall (L the smallest extent).  The paper gives the end values
+    (2e-3 at the centre, 4e-3 at the walls) but not the width, the rise of the
+    Gaussian part or the jump's distance; these defaults are readings.  An
+    off-centre `centre` moves the Gaussian (not the wall band) and breaks the
+    mirror symmetry of the setup."""
+    L = min(m.lx, m.ly, m.lz if m.ndim == 3 else m.ly)
+    axes = [-0.5 * e + (np.arange(n) + 0.5) * (e / n) for e, n in ((m.lx, m.nx), (m.ly, m.ny), (m.lz, m.nz))]
+    if m.ndim == 2:
+        Y, X = np.meshgrid(axes[1], axes[0], indexing="ij")
+        r2 = (X - centre[0]) ** 2 + (Y - centre[1]) ** 2
+        dwall = np.minimum(0.5 * m.lx - np.abs(X), 0.5 * m.ly - np.abs(Y))
+    else:
+        Z, Y, X = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+        r2 = (X - centre[0]) ** 2 + (Y - centre[1]) ** 2 + (Z - centre[2]) ** 2
+        dwall = np.minimum(np.minimum(0.5 * m.lx - np.abs(X), 0.5 * m.ly - np.abs(Y)), 0.5 * m.lz - np.abs(Z))
+    c = m.c0 * (1.0 + rise * (1.0 - np.exp(-r2 / (width * L) ** 2)))
+    c[dwall < wall * L] = wall_factor * m.c0
+    return np.ascontiguousarray(c.ravel())
+
+
 def c1_small_2d() -> Model:
     return Model(ndim=2, nx=63, ny=63, tol=1e-8, steps=10, name="2d-63x63-fp64")
 
