@@ -60,7 +60,7 @@ def _mask(shape, walls):
     return sp.diags(keep.ravel().astype(np.float64))
 
 
-def solve(m, old: dict, cohesion=None, lam=None) -> dict:
+def solve(m, old: dict, cohesion=None, lam=None, shear_field=None) -> dict:
     """Solve one elastic increment.
 
     m: ep_workloads.Model (visc must be inf); old: dict with p_old, txx_old,
@@ -70,7 +70,10 @@ def solve(m, old: dict, cohesion=None, lam=None) -> dict:
     lam (2D only): a fixed plastic multiplier Lambda per cell (frozen
     plasticity).  The deviator then satisfies tau (1/(G dt) + Lambda) =
     tau^/(G dt) + 2 (sym grad v - div v / 3 I), with Lambda at a vertex the
-    mean of its four cells -- still linear in v."""
+    mean of its four cells -- still linear in v.
+
+    shear_field (2D only): a shear modulus per cell; the compliance 1/(G dt) of a vertex
+    is the mean of its four cells' compliances."""
     assert np.isinf(m.visc)
     nx, ny = m.nx, m.ny
     dx, dy = m.lx / nx, m.ly / ny
@@ -92,17 +95,24 @@ def solve(m, old: dict, cohesion=None, lam=None) -> dict:
         eyy = sp.hstack([Z(nc, nvx), Dy_vy]) - div / 3.0
         exy = mxy @ (0.5 * sp.hstack([Gy_vx, Gx_vy]))
         # stresses = const + L v; compliance factor c = 1 / (1/(G dt) + Lambda)
-        igd = 1.0 / (G * dt)
+        if shear_field is None:
+            igc = np.full(nc, 1.0 / (m.shear * dt))
+        else:
+            igc = 1.0 / (np.asarray(shear_field, dtype=np.float64).ravel() * dt)
+        I2 = igc.reshape(ny, nx)
+        igv = np.full((ny + 1, nx + 1), 1.0 / (m.shear * dt))      # wall vertices carry no stress
+        igv[1:ny, 1:nx] = 0.25 * (I2[:-1, :-1] + I2[:-1, 1:] + I2[1:, :-1] + I2[1:, 1:])
+        igv = igv.ravel()
         lc = np.zeros(nc) if lam is None else np.asarray(lam, dtype=np.float64)
         L2 = lc.reshape(ny, nx)
         lv = np.zeros((ny + 1, nx + 1))
         lv[1:ny, 1:nx] = 0.25 * (L2[:-1, :-1] + L2[:-1, 1:] + L2[1:, :-1] + L2[1:, 1:])
-        cc = sp.diags(1.0 / (igd + lc))
-        cv = sp.diags(1.0 / (igd + lv.ravel()))
+        cc = sp.diags(1.0 / (igc + lc))
+        cv = sp.diags(1.0 / (igv + lv.ravel()))
         P_L, P_0 = -K * dt * div, old["p_old"]
-        Txx_L, Txx_0 = cc @ (2 * exx), cc @ (igd * old["txx_old"])
-        Tyy_L, Tyy_0 = cc @ (2 * eyy), cc @ (igd * old["tyy_old"])
-        Txy_L, Txy_0 = cv @ (2 * exy), cv @ (mxy @ (igd * old["txy_old"]))
+        Txx_L, Txx_0 = cc @ (2 * exx), cc @ (igc * old["txx_old"])
+        Tyy_L, Tyy_0 = cc @ (2 * eyy), cc @ (igc * old["tyy_old"])
+        Txy_L, Txy_0 = cv @ (2 * exy), cv @ (mxy @ (igv * old["txy_old"]))
         # momentum operators
         Gx_c = _op([_back_interior(nx, dx), None], sh["c"])     # cells -> x-faces
         Dy_xy = _op([None, _fwd(ny, dy)], sh["xy"])             # vertices -> x-faces

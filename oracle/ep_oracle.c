@@ -65,6 +65,7 @@ struct orc_state {
     double *p, *txx, *tyy, *tzz, *txy, *txz, *tyz;
     double *p_old, *txx_old, *tyy_old, *tzz_old, *txy_old, *txz_old, *tyz_old;
     double *coh;
+    double *igdc;             /* per-cell 1/(G dt) (NULL: uniform G = prm.shear) */
     /* accumulators and diagnostics */
     double *ux, *uy, *uz;
     double *exx, *eyy, *ezz, *exy, *exz, *eyz;
@@ -237,7 +238,7 @@ void orc_free(orc_state* s)
         &s->vx, &s->vy, &s->vz, &s->vxn, &s->vyn, &s->vzn, &s->vx0, &s->vy0, &s->vz0,
         &s->ux, &s->uy, &s->uz, &s->p, &s->txx, &s->tyy, &s->tzz,
         &s->p_old, &s->txx_old, &s->tyy_old, &s->tzz_old, &s->pn, &s->txxn, &s->tyyn, &s->tzzn,
-        &s->coh, &s->dv, &s->exx, &s->eyy, &s->ezz, &s->eps_p, &s->lam, &s->tII, &s->yld, &s->lamdot, &s->lamf,
+        &s->coh, &s->igdc, &s->dv, &s->exx, &s->eyy, &s->ezz, &s->eps_p, &s->lam, &s->tII, &s->yld, &s->lamdot, &s->lamf,
         &s->txy, &s->txy_old, &s->txyn, &s->Txy, &s->exy,
         &s->txz, &s->txz_old, &s->txzn, &s->Txz, &s->exz,
         &s->tyz, &s->tyz_old, &s->tyzn, &s->Tyz, &s->eyz,
@@ -382,6 +383,16 @@ static double consistent_lambda(double J2, double D, double p_tr, double c, doub
 
 static double p_res_visc(const orc_state* s) { return isinf(s->prm.bulk) ? s->eta : s->prm.bulk * s->prm.dt; }
 
+/* Compliance 1/(G dt) of the interior vertex (i, j): the uniform value, or the
+ * mean over its four cells when G is given per cell. */
+static double igd_vertex(const orc_state* s, int i, int j, double igd)
+{
+    if (!s->igdc) return igd;
+    const int nx = s->nx;
+    return 0.25 * (s->igdc[(i - 1) + (long)nx * (j - 1)] + s->igdc[i + (long)nx * (j - 1)]
+                 + s->igdc[(i - 1) + (long)nx * j] + s->igdc[i + (long)nx * j]);
+}
+
 static double sweep2d(orc_state* s, int mode)
 {
     const int physical = mode == 1;
@@ -394,7 +405,6 @@ static double sweep2d(orc_state* s, int mode)
     const double igd = 1.0 / (s->prm.shear * s->prm.dt);
     const double ikd = 1.0 / (s->prm.bulk * s->prm.dt);
     const double kk = 1.0 / (ikt + ikd);      /* pressure compliance of one update */
-    const double D = igt + igd + s->inv_mus;
     const double A = s->A, B = s->B;
 
     /* 1. divergence and pressure at centres */
@@ -413,7 +423,7 @@ static double sweep2d(orc_state* s, int mode)
             if (i == 0 || i == nx || j == 0 || j == ny) { s->Txy[XY2(i, j)] = 0.0; continue; }
             double exy = 0.5 * ((s->vx[VX2(i, j)] - s->vx[VX2(i, j - 1)]) / dy
                               + (s->vy[VY2(i, j)] - s->vy[VY2(i - 1, j)]) / dx);
-            s->Txy[XY2(i, j)] = s->txy[XY2(i, j)] * igt + s->txy_old[XY2(i, j)] * igd + 2.0 * exy;
+            s->Txy[XY2(i, j)] = s->txy[XY2(i, j)] * igt + s->txy_old[XY2(i, j)] * igd_vertex(s, i, j, igd) + 2.0 * exy;
         }
     /* 3. normal trial and return mapping at centres */
     long long ny_count = 0;
@@ -425,8 +435,10 @@ static double sweep2d(orc_state* s, int mode)
             double div = s->dv[c];
             double exx = (s->vx[VX2(i + 1, j)] - s->vx[VX2(i, j)]) / dx - div / 3.0;
             double eyy = (s->vy[VY2(i, j + 1)] - s->vy[VY2(i, j)]) / dy - div / 3.0;
-            double Txx = s->txx[c] * igt + s->txx_old[c] * igd + 2.0 * exx;
-            double Tyy = s->tyy[c] * igt + s->tyy_old[c] * igd + 2.0 * eyy;
+            const double igdc = s->igdc ? s->igdc[c] : igd;
+            const double D = igt + igdc + s->inv_mus;
+            double Txx = s->txx[c] * igt + s->txx_old[c] * igdc + 2.0 * exx;
+            double Tyy = s->tyy[c] * igt + s->tyy_old[c] * igdc + 2.0 * eyy;
             double Tb = 0.25 * (s->Txy[XY2(i, j)] + s->Txy[XY2(i + 1, j)]
                               + s->Txy[XY2(i, j + 1)] + s->Txy[XY2(i + 1, j + 1)]);
             double J2 = 0.5 * (Txx * Txx + Tyy * Tyy) + Tb * Tb;
@@ -460,7 +472,7 @@ static double sweep2d(orc_state* s, int mode)
             if (i == 0 || i == nx || j == 0 || j == ny) { s->txyn[XY2(i, j)] = 0.0; continue; }
             double lv = 0.25 * (s->lam[C2(i - 1, j - 1)] + s->lam[C2(i, j - 1)]
                               + s->lam[C2(i - 1, j)] + s->lam[C2(i, j)]);
-            s->txyn[XY2(i, j)] = s->Txy[XY2(i, j)] / (D + lv);
+            s->txyn[XY2(i, j)] = s->Txy[XY2(i, j)] / (igt + igd_vertex(s, i, j, igd) + s->inv_mus + lv);
             dtm = fmax(dtm, fabs(s->txyn[XY2(i, j)] - s->txy[XY2(i, j)]));
         }
     /* 5. momentum residual and velocity update at interior faces */
@@ -959,6 +971,23 @@ static void objective3d(orc_state* s)
     copy_n(s->txz, xz, nxz);
     copy_n(s->tyz, yz, nyz);
     free(wxy); free(wxz); free(wyz); free(pn); free(xx); free(yy); free(zz); free(xy); free(xz); free(yz);
+}
+
+/* Per-cell shear modulus (2D; the heterogeneous setups' G field).  The
+ * physical compliance 1/(G dt) of a cell replaces the uniform one in its
+ * stress update; a vertex takes the mean compliance of its four cells (the
+ * harmonic mean of G; a reading).  The pseudo-time steps stay those of
+ * prm.shear, which must bound every G.  Returns 0, or -1 (3D, or a G that
+ * is not in (0, prm.shear]). */
+int orc_set_shear_modulus(orc_state* s, const double* G)
+{
+    const long nc = (long)s->nx * s->ny;
+    if (s->ndim != 2) return -1;
+    for (long c = 0; c < nc; ++c)
+        if (!(G[c] > 0.0) || !(G[c] <= s->prm.shear)) return -1;
+    if (!s->igdc) s->igdc = (double*)malloc((size_t)nc * sizeof(double));
+    for (long c = 0; c < nc; ++c) s->igdc[c] = 1.0 / (G[c] * s->prm.dt);
+    return 0;
 }
 
 void orc_set_strain_rate(orc_state* s, const double erate[3])

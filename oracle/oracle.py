@@ -76,6 +76,8 @@ def lib():
         L.orc_history_len.argtypes = [C.c_void_p]
         L.orc_objective_update.argtypes = [C.c_void_p]
         L.orc_set_strain_rate.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
+        L.orc_set_shear_modulus.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
+        L.orc_set_shear_modulus.restype = C.c_int
         L.orc_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -152,6 +154,14 @@ class Oracle:
     def set_strain_rate(self, erate) -> None:
         """Background strain rate of the next increments."""
         lib().orc_set_strain_rate(self._h, (C.c_double * 3)(*[float(x) for x in erate]))
+
+    def set_shear_modulus(self, G) -> None:
+        """Per-cell shear modulus (2D, x fastest, every value in (0, shear])."""
+        a = np.ascontiguousarray(G, dtype=np.float64).ravel()
+        if a.size != self.model.nx * self.model.ny:
+            raise ValueError("set_shear_modulus: one value per cell expected")
+        if lib().orc_set_shear_modulus(self._h, _dptr(a)) != 0:
+            raise ValueError("set_shear_modulus: 2D only, 0 < G <= shear")
 
     def objective_update(self) -> None:
         """Objective (Jaumann) update of the current stresses with the current
