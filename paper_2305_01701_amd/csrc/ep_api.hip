@@ -93,6 +93,7 @@ size_t carve(const ep_params* p, ep_handle* h, char* base)
     char* q;
     q = take(b64); if (h) h->coh64 = (double*)q;
     q = take(b64); if (h) h->lam64 = (double*)q;
+    q = p->ndim == 2 ? take(b64) : nullptr; if (h) h->igdc64 = (double*)q;
     for (int d = 0; d < 3; ++d) {
         char* a = d < p->ndim ? take(b64) : nullptr;
         char* u = d < p->ndim ? take(b64) : nullptr;
@@ -118,6 +119,7 @@ size_t carve(const ep_params* p, ep_handle* h, char* base)
         if (h) h->old32[f] = (float*)q;
     }
     q = fp32 ? take(b32) : nullptr; if (h) h->coh32 = (float*)q;
+    q = fp32 && p->ndim == 2 ? take(b32) : nullptr; if (h) h->igdc32 = (float*)q;
     q = fp32 ? take(b32) : nullptr; if (h) h->lam32 = (float*)q;
     for (int d = 0; d < 3; ++d) {
         q = d < p->ndim ? take(b64) : nullptr;
@@ -227,6 +229,12 @@ SweepArgs<R> make_args(const ep_handle* h, R* const* from, R* const* to, R* cons
     // dilatancy (psi > 0): pressure change per unit plastic rate in this update
     a.Cik = (R)(h->C / (ikt + ikd));
     a.vp = (R)h->prm.eta_vp;
+    a.imus = (R)h->inv_mus;
+    a.igdc = nullptr;
+    if (h->has_g) {
+        if constexpr (sizeof(R) == 4) a.igdc = h->igdc32;
+        else a.igdc = h->igdc64;
+    }
     // pressure residual factor: K dt, or the visco-elastic viscosity in the
     // incompressible limit (the pressure rate is then the divergence)
     a.rK = (R)((incompressible ? h->eta : h->prm.bulk * h->prm.dt) / (h->kdtau * h->L));
@@ -369,6 +377,7 @@ void ensure_it32(ep_handle* h)
         for (int o = 0; o < O_N; ++o)
             if (h->old64[o]) launch_to_f32(h->old32[o], h->old64[o], h->nelem, h->st);
         launch_to_f32(h->coh32, h->coh64, h->nelem, h->st);
+        if (h->has_g) launch_to_f32(h->igdc32, h->igdc64, h->nelem, h->st);
         h->old32_valid = true;
     }
     if (!h->it32_valid) {
@@ -907,6 +916,27 @@ int ep_residual(ep_handle* h, ep_residual_info* r)
     if ((rc = read_red(h, red))) return rc;
     r->physical = red[RED_MOM];
     return EP_OK;
+}
+
+int ep_set_shear_modulus(ep_handle* h, const double* shear)
+{
+    if (!h || !shear || h->in_batch) return EP_EINVAL;
+    if (h->ndim != 2) return set_err(h, EP_EINVAL, "a per-cell shear modulus is supported in 2D only");
+    const long nc = (long)h->nx * h->ny;
+    std::vector<double> igd(nc);
+    for (long c = 0; c < nc; ++c) {
+        if (!(shear[c] > 0.0) || !(shear[c] <= h->prm.shear))
+            return set_err(h, EP_EINVAL, "shear modulus of cell %ld not in (0, shear]", c);
+        igd[c] = 1.0 / (shear[c] * h->prm.dt);
+    }
+    std::vector<double> pad(h->nelem, 0.0);
+    int ext[3] = {h->nx, h->ny, 1};
+    scatter(h, igd.data(), ext, pad);
+    HIPCHK(h, hipMemcpyAsync(h->igdc64, pad.data(), h->nelem * sizeof(double), hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    h->has_g = true;
+    h->old32_valid = false;                         // the FP32 copy is re-derived before FP32 sweeps
+    return upload_tables(h);
 }
 
 int ep_set_strain_rate(ep_handle* h, const double erate[3])

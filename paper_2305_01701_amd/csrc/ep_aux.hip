@@ -130,7 +130,9 @@ __device__ R shear_T(const SweepArgs<R>& a, int f, int of, long e, long s1, long
                      const R* v1, const R* v2)
 {
     R e2 = (v1[e] - v1[e - s1]) * i1 + (v2[e] - v2[e - s2]) * i2;
-    return a.it[f][e] * a.igt + a.old[of][e] * a.igd + e2;
+    // a per-cell G exists in 2D only, where the shear points are the vertices
+    const R ig = a.igdc ? vertex_compliance(a.igdc, e, (long)a.sy) : a.igd;
+    return a.it[f][e] * a.igt + a.old[of][e] * ig + e2;
 }
 
 template <typename R>
@@ -152,8 +154,10 @@ __global__ __launch_bounds__(256) void k_diag(SweepArgs<R> a, double* lamdot, do
         R dvz = d3 ? (a.it[F_VZ][c + sz] - a.it[F_VZ][c]) * a.idz : R(0);
         R div = dvx + dvy + dvz;
         R pn = (a.it[F_P][c] * a.ikt + a.old[O_P][c] * a.ikd - div) / (a.ikt + a.ikd);
-        R Txx = a.it[F_TXX][c] * a.igt + a.old[O_TXX][c] * a.igd + R(2) * (dvx - div / R(3));
-        R Tyy = a.it[F_TYY][c] * a.igt + a.old[O_TYY][c] * a.igd + R(2) * (dvy - div / R(3));
+        const R igc = a.igdc ? a.igdc[c] : a.igd;        // per-cell G (2D): compliance and D
+        const R Dc = a.igdc ? a.igt + igc + a.imus : a.D;
+        R Txx = a.it[F_TXX][c] * a.igt + a.old[O_TXX][c] * igc + R(2) * (dvx - div / R(3));
+        R Tyy = a.it[F_TYY][c] * a.igt + a.old[O_TYY][c] * igc + R(2) * (dvy - div / R(3));
         auto Txy = [&](long e, int ii, int jj) -> R {
             if (ii <= 0 || ii >= a.nx || jj <= 0 || jj >= a.ny) return R(0);
             return shear_T(a, F_TXY, O_TXY, e, sy, 1, a.idy, a.idx, vx, vy);
@@ -190,7 +194,7 @@ __global__ __launch_bounds__(256) void k_diag(SweepArgs<R> a, double* lamdot, do
             tii_s = sqrt(R(0.5) * (txx_s * txx_s + tyy_s * tyy_s) + bxy * bxy);
         }
         R ld, tii, Y;
-        R lam = centre_lambda(J2, a.D, pn, a.coh[c], a.A, a.B, a.Cik, a.vp, ld, tii, Y);
+        R lam = centre_lambda(J2, Dc, pn, a.coh[c], a.A, a.B, a.Cik, a.vp, ld, tii, Y);
         lamdot[c] = (double)ld;
         tii_out[c] = (double)tii;
         yld[c] = (double)Y;

@@ -94,6 +94,16 @@ __device__ __forceinline__ R consistent_rate(R sq, R D, R& p, R c, R A, R B, R C
     return ld;
 }
 
+// Compliance 1/(G dt) of the interior 2D vertex at element e when G is given
+// per cell: the mean over its four cells (cells and vertices share the
+// element stride sy).
+template <typename R>
+__device__ __forceinline__ R vertex_compliance(const R* __restrict__ igdc, long e, long sy)
+{
+#pragma clang fp contract(on)
+    return R(0.25) * (igdc[e - 1 - sy] + igdc[e - sy] + igdc[e - 1] + igdc[e]);
+}
+
 // Return mapping at a centre.  J2 is of the trial sums T; returns Lambda
 // (0 when elastic, +inf at the apex) and writes the plastic rate
 // D (tauII_tr - tauII), the returned tauII and the bound Y; p gets the

@@ -41,6 +41,7 @@ struct ep_handle {
     int cur64;
     double* old64[ep::O_N];
     double *coh64, *lam64;
+    double* igdc64;        // 2D: per-cell 1/(G dt) when has_g
     double* vstart64[3];
     double* u64[3];
     double* e64[6];
@@ -49,6 +50,8 @@ struct ep_handle {
     int cur32;
     float* old32[ep::O_N];
     float *coh32, *lam32;
+    float* igdc32;
+    bool has_g;
     unsigned long long* red;
     bool it32_valid, old32_valid, it64_valid;
     bool timing;

@@ -44,6 +44,8 @@ struct SweepArgs {
     R Cik;                 // dilatancy: C of the plastic potential / (ikt + ikd), the pressure
                            // change per unit plastic rate (0 for psi = 0)
     R vp;                  // consistency regularisation viscosity eta_vp (0: perfect plasticity)
+    const R* igdc;         // 2D: per-cell 1/(G dt) (nullptr: uniform G, igd)
+    R imus;                // 1/mu_s
     R rK, rG;              // pseudo-rate -> residual factors: K dt/(K~dtau L), eta/(G~dtau L)
     R ebx, eby, ebz;       // background strain rate subtracted from the stored velocities
                            // (FP32 fields store v - erate * x; 0 when v is stored in full)

@@ -27,7 +27,8 @@ __device__ __forceinline__ R vertex_T2(const SweepArgs<R>& a, long e, int i, int
     const R* vx = a.it[F_VX];
     const R* vy = a.it[F_VY];
     R e2 = (vx[e] - vx[e - a.sy]) * a.idy + (vy[e] - vy[e - 1]) * a.idx;
-    return a.it[F_TXY][e] * a.igt + a.old[O_TXY][e] * a.igd + e2;
+    const R ig = a.igdc ? vertex_compliance(a.igdc, e, (long)a.sy) : a.igd;
+    return a.it[F_TXY][e] * a.igt + a.old[O_TXY][e] * ig + e2;
 }
 
 // ------------------------------------------------------------------ 2D
@@ -46,21 +47,23 @@ __global__ __launch_bounds__(NT) void k_centre_2d(SweepArgs<R> a)
         R dvy = (vy[c + a.sy] - vy[c]) * a.idy + a.eby;
         R div = dvx + dvy;
         R pn = (a.it[F_P][c] * a.ikt + a.old[O_P][c] * a.ikd - div) / (a.ikt + a.ikd);
-        R Txx = a.it[F_TXX][c] * a.igt + a.old[O_TXX][c] * a.igd + R(2) * (dvx - div / R(3));
-        R Tyy = a.it[F_TYY][c] * a.igt + a.old[O_TYY][c] * a.igd + R(2) * (dvy - div / R(3));
+        const R igc = a.igdc ? a.igdc[c] : a.igd;        // per-cell G: the cell's compliance and D
+        const R Dc = a.igdc ? a.igt + igc + a.imus : a.D;
+        R Txx = a.it[F_TXX][c] * a.igt + a.old[O_TXX][c] * igc + R(2) * (dvx - div / R(3));
+        R Tyy = a.it[F_TYY][c] * a.igt + a.old[O_TYY][c] * igc + R(2) * (dvy - div / R(3));
         R Tb = R(0.25) * (vertex_T2(a, c, i, j) + vertex_T2(a, c + 1, i + 1, j)
                         + vertex_T2(a, c + a.sy, i, j + 1) + vertex_T2(a, c + a.sy + 1, i + 1, j + 1));
         R J2 = R(0.5) * (Txx * Txx + Tyy * Tyy) + Tb * Tb;
         R ld, tii, Y;
         const R ptr = pn;
-        R lam = centre_lambda(J2, a.D, pn, a.coh[c], a.A, a.B, a.Cik, a.vp, ld, tii, Y);
+        R lam = centre_lambda(J2, Dc, pn, a.coh[c], a.A, a.B, a.Cik, a.vp, ld, tii, Y);
         if (a.lam_mode == LAM_FROZEN) {                  // frozen plasticity: Lambda held fixed
             lam = a.lam[c];
-            if (a.Cik != R(0)) pn = ptr + lam * sqrt(J2) / (a.D + lam) * a.Cik;   // its dilatancy
+            if (a.Cik != R(0)) pn = ptr + lam * sqrt(J2) / (Dc + lam) * a.Cik;   // its dilatancy
         } else {
             a.lam[c] = lam;                              // read by the shear-point kernel
         }
-        R txx = Txx / (a.D + lam), tyy = Tyy / (a.D + lam);
+        R txx = Txx / (Dc + lam), tyy = Tyy / (Dc + lam);
         a.nx_[F_P][c] = pn;
         a.nx_[F_TXX][c] = txx;
         a.nx_[F_TYY][c] = tyy;
@@ -90,7 +93,8 @@ __global__ __launch_bounds__(NT) void k_vertex_2d(SweepArgs<R> a)
         if (i > 0 && i < a.nx && j > 0 && j < a.ny) {
             R T = vertex_T2(a, e, i, j);
             R lv = R(0.25) * (a.lam[e - a.sy - 1] + a.lam[e - a.sy] + a.lam[e - 1] + a.lam[e]);
-            t = T / (a.D + lv);
+            const R Dv = a.igdc ? a.igt + vertex_compliance(a.igdc, e, (long)a.sy) + a.imus : a.D;
+            t = T / (Dv + lv);
         }
         a.nx_[F_TXY][e] = t;
         if (MODE == MODE_CHECK) rmax = (double)(fabs(t - a.it[F_TXY][e]) * a.rG);

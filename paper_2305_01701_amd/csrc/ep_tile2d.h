@@ -94,7 +94,8 @@ __device__ __forceinline__ void sweep_tile_2d(const SweepArgs<R>& a, int bx, int
         R t = R(0);
         if (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1) {
             R e2 = (s_vx[q] - s_vx[q - W]) * idy + (s_vy[q] - s_vy[q - 1]) * idx;
-            t = gxy[u] * igt + gxyo[u] * igd + e2;
+            const R ig = a.igdc ? vertex_compliance(a.igdc, i + sy * j, sy) : igd;
+            t = gxy[u] * igt + gxyo[u] * ig + e2;
         }
         s_Txy[q] = t;
     }
@@ -120,17 +121,21 @@ __device__ __forceinline__ void sweep_tile_2d(const SweepArgs<R>& a, int bx, int
             R div = dvx + dvy;
             const R pk = gp[u], txk = gsx[u], tyk = gsy[u];
             R pn = (pk * ikt + gpo[u] * ikd - div) * a.ikk;
-            R Txx = txk * igt + gsxo[u] * igd + R(2) * (dvx - div / R(3));
-            R Tyy = tyk * igt + gsyo[u] * igd + R(2) * (dvy - div / R(3));
+            // per-cell G: the cell's compliance and its D
+            const R igc = a.igdc ? a.igdc[e] : igd;
+            const R Dc = a.igdc ? igt + igc + a.imus : D;
+            const R invDc = a.igdc ? R(1) / Dc : a.invD;
+            R Txx = txk * igt + gsxo[u] * igc + R(2) * (dvx - div / R(3));
+            R Tyy = tyk * igt + gsyo[u] * igc + R(2) * (dvy - div / R(3));
             R Tb = R(0.25) * (s_Txy[q] + s_Txy[q + 1] + s_Txy[q + W] + s_Txy[q + W + 1]);
             R J2 = R(0.5) * (Txx * Txx + Tyy * Tyy) + Tb * Tb;
             R lam;
             const R ptr = pn;
-            R sc_ = return_scale(J2, D, a.invD, pn, gc[u], a.A, a.B, a.Cik, a.vp, lam);
+            R sc_ = return_scale(J2, Dc, invDc, pn, gc[u], a.A, a.B, a.Cik, a.vp, lam);
             const bool own = la >= 2 && la < TX + 2 && lbb >= 2 && lbb < TY + 2;
             if (a.lam_mode == LAM_FROZEN) {
                 lam = a.lam[e];
-                sc_ = R(1) / (D + lam);
+                sc_ = R(1) / (Dc + lam);
                 // dilatancy of the held Lambda: lamdot = Lambda sqrt(J2) / (D + Lambda)
                 if (a.Cik != R(0)) pn = ptr + lam * fast_sqrt(J2) * sc_ * a.Cik;
             } else if (a.lam_mode == LAM_STORE && own) {
@@ -164,7 +169,8 @@ __device__ __forceinline__ void sweep_tile_2d(const SweepArgs<R>& a, int bx, int
             R t = R(0);
             if (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1) {
                 R lv = R(0.25) * (s_lam[q - W - 1] + s_lam[q - W] + s_lam[q - 1] + s_lam[q]);
-                t = s_Txy[q] * fast_rcp(D + lv);
+                const R Dv = a.igdc ? igt + vertex_compliance(a.igdc, i + sy * j, sy) + a.imus : D;
+                t = s_Txy[q] * fast_rcp(Dv + lv);
             }
             s_nxy[q] = t;
             if (la < TX + 2 + hx && lbb < TY + 2 + hy && i <= nx && j <= ny) {

@@ -34,7 +34,7 @@ FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
 # every symbol include/ep.h declares
 SYMBOLS = ["ep_abi_version", "ep_workspace_size", "ep_init", "ep_load_step", "ep_sweep",
            "ep_residual", "ep_fields", "ep_field_shape", "ep_destroy", "ep_last_error",
-           "ep_enable_timing", "ep_sweep_timing", "ep_step_history", "ep_set_guess", "ep_objective_update", "ep_set_strain_rate",
+           "ep_enable_timing", "ep_sweep_timing", "ep_step_history", "ep_set_guess", "ep_objective_update", "ep_set_strain_rate", "ep_set_shear_modulus",
            "ep_batch_workspace_size", "ep_batch_init", "ep_batch_tune", "ep_batch_tile_shape",
            "ep_batch_load_step", "ep_batch_model", "ep_batch_enable_timing", "ep_batch_timing",
            "ep_batch_destroy", "ep_batch_last_error",
@@ -113,6 +113,7 @@ def lib():
         L.ep_set_guess.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.ep_objective_update.argtypes = [vp]
         L.ep_set_strain_rate.argtypes = [vp, C.POINTER(C.c_double)]
+        L.ep_set_shear_modulus.argtypes = [vp, C.POINTER(C.c_double)]
         L.ep_batch_workspace_size.argtypes = [C.c_int, C.POINTER(ep_params), C.POINTER(C.c_size_t)]
         L.ep_batch_init.argtypes = [C.c_int, C.POINTER(ep_params), C.POINTER(C.POINTER(C.c_double)), vp,
                                     C.c_size_t, vp, C.POINTER(vp)]
@@ -349,6 +350,14 @@ class ModelView:
         """Background strain rate of the next increments (loading schedule)."""
         arr = (C.c_double * 3)(*[float(x) for x in erate])
         self._check(lib().ep_set_strain_rate(self.h, arr), "ep_set_strain_rate")
+
+    def set_shear_modulus(self, shear) -> None:
+        """Per-cell shear modulus (2D, x fastest, each in (0, shear])."""
+        arr = np.ascontiguousarray(shear, dtype=np.float64).ravel()
+        if arr.size != self.model.nx * self.model.ny:
+            raise ValueError("set_shear_modulus: one value per cell expected")
+        self._check(lib().ep_set_shear_modulus(self.h, arr.ctypes.data_as(C.POINTER(C.c_double))),
+                    "ep_set_shear_modulus")
 
     def objective_update(self) -> None:
         """Objective (Jaumann) update of the current stresses with the current
