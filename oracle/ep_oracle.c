@@ -41,6 +41,14 @@
  * L = max extent, V~ dtau = cfl * min spacing.  Then
  *   G~dtau = Re eta cfl h / (L (r + 4/3)),  K~dtau = r G~dtau,
  *   dtau/rho~ = cfl h L / (Re eta).
+ *
+ * Options, each documented where it is computed: the dilatant return
+ * (psi > 0) and the consistency-regularised return (eta_vp > 0) in
+ * consistent_lambda; the incompressible limit (K = +inf) in the pressure
+ * update and p_res_visc; frozen plasticity (freeze_iter) in the sweeps; the
+ * objective stress update (objective) in objective2d/3d; a per-cell shear
+ * modulus (2D) in orc_set_shear_modulus and igd_vertex; loading schedules in
+ * orc_set_strain_rate.
  */
 #include "ep_oracle.h"
 
