@@ -52,6 +52,14 @@ def workload(name):
                       "phi U[20,40], c0 U[1e-3,3e-3], inclusion radius U[0.05,0.15] at seeded positions, "
                       "strain increment 1e-4, tol 1e-6, one persistent launch per sweep under graph replays, "
                       "autotuned tile shapes")
+    if name.startswith("2d-") and name.endswith("-het"):
+        from ep_workloads import Model
+        n = int(name[3:-4])
+        return (Model(ndim=2, nx=n, ny=n, shear=1.2, c0=2e-3, dt=2.5e-4, tol=1e-6, steps=10,
+                      freeze_iter=16 * n, name=name),
+                f"heterogeneous setup: 2d-{n}^2 pure shear, Gaussian G from 1 (centre) to 1.2 and Gaussian "
+                "cohesion from 2e-3 with the jump to 4e-3 next to the walls, K=2, phi=30, strain increment "
+                "2.5e-4, tol 1e-6, frozen plasticity after 16 nx iterations")
     if name.startswith("e2-"):
         from ep_workloads import e2_symmetry
         n = int(name[3:])
@@ -402,7 +410,14 @@ def main():
     prec = E.EP_FP32_FIELDS if args.precision == "fp32" else E.EP_FP64
     sweep = {"auto": E.EP_SWEEP_AUTO, "fused": E.EP_SWEEP_FUSED, "unfused": E.EP_SWEEP_UNFUSED}[args.sweep]
     log("workload", m.name, "cells", m.n_cells, "precision", args.precision, "sweep", args.sweep)
-    s = E.Solver(m, precision=prec, sweep=sweep)
+    extra_reads = 0
+    if args.workload.startswith("2d-") and args.workload.endswith("-het"):
+        from ep_workloads import gaussian_cohesion, gaussian_shear
+        s = E.Solver(m, gaussian_cohesion(m), precision=prec, sweep=sweep)
+        s.set_shear_modulus(gaussian_shear(m))
+        extra_reads = 1                        # the per-cell compliance, read at centres
+    else:
+        s = E.Solver(m, precision=prec, sweep=sweep)
     log("workspace", f"{s.ws_bytes / 2**30:.2f} GiB")
 
     for n in range(args.warmup):
@@ -425,8 +440,8 @@ def main():
 
     it32 = sum(st["iters_fp32"] for st in stats)
     it64 = sum(st["iters"] - st["iters_fp32"] for st in stats)
-    a32 = bytes_per_cell(m.ndim, 4) * m.n_cells
-    a64 = bytes_per_cell(m.ndim, 8) * m.n_cells
+    a32 = (bytes_per_cell(m.ndim, 4) + 4 * extra_reads) * m.n_cells
+    a64 = (bytes_per_cell(m.ndim, 8) + 8 * extra_reads) * m.n_cells
     value = (it32 * a32 + it64 * a64) / wall / 1e9 if wall > 0 else 0.0
 
     # roofline of the dominant sweep
@@ -465,7 +480,7 @@ def main():
     s.close()
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not extra_reads:
         log("cpu baseline (oracle) ...")
         cpu = cpu_baseline(m, args.cpu_budget)
         log("cpu baseline", cpu)

@@ -136,6 +136,20 @@ def gaussian_cohesion(m: Model, rise: float = 0.2, width: float = 0.2, wall: flo
     return np.ascontiguousarray(c.ravel())
 
 
+def gaussian_shear(m: Model, low: float = 1.0, high: float = 1.2, width: float = 0.2,
+                   centre=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """Per-cell shear modulus of the heterogeneous setups (2D, x fastest):
+    `low` at the centre rising as a Gaussian to `high` towards the walls,
+        G = high - (high - low) exp(-r^2 / (width L)^2);
+    the end values are the paper's (1 and 1.2), the width a reading."""
+    L = min(m.lx, m.ly)
+    xc = -0.5 * m.lx + (np.arange(m.nx) + 0.5) * (m.lx / m.nx)
+    yc = -0.5 * m.ly + (np.arange(m.ny) + 0.5) * (m.ly / m.ny)
+    X, Y = np.meshgrid(xc, yc, indexing="xy")
+    r2 = (X - centre[0]) ** 2 + (Y - centre[1]) ** 2
+    return np.ascontiguousarray((high - (high - low) * np.exp(-r2 / (width * L) ** 2)).ravel())
+
+
 def c1_small_2d() -> Model:
     return Model(ndim=2, nx=63, ny=63, tol=1e-8, steps=10, name="2d-63x63-fp64")
 
