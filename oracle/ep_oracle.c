@@ -47,7 +47,7 @@
  * consistent_lambda; the incompressible limit (K = +inf) in the pressure
  * update and p_res_visc; frozen plasticity (freeze_iter) in the sweeps; the
  * objective stress update (objective) in objective2d/3d; a per-cell shear
- * modulus (2D) in orc_set_shear_modulus and igd_vertex; loading schedules in
+ * modulus in orc_set_shear_modulus, igd_vertex and igd_edge; loading schedules in
  * orc_set_strain_rate.
  */
 #include "ep_oracle.h"
@@ -527,6 +527,21 @@ static double sweep2d(orc_state* s, int mode)
 }
 
 /* ------------------------------------------------------------------ 3D */
+/* Compliance 1/(G dt) of an interior 3D edge: the uniform value, or the mean
+ * over the four cells around it when G is given per cell.  axis: the edge's
+ * direction ('z': an xy edge at (i, j) of layer k; 'y': an xz edge; 'x': a yz
+ * edge), the four cells in the order the edge's Lambda takes them. */
+static double igd_edge(const orc_state* s, char axis, int i, int j, int k, double igd)
+{
+    if (!s->igdc) return igd;
+    const long nx = s->nx, nxy = (long)s->nx * s->ny;
+#define CELL(a, b, c) s->igdc[(a) + nx * (b) + nxy * (c)]
+    if (axis == 'z') return 0.25 * (CELL(i - 1, j - 1, k) + CELL(i, j - 1, k) + CELL(i - 1, j, k) + CELL(i, j, k));
+    if (axis == 'y') return 0.25 * (CELL(i - 1, j, k - 1) + CELL(i, j, k - 1) + CELL(i - 1, j, k) + CELL(i, j, k));
+    return 0.25 * (CELL(i, j - 1, k - 1) + CELL(i, j, k - 1) + CELL(i, j - 1, k) + CELL(i, j, k));
+#undef CELL
+}
+
 static double sweep3d(orc_state* s, int mode)
 {
     const int physical = mode == 1;
@@ -539,7 +554,6 @@ static double sweep3d(orc_state* s, int mode)
     const double igd = 1.0 / (s->prm.shear * s->prm.dt);
     const double ikd = 1.0 / (s->prm.bulk * s->prm.dt);
     const double kk = 1.0 / (ikt + ikd);      /* pressure compliance of one update */
-    const double D = igt + igd + s->inv_mus;
     const double A = s->A, B = s->B;
 
     /* 1. divergence and pressure */
@@ -563,7 +577,7 @@ static double sweep3d(orc_state* s, int mode)
                 if (i == 0 || i == nx || j == 0 || j == ny) { s->Txy[e] = 0.0; continue; }
                 double exy = 0.5 * ((s->vx[VX3(i, j, k)] - s->vx[VX3(i, j - 1, k)]) / dy
                                   + (s->vy[VY3(i, j, k)] - s->vy[VY3(i - 1, j, k)]) / dx);
-                s->Txy[e] = s->txy[e] * igt + s->txy_old[e] * igd + 2.0 * exy;
+                s->Txy[e] = s->txy[e] * igt + s->txy_old[e] * igd_edge(s, 'z', i, j, k, igd) + 2.0 * exy;
             }
 #pragma omp parallel for
     for (int k = 0; k <= nz; ++k)
@@ -573,7 +587,7 @@ static double sweep3d(orc_state* s, int mode)
                 if (i == 0 || i == nx || k == 0 || k == nz) { s->Txz[e] = 0.0; continue; }
                 double exz = 0.5 * ((s->vx[VX3(i, j, k)] - s->vx[VX3(i, j, k - 1)]) / dz
                                   + (s->vz[VZ3(i, j, k)] - s->vz[VZ3(i - 1, j, k)]) / dx);
-                s->Txz[e] = s->txz[e] * igt + s->txz_old[e] * igd + 2.0 * exz;
+                s->Txz[e] = s->txz[e] * igt + s->txz_old[e] * igd_edge(s, 'y', i, j, k, igd) + 2.0 * exz;
             }
 #pragma omp parallel for
     for (int k = 0; k <= nz; ++k)
@@ -583,7 +597,7 @@ static double sweep3d(orc_state* s, int mode)
                 if (j == 0 || j == ny || k == 0 || k == nz) { s->Tyz[e] = 0.0; continue; }
                 double eyz = 0.5 * ((s->vy[VY3(i, j, k)] - s->vy[VY3(i, j, k - 1)]) / dz
                                   + (s->vz[VZ3(i, j, k)] - s->vz[VZ3(i, j - 1, k)]) / dy);
-                s->Tyz[e] = s->tyz[e] * igt + s->tyz_old[e] * igd + 2.0 * eyz;
+                s->Tyz[e] = s->tyz[e] * igt + s->tyz_old[e] * igd_edge(s, 'x', i, j, k, igd) + 2.0 * eyz;
             }
     /* 3. normal trials and return mapping at centres */
     long long ny_count = 0;
@@ -597,9 +611,11 @@ static double sweep3d(orc_state* s, int mode)
                 double exx = (s->vx[VX3(i + 1, j, k)] - s->vx[VX3(i, j, k)]) / dx - div / 3.0;
                 double eyy = (s->vy[VY3(i, j + 1, k)] - s->vy[VY3(i, j, k)]) / dy - div / 3.0;
                 double ezz = (s->vz[VZ3(i, j, k + 1)] - s->vz[VZ3(i, j, k)]) / dz - div / 3.0;
-                double Txx = s->txx[c] * igt + s->txx_old[c] * igd + 2.0 * exx;
-                double Tyy = s->tyy[c] * igt + s->tyy_old[c] * igd + 2.0 * eyy;
-                double Tzz = s->tzz[c] * igt + s->tzz_old[c] * igd + 2.0 * ezz;
+                const double igdc = s->igdc ? s->igdc[c] : igd;
+                const double D = igt + igdc + s->inv_mus;
+                double Txx = s->txx[c] * igt + s->txx_old[c] * igdc + 2.0 * exx;
+                double Tyy = s->tyy[c] * igt + s->tyy_old[c] * igdc + 2.0 * eyy;
+                double Tzz = s->tzz[c] * igt + s->tzz_old[c] * igdc + 2.0 * ezz;
                 double Txyb = 0.25 * (s->Txy[XY3(i, j, k)] + s->Txy[XY3(i + 1, j, k)]
                                     + s->Txy[XY3(i, j + 1, k)] + s->Txy[XY3(i + 1, j + 1, k)]);
                 double Txzb = 0.25 * (s->Txz[XZ3(i, j, k)] + s->Txz[XZ3(i + 1, j, k)]
@@ -641,7 +657,7 @@ static double sweep3d(orc_state* s, int mode)
                 if (i == 0 || i == nx || j == 0 || j == ny) { s->txyn[e] = 0.0; continue; }
                 double lv = 0.25 * (s->lam[C3(i - 1, j - 1, k)] + s->lam[C3(i, j - 1, k)]
                                   + s->lam[C3(i - 1, j, k)] + s->lam[C3(i, j, k)]);
-                s->txyn[e] = s->Txy[e] / (D + lv);
+                s->txyn[e] = s->Txy[e] / (igt + igd_edge(s, 'z', i, j, k, igd) + s->inv_mus + lv);
                 dtm = fmax(dtm, fabs(s->txyn[e] - s->txy[e]));
             }
 #pragma omp parallel for reduction(max : dtm)
@@ -652,7 +668,7 @@ static double sweep3d(orc_state* s, int mode)
                 if (i == 0 || i == nx || k == 0 || k == nz) { s->txzn[e] = 0.0; continue; }
                 double lv = 0.25 * (s->lam[C3(i - 1, j, k - 1)] + s->lam[C3(i, j, k - 1)]
                                   + s->lam[C3(i - 1, j, k)] + s->lam[C3(i, j, k)]);
-                s->txzn[e] = s->Txz[e] / (D + lv);
+                s->txzn[e] = s->Txz[e] / (igt + igd_edge(s, 'y', i, j, k, igd) + s->inv_mus + lv);
                 dtm = fmax(dtm, fabs(s->txzn[e] - s->txz[e]));
             }
 #pragma omp parallel for reduction(max : dtm)
@@ -663,7 +679,7 @@ static double sweep3d(orc_state* s, int mode)
                 if (j == 0 || j == ny || k == 0 || k == nz) { s->tyzn[e] = 0.0; continue; }
                 double lv = 0.25 * (s->lam[C3(i, j - 1, k - 1)] + s->lam[C3(i, j, k - 1)]
                                   + s->lam[C3(i, j - 1, k)] + s->lam[C3(i, j, k)]);
-                s->tyzn[e] = s->Tyz[e] / (D + lv);
+                s->tyzn[e] = s->Tyz[e] / (igt + igd_edge(s, 'x', i, j, k, igd) + s->inv_mus + lv);
                 dtm = fmax(dtm, fabs(s->tyzn[e] - s->tyz[e]));
             }
     /* 5. momentum residual and velocity update */
@@ -981,16 +997,15 @@ static void objective3d(orc_state* s)
     free(wxy); free(wxz); free(wyz); free(pn); free(xx); free(yy); free(zz); free(xy); free(xz); free(yz);
 }
 
-/* Per-cell shear modulus (2D; the heterogeneous setups' G field).  The
- * physical compliance 1/(G dt) of a cell replaces the uniform one in its
- * stress update; a vertex takes the mean compliance of its four cells (the
- * harmonic mean of G; a reading).  The pseudo-time steps stay those of
- * prm.shear, which must bound every G.  Returns 0, or -1 (3D, or a G that
+/* Per-cell shear modulus (the heterogeneous setups' G field).  The physical
+ * compliance 1/(G dt) of a cell replaces the uniform one in its stress
+ * update; a vertex (2D) or edge (3D) takes the mean compliance of its four
+ * cells (the harmonic mean of G; a reading).  The pseudo-time steps stay
+ * those of prm.shear, which must bound every G.  Returns 0, or -1 (a G that
  * is not in (0, prm.shear]). */
 int orc_set_shear_modulus(orc_state* s, const double* G)
 {
-    const long nc = (long)s->nx * s->ny;
-    if (s->ndim != 2) return -1;
+    const long nc = n_cells(s);
     for (long c = 0; c < nc; ++c)
         if (!(G[c] > 0.0) || !(G[c] <= s->prm.shear)) return -1;
     if (!s->igdc) s->igdc = (double*)malloc((size_t)nc * sizeof(double));

@@ -82,7 +82,7 @@ void orc_objective_update(orc_state* s);
 /* Background strain rate of the next increments (walls take it at the next
  * orc_load_step). */
 void orc_set_strain_rate(orc_state* s, const double erate[3]);
-int  orc_set_shear_modulus(orc_state* s, const double* G);  /* 2D per-cell G (see the source) */
+int  orc_set_shear_modulus(orc_state* s, const double* G);  /* per-cell G (see the source) */
 void   orc_free(orc_state* s);
 long   orc_field_size(const orc_state* s, int field);
 int    orc_get(const orc_state* s, int field, double* out);

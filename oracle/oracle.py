@@ -156,12 +156,12 @@ class Oracle:
         lib().orc_set_strain_rate(self._h, (C.c_double * 3)(*[float(x) for x in erate]))
 
     def set_shear_modulus(self, G) -> None:
-        """Per-cell shear modulus (2D, x fastest, every value in (0, shear])."""
+        """Per-cell shear modulus (x fastest, every value in (0, shear])."""
         a = np.ascontiguousarray(G, dtype=np.float64).ravel()
-        if a.size != self.model.nx * self.model.ny:
+        if a.size != self.model.n_cells:
             raise ValueError("set_shear_modulus: one value per cell expected")
         if lib().orc_set_shear_modulus(self._h, _dptr(a)) != 0:
-            raise ValueError("set_shear_modulus: 2D only, 0 < G <= shear")
+            raise ValueError("set_shear_modulus: 0 < G <= shear")
 
     def objective_update(self) -> None:
         """Objective (Jaumann) update of the current stresses with the current

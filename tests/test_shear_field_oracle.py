@@ -93,10 +93,54 @@ def test_field_equal_to_the_reference_is_the_uniform_run_and_bad_fields_are_reje
         b.set_shear_modulus(np.full(m.nx * m.ny, 1.01 * m.shear))
     with pytest.raises(ValueError):
         b.set_shear_modulus(np.zeros(m.nx * m.ny))
-    m3 = Model(ndim=3, nx=5, ny=5, nz=5)
-    o3 = Oracle(m3)
-    with pytest.raises(ValueError):
-        o3.set_shear_modulus(np.ones(m3.nx * m3.ny))
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("plane", ["xy", "xz", "yz"])
+def test_3d_field_invariant_along_one_axis_reduces_to_2d(plane):
+    """A 3D model whose G field does not vary along one axis, loaded by pure
+    shear in the other two (no strain rate along the invariant axis), has the
+    plane-strain solution of the 2D model in that plane with the same G
+    field: each edge type's compliance (xy edges for a z-invariant field, xz
+    for y-invariant, yz for x-invariant) must reproduce the 2D vertex
+    compliance, pinned above by the direct solve."""
+    n2 = (13, 11)
+    axes = {"xy": (0, 1, 2), "xz": (0, 2, 1), "yz": (1, 2, 0)}[plane]   # 2D x, 2D y, invariant axis
+    m2 = Model(ndim=2, nx=n2[0], ny=n2[1], lx=1.2, ly=1.0, shear=1.2, c0=10.0, dt=1e-4, tol=1e-12, n_check=10,
+               steps=3)
+    G2 = gaussian_G(m2).reshape(n2[1], n2[0])
+    n3 = [0, 0, 0]
+    ext = [0.0, 0.0, 0.0]
+    n3[axes[0]], n3[axes[1]], n3[axes[2]] = n2[0], n2[1], 4
+    ext[axes[0]], ext[axes[1]], ext[axes[2]] = 1.2, 1.0, 0.7
+    er = [0.0, 0.0, 0.0]
+    er[axes[0]], er[axes[1]] = 1.0, -1.0
+    m3 = Model(ndim=3, nx=n3[0], ny=n3[1], nz=n3[2], lx=ext[0], ly=ext[1], lz=ext[2], shear=1.2, c0=10.0,
+               dt=1e-4, erate=tuple(er), tol=1e-12, n_check=10, steps=3)
+    # G3 indexed (z, y, x); the 2D field (y2, x2) broadcast along the invariant axis
+    z, y, x = np.meshgrid(np.arange(n3[2]), np.arange(n3[1]), np.arange(n3[0]), indexing="ij")
+    pos = (x, y, z)
+    G3 = G2[pos[axes[1]], pos[axes[0]]]
+    o2, o3 = Oracle(m2), Oracle(m3)
+    o2.set_shear_modulus(G2.ravel())
+    o3.set_shear_modulus(G3.ravel())
+    for _ in range(3):
+        assert o2.load_step()["status"] == 0 and o3.load_step()["status"] == 0
+    names3 = {"xy": ("txx", "tyy", "txy"), "xz": ("txx", "tzz", "txz"), "yz": ("tyy", "tzz", "tyz")}[plane]
+    shapes3 = {"txy": (n3[2], n3[1] + 1, n3[0] + 1), "txz": (n3[2] + 1, n3[1], n3[0] + 1),
+               "tyz": (n3[2] + 1, n3[1] + 1, n3[0])}
+    for k2, k3 in zip(("p", "txx", "tyy", "txy"), ("p",) + names3):
+        a2 = o2.get(k2)
+        shape3 = shapes3.get(k3, (n3[2], n3[1], n3[0]))
+        a3 = o3.get(k3).reshape(shape3)
+        # move the 2D axes to (y2, x2) and take an interior slice along the invariant axis
+        order = [2 - axes[1], 2 - axes[0], 2 - axes[2]]
+        a3 = np.transpose(a3, order)
+        sl = a3[..., 1] if a3.shape[2] > 1 else a3[..., 0]
+        sc = np.abs(a2).max()
+        assert sl.shape == (a2.size // sl.shape[1], sl.shape[1])
+        assert np.abs(sl.ravel() - a2).max() <= 1e-8 * sc, (plane, k3)
+    assert np.abs(o2.get("txy")).max() > 1e-3 * np.abs(o2.get("txx")).max()
+    o2.close()
     o3.close()
