@@ -234,16 +234,18 @@ int ep_objective_update(ep_handle* h);
  * non-finite rate). */
 int ep_set_strain_rate(ep_handle* h, const double erate[3]);
 
-/* Shear modulus per cell (2D; the heterogeneous setups of the section on
- * initial conditions and heterogeneities, e.g. a Gaussian G rising from the
- * centre towards the walls).  shear: host array of nx*ny values, x fastest,
- * each in (0, ep_params.shear]; copied, the caller keeps ownership.  A cell's
- * physical compliance 1/(G dt) replaces the uniform one in its stress update;
- * a vertex takes the mean compliance of its four cells; the pseudo-time steps
- * and the residual scales stay those of ep_params.shear (which therefore
- * bounds every G).  Applies from the next sweep on; may be called again.
- * EP_EINVAL for a 3D or batch model, a NULL array or a value out of range
- * (nothing is changed then). */
+/* Shear modulus per cell (the heterogeneous setups of the section on initial
+ * conditions and heterogeneities, e.g. a Gaussian G rising from the centre
+ * towards the walls).  shear: host array of one value per cell (nx*ny, or
+ * nx*ny*nz in 3D), x fastest, each in (0, ep_params.shear]; copied, the
+ * caller keeps ownership.  A cell's physical compliance 1/(G dt) replaces the
+ * uniform one in its stress update; a vertex (2D) or edge (3D) takes the mean
+ * compliance of its four cells; the pseudo-time steps and the residual scales
+ * stay those of ep_params.shear (which therefore bounds every G).  In 3D the
+ * model's sweeps then run the unfused kernels (the fused kernel takes a
+ * uniform G).  Applies from the next sweep on; may be called again.
+ * EP_EINVAL for a batch model, a NULL array or a value out of range (nothing
+ * is changed then). */
 int ep_set_shear_modulus(ep_handle* h, const double* shear);
 
 /* Copy one field between the device state and a host FP64 array of exactly

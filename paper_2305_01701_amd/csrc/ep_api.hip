@@ -93,7 +93,7 @@ size_t carve(const ep_params* p, ep_handle* h, char* base)
     char* q;
     q = take(b64); if (h) h->coh64 = (double*)q;
     q = take(b64); if (h) h->lam64 = (double*)q;
-    q = p->ndim == 2 ? take(b64) : nullptr; if (h) h->igdc64 = (double*)q;
+    q = take(b64); if (h) h->igdc64 = (double*)q;
     for (int d = 0; d < 3; ++d) {
         char* a = d < p->ndim ? take(b64) : nullptr;
         char* u = d < p->ndim ? take(b64) : nullptr;
@@ -119,7 +119,7 @@ size_t carve(const ep_params* p, ep_handle* h, char* base)
         if (h) h->old32[f] = (float*)q;
     }
     q = fp32 ? take(b32) : nullptr; if (h) h->coh32 = (float*)q;
-    q = fp32 && p->ndim == 2 ? take(b32) : nullptr; if (h) h->igdc32 = (float*)q;
+    q = fp32 ? take(b32) : nullptr; if (h) h->igdc32 = (float*)q;
     q = fp32 ? take(b32) : nullptr; if (h) h->lam32 = (float*)q;
     for (int d = 0; d < 3; ++d) {
         q = d < p->ndim ? take(b64) : nullptr;
@@ -294,7 +294,8 @@ void launch_sweep(const ep_handle* h, bool physical, int from, int mode, int lam
     if (h->ndim == 2) {
         launch_sweep_unfused_2d<R>(a, mode, h->st);
     } else {
-        if (fused && a.fs > 0) launch_sweep_fused_3d<R>(a, mode, h->st);
+        // the fused 3D kernel has no per-cell shear modulus: such models run the unfused kernels
+        if (fused && a.fs > 0 && !a.igdc) launch_sweep_fused_3d<R>(a, mode, h->st);
         else launch_sweep_unfused_3d<R>(a, mode, h->st);
     }
 }
@@ -921,8 +922,8 @@ int ep_residual(ep_handle* h, ep_residual_info* r)
 int ep_set_shear_modulus(ep_handle* h, const double* shear)
 {
     if (!h || !shear || h->in_batch) return EP_EINVAL;
-    if (h->ndim != 2) return set_err(h, EP_EINVAL, "a per-cell shear modulus is supported in 2D only");
-    const long nc = (long)h->nx * h->ny;
+    const int nz1 = h->ndim == 3 ? h->nz : 1;
+    const long nc = (long)h->nx * h->ny * nz1;
     std::vector<double> igd(nc);
     for (long c = 0; c < nc; ++c) {
         if (!(shear[c] > 0.0) || !(shear[c] <= h->prm.shear))
@@ -930,7 +931,7 @@ int ep_set_shear_modulus(ep_handle* h, const double* shear)
         igd[c] = 1.0 / (shear[c] * h->prm.dt);
     }
     std::vector<double> pad(h->nelem, 0.0);
-    int ext[3] = {h->nx, h->ny, 1};
+    int ext[3] = {h->nx, h->ny, nz1};
     scatter(h, igd.data(), ext, pad);
     HIPCHK(h, hipMemcpyAsync(h->igdc64, pad.data(), h->nelem * sizeof(double), hipMemcpyHostToDevice, h->st));
     HIPCHK(h, hipStreamSynchronize(h->st));

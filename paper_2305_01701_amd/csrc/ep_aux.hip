@@ -130,8 +130,11 @@ __device__ R shear_T(const SweepArgs<R>& a, int f, int of, long e, long s1, long
                      const R* v1, const R* v2)
 {
     R e2 = (v1[e] - v1[e - s1]) * i1 + (v2[e] - v2[e - s2]) * i2;
-    // a per-cell G exists in 2D only, where the shear points are the vertices
-    const R ig = a.igdc ? vertex_compliance(a.igdc, e, (long)a.sy) : a.igd;
+    // per-cell G: the mean compliance of the four cells around the shear point
+    const R ig = !a.igdc ? a.igd
+               : f == F_TXY ? edge_compliance(a.igdc, e, 1L, (long)a.sy)
+               : f == F_TXZ ? edge_compliance(a.igdc, e, 1L, a.sz)
+                            : edge_compliance(a.igdc, e, (long)a.sy, a.sz);
     return a.it[f][e] * a.igt + a.old[of][e] * ig + e2;
 }
 
@@ -154,7 +157,7 @@ __global__ __launch_bounds__(256) void k_diag(SweepArgs<R> a, double* lamdot, do
         R dvz = d3 ? (a.it[F_VZ][c + sz] - a.it[F_VZ][c]) * a.idz : R(0);
         R div = dvx + dvy + dvz;
         R pn = (a.it[F_P][c] * a.ikt + a.old[O_P][c] * a.ikd - div) / (a.ikt + a.ikd);
-        const R igc = a.igdc ? a.igdc[c] : a.igd;        // per-cell G (2D): compliance and D
+        const R igc = a.igdc ? a.igdc[c] : a.igd;        // per-cell G: compliance and D
         const R Dc = a.igdc ? a.igt + igc + a.imus : a.D;
         R Txx = a.it[F_TXX][c] * a.igt + a.old[O_TXX][c] * igc + R(2) * (dvx - div / R(3));
         R Tyy = a.it[F_TYY][c] * a.igt + a.old[O_TYY][c] * igc + R(2) * (dvy - div / R(3));

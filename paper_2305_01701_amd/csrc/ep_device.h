@@ -104,6 +104,16 @@ __device__ __forceinline__ R vertex_compliance(const R* __restrict__ igdc, long 
     return R(0.25) * (igdc[e - 1 - sy] + igdc[e - sy] + igdc[e - 1] + igdc[e]);
 }
 
+// Compliance of an interior 3D edge (or 2D vertex): the mean over the four
+// cells around it, e - s1 - s2, e - s2, e - s1 and e (xy edges: s1 = 1,
+// s2 = sy; xz: 1, sz; yz: sy, sz).
+template <typename R>
+__device__ __forceinline__ R edge_compliance(const R* __restrict__ igdc, long e, long s1, long s2)
+{
+#pragma clang fp contract(on)
+    return R(0.25) * (igdc[e - s1 - s2] + igdc[e - s2] + igdc[e - s1] + igdc[e]);
+}
+
 // Return mapping at a centre.  J2 is of the trial sums T; returns Lambda
 // (0 when elastic, +inf at the apex) and writes the plastic rate
 // D (tauII_tr - tauII), the returned tauII and the bound Y; p gets the

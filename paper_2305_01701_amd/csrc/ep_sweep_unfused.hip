@@ -150,21 +150,24 @@ __device__ __forceinline__ R T_xy(const SweepArgs<R>& a, long e, int i, int j)
 {
     if (i <= 0 || i >= a.nx || j <= 0 || j >= a.ny) return R(0);
     R e2 = (a.it[F_VX][e] - a.it[F_VX][e - a.sy]) * a.idy + (a.it[F_VY][e] - a.it[F_VY][e - 1]) * a.idx;
-    return a.it[F_TXY][e] * a.igt + a.old[O_TXY][e] * a.igd + e2;
+    const R ig = a.igdc ? edge_compliance(a.igdc, e, 1L, (long)a.sy) : a.igd;
+    return a.it[F_TXY][e] * a.igt + a.old[O_TXY][e] * ig + e2;
 }
 template <typename R>
 __device__ __forceinline__ R T_xz(const SweepArgs<R>& a, long e, int i, int k)
 {
     if (i <= 0 || i >= a.nx || k <= 0 || k >= a.nz) return R(0);
     R e2 = (a.it[F_VX][e] - a.it[F_VX][e - a.sz]) * a.idz + (a.it[F_VZ][e] - a.it[F_VZ][e - 1]) * a.idx;
-    return a.it[F_TXZ][e] * a.igt + a.old[O_TXZ][e] * a.igd + e2;
+    const R ig = a.igdc ? edge_compliance(a.igdc, e, 1L, a.sz) : a.igd;
+    return a.it[F_TXZ][e] * a.igt + a.old[O_TXZ][e] * ig + e2;
 }
 template <typename R>
 __device__ __forceinline__ R T_yz(const SweepArgs<R>& a, long e, int j, int k)
 {
     if (j <= 0 || j >= a.ny || k <= 0 || k >= a.nz) return R(0);
     R e2 = (a.it[F_VY][e] - a.it[F_VY][e - a.sz]) * a.idz + (a.it[F_VZ][e] - a.it[F_VZ][e - a.sy]) * a.idy;
-    return a.it[F_TYZ][e] * a.igt + a.old[O_TYZ][e] * a.igd + e2;
+    const R ig = a.igdc ? edge_compliance(a.igdc, e, (long)a.sy, a.sz) : a.igd;
+    return a.it[F_TYZ][e] * a.igt + a.old[O_TYZ][e] * ig + e2;
 }
 
 template <typename R, int MODE>
@@ -183,8 +186,10 @@ __global__ __launch_bounds__(NT) void k_centre_3d(SweepArgs<R> a)
         R dvz = (a.it[F_VZ][c + sz] - a.it[F_VZ][c]) * a.idz + a.ebz;
         R div = dvx + dvy + dvz;
         R pn = (a.it[F_P][c] * a.ikt + a.old[O_P][c] * a.ikd - div) / (a.ikt + a.ikd);
-        R Txx = a.it[F_TXX][c] * a.igt + a.old[O_TXX][c] * a.igd + R(2) * (dvx - div / R(3));
-        R Tyy = a.it[F_TYY][c] * a.igt + a.old[O_TYY][c] * a.igd + R(2) * (dvy - div / R(3));
+        const R igc = a.igdc ? a.igdc[c] : a.igd;        // per-cell G: the cell's compliance and D
+        const R Dc = a.igdc ? a.igt + igc + a.imus : a.D;
+        R Txx = a.it[F_TXX][c] * a.igt + a.old[O_TXX][c] * igc + R(2) * (dvx - div / R(3));
+        R Tyy = a.it[F_TYY][c] * a.igt + a.old[O_TYY][c] * igc + R(2) * (dvy - div / R(3));
         R Tzz = -(Txx + Tyy);
         R Txy = R(0.25) * (T_xy(a, c, i, j) + T_xy(a, c + 1, i + 1, j) + T_xy(a, c + sy, i, j + 1)
                          + T_xy(a, c + sy + 1, i + 1, j + 1));
@@ -195,14 +200,14 @@ __global__ __launch_bounds__(NT) void k_centre_3d(SweepArgs<R> a)
         R J2 = R(0.5) * (Txx * Txx + Tyy * Tyy + Tzz * Tzz) + Txy * Txy + Txz * Txz + Tyz * Tyz;
         R ld, tii, Y;
         const R ptr = pn;
-        R lam = centre_lambda(J2, a.D, pn, a.coh[c], a.A, a.B, a.Cik, a.vp, ld, tii, Y);
+        R lam = centre_lambda(J2, Dc, pn, a.coh[c], a.A, a.B, a.Cik, a.vp, ld, tii, Y);
         if (a.lam_mode == LAM_FROZEN) {                  // frozen plasticity: Lambda held fixed
             lam = a.lam[c];
-            if (a.Cik != R(0)) pn = ptr + lam * sqrt(J2) / (a.D + lam) * a.Cik;   // its dilatancy
+            if (a.Cik != R(0)) pn = ptr + lam * sqrt(J2) / (Dc + lam) * a.Cik;   // its dilatancy
         } else {
             a.lam[c] = lam;                              // read by the shear-point kernel
         }
-        R txx = Txx / (a.D + lam), tyy = Tyy / (a.D + lam);
+        R txx = Txx / (Dc + lam), tyy = Tyy / (Dc + lam);
         a.nx_[F_P][c] = pn;
         a.nx_[F_TXX][c] = txx;
         a.nx_[F_TYY][c] = tyy;
@@ -236,7 +241,7 @@ __global__ __launch_bounds__(NT) void k_edge_3d(SweepArgs<R> a)
             R t = R(0);
             if (i > 0 && i < a.nx && j > 0 && j < a.ny) {
                 R lv = R(0.25) * (lam[e - sy - 1] + lam[e - sy] + lam[e - 1] + lam[e]);
-                t = T_xy(a, e, i, j) / (a.D + lv);
+                t = T_xy(a, e, i, j) / ((a.igdc ? a.igt + edge_compliance(a.igdc, e, 1L, sy) + a.imus : a.D) + lv);
             }
             a.nx_[F_TXY][e] = t;
             if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)fabs(t - a.it[F_TXY][e]));
@@ -245,7 +250,7 @@ __global__ __launch_bounds__(NT) void k_edge_3d(SweepArgs<R> a)
             R t = R(0);
             if (i > 0 && i < a.nx && k > 0 && k < a.nz) {
                 R lv = R(0.25) * (lam[e - sz - 1] + lam[e - sz] + lam[e - 1] + lam[e]);
-                t = T_xz(a, e, i, k) / (a.D + lv);
+                t = T_xz(a, e, i, k) / ((a.igdc ? a.igt + edge_compliance(a.igdc, e, 1L, sz) + a.imus : a.D) + lv);
             }
             a.nx_[F_TXZ][e] = t;
             if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)fabs(t - a.it[F_TXZ][e]));
@@ -254,7 +259,7 @@ __global__ __launch_bounds__(NT) void k_edge_3d(SweepArgs<R> a)
             R t = R(0);
             if (j > 0 && j < a.ny && k > 0 && k < a.nz) {
                 R lv = R(0.25) * (lam[e - sz - sy] + lam[e - sz] + lam[e - sy] + lam[e]);
-                t = T_yz(a, e, j, k) / (a.D + lv);
+                t = T_yz(a, e, j, k) / ((a.igdc ? a.igt + edge_compliance(a.igdc, e, (long)sy, sz) + a.imus : a.D) + lv);
             }
             a.nx_[F_TYZ][e] = t;
             if (MODE == MODE_CHECK) rmax = nmax(rmax, (double)fabs(t - a.it[F_TYZ][e]));

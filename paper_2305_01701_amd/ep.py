@@ -352,9 +352,9 @@ class ModelView:
         self._check(lib().ep_set_strain_rate(self.h, arr), "ep_set_strain_rate")
 
     def set_shear_modulus(self, shear) -> None:
-        """Per-cell shear modulus (2D, x fastest, each in (0, shear])."""
+        """Per-cell shear modulus (x fastest, each in (0, shear])."""
         arr = np.ascontiguousarray(shear, dtype=np.float64).ravel()
-        if arr.size != self.model.nx * self.model.ny:
+        if arr.size != self.model.n_cells:
             raise ValueError("set_shear_modulus: one value per cell expected")
         self._check(lib().ep_set_shear_modulus(self.h, arr.ctypes.data_as(C.POINTER(C.c_double))),
                     "ep_set_shear_modulus")

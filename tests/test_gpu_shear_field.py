@@ -1,9 +1,10 @@
-"""GPU parity of the per-cell shear modulus (2D; the heterogeneous setups of
-the section on initial conditions and heterogeneities) against the oracle:
-single sweeps from random states with a random G field (tile and unfused
-sweeps) within 1e-11; the heterogeneous setup (Gaussian G from 1 to 1.2 and
-Gaussian cohesion with its wall jump, off-centre) with identical FP64
-iteration counts, FP32 fields, frozen plasticity; rejected inputs."""
+"""GPU parity of the per-cell shear modulus (the heterogeneous setups of the
+section on initial conditions and heterogeneities) against the oracle:
+single sweeps from random states with a random G field (2D tile and unfused
+sweeps, 3D unfused) within 1e-11; the 2D heterogeneous setup (Gaussian G
+from 1 to 1.2 and Gaussian cohesion with its wall jump, off-centre) with
+identical FP64 iteration counts, FP32 fields, frozen plasticity; a 3D
+trajectory with a Gaussian G; rejected inputs."""
 import numpy as np
 import pytest
 
@@ -111,8 +112,54 @@ def test_rejected_fields():
     with pytest.raises(EpError):
         g.set_shear_modulus(np.zeros(m.nx * m.ny))
     g.close()
-    m3 = Model(ndim=3, nx=5, ny=5, nz=5)
-    g3 = Solver(m3)
-    with pytest.raises((EpError, ValueError)):
-        g3.set_shear_modulus(np.ones(m3.nx * m3.ny))
-    g3.close()
+
+
+def gaussian_G3(m, centre=(0.06, -0.04, 0.03)):
+    """3D: G from 1 near the centre to 1.2 towards the walls, off-centre."""
+    ax = [-0.5 * e + (np.arange(n) + 0.5) * (e / n) for e, n in ((m.lx, m.nx), (m.ly, m.ny), (m.lz, m.nz))]
+    Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    r2 = (X - centre[0]) ** 2 + (Y - centre[1]) ** 2 + (Z - centre[2]) ** 2
+    return (1.2 - 0.2 * np.exp(-r2 / 0.25 ** 2)).ravel()
+
+
+@pytest.mark.parametrize("sweep", [0, 2], ids=["auto", "unfused"])
+def test_3d_single_sweeps_with_a_random_field(sweep):
+    """3D: a G field routes the sweeps to the unfused kernels (also under
+    EP_SWEEP_AUTO, whose default in 3D is the fused kernel)."""
+    m = Model(ndim=3, nx=13, ny=11, nz=9, shear=1.5, c0=1e-4)
+    r = np.random.Generator(np.random.PCG64(47))
+    G = r.uniform(0.5, 1.5, m.n_cells)
+    say("3d per-cell G single sweeps, sweep", sweep)
+    st = random_state(m, seed=53, amp_s=2e-3)
+    st["tzz"] = -(st["txx"] + st["tyy"])
+    g, o = pair(m, G, sweep=sweep)
+    set_state(g, m, st, settable_tzz=False)
+    set_state(o, m, st, settable_tzz=True)
+    for n in (1, 4):
+        g.sweep(n)
+        for _ in range(n):
+            o.sweep()
+        names = it_names(m)
+        compare(m, g.fields(names), o.fields(names), names, 1e-11, f"{n} sweeps")
+    g.close()
+    o.close()
+
+
+@pytest.mark.parametrize("prec,eta_vp", [(FP64, 0.0), (FP32, 5e-5)], ids=["fp64", "fp32-regularised"])
+def test_3d_trajectory_with_a_gaussian_field(prec, eta_vp):
+    m = Model(ndim=3, nx=17, ny=15, nz=13, shear=1.2, dt=2e-4, tol=1e-8, n_check=10, incl_radius=0.25,
+              incl_centre=(0.04, -0.03, 0.02), steps=5, eta_vp=eta_vp)
+    say("3d per-cell G trajectory, prec", prec)
+    g, o = pair(m, gaussian_G3(m), prec)
+    out = [(g.load_step(), o.load_step()) for _ in range(m.steps)]
+    assert out[-1][1]["n_yield"] > 0
+    for n, (sg, so) in enumerate(out):
+        assert sg["status"] == 0 and so["status"] == 0, n
+        if prec == FP64:
+            assert sg["iters"] == so["iters"] and sg["n_yield"] == so["n_yield"], (n, sg["iters"], so["iters"])
+    tol = 1e-6 if prec == FP64 else 1e-4
+    names = it_names(m)
+    compare(m, g.fields(names), o.fields(names), names, tol)
+    compare_accumulators(m, g.fields(accum_names(m)), o.fields(accum_names(m)), tol)
+    g.close()
+    o.close()
