@@ -60,6 +60,11 @@ def workload(name):
                 f"heterogeneous setup: 2d-{n}^2 pure shear, Gaussian G from 1 (centre) to 1.2 and Gaussian "
                 "cohesion from 2e-3 with the jump to 4e-3 next to the walls, K=2, phi=30, strain increment "
                 "2.5e-4, tol 1e-6, frozen plasticity after 16 nx iterations")
+    if name.startswith("3d-") and name.endswith("-het"):
+        n = int(name[3:-4])
+        return (c3_3d(n).with_(shear=1.2, name=name),
+                f"3d-{n}^3 as the default workload with a Gaussian G from 1 (centre) to 1.2 (per-cell shear "
+                "modulus: unfused sweeps)")
     if name.startswith("e2-"):
         from ep_workloads import e2_symmetry
         n = int(name[3:])
@@ -416,6 +421,11 @@ def main():
         s = E.Solver(m, gaussian_cohesion(m), precision=prec, sweep=sweep)
         s.set_shear_modulus(gaussian_shear(m))
         extra_reads = 1                        # the per-cell compliance, read at centres
+    elif args.workload.startswith("3d-") and args.workload.endswith("-het"):
+        from ep_workloads import gaussian_shear
+        s = E.Solver(m, precision=prec, sweep=sweep)
+        s.set_shear_modulus(gaussian_shear(m))
+        extra_reads = 1
     else:
         s = E.Solver(m, precision=prec, sweep=sweep)
     log("workspace", f"{s.ws_bytes / 2**30:.2f} GiB")

@@ -138,15 +138,15 @@ def gaussian_cohesion(m: Model, rise: float = 0.2, width: float = 0.2, wall: flo
 
 def gaussian_shear(m: Model, low: float = 1.0, high: float = 1.2, width: float = 0.2,
                    centre=(0.0, 0.0, 0.0)) -> np.ndarray:
-    """Per-cell shear modulus of the heterogeneous setups (2D, x fastest):
-    `low` at the centre rising as a Gaussian to `high` towards the walls,
+    """Per-cell shear modulus of the heterogeneous setups (x fastest): `low`
+    at the centre rising as a Gaussian to `high` towards the walls,
         G = high - (high - low) exp(-r^2 / (width L)^2);
     the end values are the paper's (1 and 1.2), the width a reading."""
-    L = min(m.lx, m.ly)
-    xc = -0.5 * m.lx + (np.arange(m.nx) + 0.5) * (m.lx / m.nx)
-    yc = -0.5 * m.ly + (np.arange(m.ny) + 0.5) * (m.ly / m.ny)
-    X, Y = np.meshgrid(xc, yc, indexing="xy")
-    r2 = (X - centre[0]) ** 2 + (Y - centre[1]) ** 2
+    ext = [(m.lx, m.nx), (m.ly, m.ny)] + ([(m.lz, m.nz)] if m.ndim == 3 else [])
+    L = min(e for e, _ in ext)
+    ax = [-0.5 * e + (np.arange(n) + 0.5) * (e / n) for e, n in ext]
+    grids = np.meshgrid(*ax[::-1], indexing="ij")[::-1]          # x, y(, z), each (.., ny, nx)
+    r2 = sum((g - c) ** 2 for g, c in zip(grids, centre))
     return np.ascontiguousarray((high - (high - low) * np.exp(-r2 / (width * L) ** 2)).ravel())
 
 
