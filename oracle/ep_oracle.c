@@ -17,12 +17,17 @@
  * backward Euler in pseudo-time for p and tau, explicit for v.  With
  * Q = sqrt(J2) (psi = 0) the plastic term is Lambda * tau with
  * Lambda = lambda_dot / tauII, so the stress update is tau = T / (D + Lambda)
- * with T = tau_old/(G~dtau) + tau^/(G dt) + 2 e', D = 1/(G~dtau) + 1/(G dt)
- * + 1/mu_s; Lambda is chosen at cell centres so that the returned tauII equals
- * the Drucker-Prager bound A p + B c (radial return: the trial deviator is
- * scaled down onto the yield surface), and averaged from the four adjacent
- * centres to vertices / edges.  The centre J2 uses the four-point average of
- * the vertex (edge) shear trial.
+ * with T = tau_old/(G~dtau) + S, S = tau^/(G dt) + 2 e' the physical trial,
+ * D = 1/(G~dtau) + Dp, Dp = 1/(G dt) + 1/mu_s.  Lambda is set at cell
+ * centres by the radial return of the physical trial S (its shear
+ * components averaged from the four shear points) against the
+ * Drucker-Prager bound A p + B c, so that the fixed point tau = S/(Dp + Lambda)
+ * is the solution of the increment's equations with the pseudo-time terms
+ * removed (the paper: the quasi-static solution is the attractor of the
+ * pseudo-time iteration; Re and r only set its convergence).  The iteration
+ * blends that Lambda with the return of the pseudo-time trial (centre_return),
+ * which changes the path, not the fixed point.  Vertices / edges take the
+ * mean Lambda of their four centres.
  *
  * Residual (Convergence study section): the L-inf momentum residual
  * max|div(tau) - grad p| over interior faces, combined (max) with the
@@ -30,11 +35,14 @@
  * from their local fixed point per unit length,
  *   |p^{k+1}-p^k| K dt / (K~dtau L)  and  |tau^{k+1}-tau^k| eta / (G~dtau L),
  * so that a homogeneous state whose stresses are still relaxing in pseudo-time
- * is not taken as converged.  An increment stops when this is at most
- * tol * max(R_ref, 2 G max|erate| dt / L), R_ref being the momentum residual
- * of the physical stresses of the plain guess (pseudo-time terms removed).
- * Those physical stresses are also the pseudo-time starting point of p and
- * tau; velocities start from the previous increment's.
+ * is not taken as converged.  When this is at most
+ * tol * max(R_ref, 2 G max|erate| dt / L) at a check, the physical stresses of
+ * the current velocities (pseudo-time terms removed) are evaluated; their
+ * momentum residual must meet the same bound (the certificate), and they are
+ * the accepted stresses.  R_ref is the momentum residual of the physical
+ * stresses of the plain guess (the previous increment's velocities); those
+ * stresses are also the pseudo-time starting point of p and tau, and a
+ * starting state that already meets the bound is accepted as it is.
  *
  * PT parameters (equations for rho~, G~, K~, Vp and the optimal Re, r): the
  * viscosity in rho~ is the visco-elastic eta = 1/(1/(G dt) + 1/mu_s),
@@ -44,7 +52,7 @@
  *
  * Options, each documented where it is computed: the dilatant return
  * (psi > 0) and the consistency-regularised return (eta_vp > 0) in
- * consistent_lambda; the incompressible limit (K = +inf) in the pressure
+ * plastic_lambda; the incompressible limit (K = +inf) in the pressure
  * update and p_res_visc; frozen plasticity (freeze_iter) in the sweeps; the
  * objective stress update (objective) in objective2d/3d; a per-cell shear
  * modulus in orc_set_shear_modulus, igd_vertex and igd_edge; loading schedules in
@@ -83,6 +91,7 @@ struct orc_state {
     double *vxn, *vyn, *vzn;
     double *pn, *txxn, *tyyn, *tzzn, *txyn, *txzn, *tyzn;
     double *Txy, *Txz, *Tyz, *dv;
+    double *Sxy, *Sxz, *Syz;  /* physical shear trials (pseudo-time terms removed) */
     double *vx0, *vy0, *vz0;  /* velocities at the start of the increment */
     /* bookkeeping of the last sweep */
     double vmax;
@@ -209,11 +218,11 @@ orc_state* orc_create(const orc_params* prm, const double* cohesion)
     s->lam = zalloc(nc); s->tII = zalloc(nc); s->yld = zalloc(nc); s->lamdot = zalloc(nc);
     s->lamf = zalloc(nc);
     s->txy = zalloc(n_xy(s)); s->txy_old = zalloc(n_xy(s)); s->txyn = zalloc(n_xy(s));
-    s->Txy = zalloc(n_xy(s)); s->exy = zalloc(n_xy(s));
+    s->Txy = zalloc(n_xy(s)); s->exy = zalloc(n_xy(s)); s->Sxy = zalloc(n_xy(s));
     s->txz = zalloc(n_xz(s)); s->txz_old = zalloc(n_xz(s)); s->txzn = zalloc(n_xz(s));
-    s->Txz = zalloc(n_xz(s)); s->exz = zalloc(n_xz(s));
+    s->Txz = zalloc(n_xz(s)); s->exz = zalloc(n_xz(s)); s->Sxz = zalloc(n_xz(s));
     s->tyz = zalloc(n_yz(s)); s->tyz_old = zalloc(n_yz(s)); s->tyzn = zalloc(n_yz(s));
-    s->Tyz = zalloc(n_yz(s)); s->eyz = zalloc(n_yz(s));
+    s->Tyz = zalloc(n_yz(s)); s->eyz = zalloc(n_yz(s)); s->Syz = zalloc(n_yz(s));
 
     if (cohesion) memcpy(s->coh, cohesion, (size_t)nc * sizeof(double));
 
@@ -250,6 +259,7 @@ void orc_free(orc_state* s)
         &s->txy, &s->txy_old, &s->txyn, &s->Txy, &s->exy,
         &s->txz, &s->txz_old, &s->txzn, &s->Txz, &s->exz,
         &s->tyz, &s->tyz_old, &s->tyzn, &s->Tyz, &s->eyz,
+        &s->Sxy, &s->Sxz, &s->Syz,
     };
     for (size_t q = 0; q < sizeof(all) / sizeof(all[0]); ++q) free(*all[q]);
     free(s);
@@ -324,61 +334,35 @@ void orc_scalars(const orc_state* s, double out[8])
 void orc_history(orc_state* s, double* buf, int cap) { s->hist = buf; s->hist_cap = cap; s->hist_len = 0; }
 int orc_history_len(const orc_state* s) { return s->hist_len; }
 
-/* Centre return mapping shared by 2D and 3D: given the trial sums, the
- * pressure and the cohesion, return Lambda (0 when elastic) and the centre
- * quantities used for diagnostics. */
-static double centre_lambda(double J2, double D, double p, double c, double A, double B,
-                            double* tII_ret, double* Y_out, double* lamdot)
-{
-    double tII_tr = sqrt(J2) / D;            /* trial tauII if Lambda = 0 */
-    double Y = A * p + B * c;
-    if (Y < 0.0) Y = 0.0;                    /* apex: nothing can be carried */
-    double lam = 0.0;
-    *lamdot = 0.0;
-    if (tII_tr > Y) {
-        lam = D * (tII_tr / Y - 1.0);        /* +inf when Y == 0 */
-        *lamdot = D * (tII_tr - Y);
-        *tII_ret = Y;
-    } else {
-        *tII_ret = tII_tr;
-    }
-    *Y_out = Y;
-    return lam;
-}
-
-/* ------------------------------------------------------------------ 2D */
-/* Pressure term of the residual: |p^{k+1} - p^k| times K dt / (K~dtau L),
- * the distance of p from its local fixed point per unit length.  In the
- * incompressible limit (K = +inf, equation A2ssP2: 1/(K dt) = 0) the
- * pressure rate is the divergence, and the factor takes the visco-elastic
- * viscosity in place of K dt, as the deviator term does (a reading). */
-/* Dilatant and/or regularised return.
+/* Plastic rate of a yielding centre (called only when the trial stress lies
+ * outside the bound).
  * Dilatancy (psi > 0; Plasticity section, potential Q = sqrt(J2) - C p): the
  * plastic strain rate lambda_dot dQ/dsigma has the volumetric part
  * lambda_dot C, which enters the pressure equation like a source:
- *     p = p_tr + lambda_dot C k,   k = 1 / (1/(K~dtau) + 1/(K dt)),
- * with p_tr the pressure update without it.
+ *     p = p_tr + lambda_dot C k,
+ * with p_tr the pressure update without it and k its compliance
+ * (1 / (1/(K~dtau) + 1/(K dt)); K dt when the pseudo-time terms are removed).
  * Regularisation (eta_vp > 0; the visco-plastic strain rate of the
  * constitutive section, with the consistency viscosity of the literature the
  * introduction cites): the consistency condition becomes
- * tauII = A p + B c + eta_vp lambda_dot, i.e. the stress may exceed the bound
- * by a viscous overstress.
- * With the deviatoric update tauII D + lambda_dot = sqrt(J2(T)) and the bound
- * max(0, A p + B c) (nothing is carried beyond the apex), lambda_dot solves
+ * tauII = max(0, A p + B c) + eta_vp lambda_dot, a viscous overstress.
+ * With a deviator of compliance D, tauII D + lambda_dot = sqrt(J2) of the
+ * trial, so lambda_dot solves
  *     D (max(0, A p + B c) + eta_vp lambda_dot) + lambda_dot = sqrt(J2),
  * p = p_tr + lambda_dot C k, whose left side increases with lambda_dot and is
  * linear on either side of the apex.  The root of the piece with a
  * non-negative bound,
  *     lambda_dot = (sqrt(J2) - D (A p_tr + B c)) / (1 + D A C k + D eta_vp),
  * is the solution when its bound is non-negative; otherwise the solution lies
- * on the apex piece, lambda_dot = sqrt(J2) / (1 + D eta_vp).
+ * on the apex piece, lambda_dot = sqrt(J2) / (1 + D eta_vp).  With C = 0 and
+ * eta_vp = 0 this is the radial return lambda_dot = sqrt(J2) - D Y.
  * Returns Lambda = lambda_dot / tauII (+inf when tauII = 0); *p gets the
- * corrected pressure.  Called for yielding centres only. */
-static double consistent_lambda(double J2, double D, double p_tr, double c, double A, double B, double C,
-                                double k, double eta_vp, double* p, double* tII_ret, double* Y_out, double* lamdot)
+ * corrected pressure, *tII the returned tauII, *Y the bound. */
+static double plastic_lambda(double sq, double D, double p_tr, double c, double A, double B, double C,
+                             double k, double eta_vp, double* p, double* tII_ret, double* Y_out, double* lamdot)
 {
-    double ld = (sqrt(J2) - D * (A * p_tr + B * c)) / (1.0 + D * A * C * k + D * eta_vp);
-    if (A * (p_tr + ld * C * k) + B * c < 0.0) ld = sqrt(J2) / (1.0 + D * eta_vp);
+    double ld = (sq - D * (A * p_tr + B * c)) / (1.0 + D * A * C * k + D * eta_vp);
+    if (A * (p_tr + ld * C * k) + B * c < 0.0) ld = sq / (1.0 + D * eta_vp);
     *p = p_tr + ld * C * k;
     double Y = A * (*p) + B * c;
     if (Y < 0.0) Y = 0.0;
@@ -387,6 +371,63 @@ static double consistent_lambda(double J2, double D, double p_tr, double c, doub
     *tII_ret = tII;
     *Y_out = Y;
     return tII > 0.0 ? ld / tII : INFINITY;
+}
+
+/* Return mapping at a centre (Return mapping section; readings on the
+ * staggered grid, the Lambda form): the deviatoric update of the iteration is
+ * tau = T / (D + Lambda), T = tau_k/(G~dtau) + S, S = tau^/(G dt) + 2 e',
+ * D = 1/(G~dtau) + Dp, Dp = 1/(G dt) + 1/mu_s, and a shear point takes the
+ * mean Lambda of its four centres.
+ *
+ * The plastic multiplier is set by the physical trial S, in which the
+ * pseudo-time terms are absent: with the shear components of S averaged from
+ * the four (2D) or four-per-plane (3D) shear points, Lambda_phys is the
+ * radial return of S against the bound, sqrt(J2(S)) = (Dp + Lambda) tauII,
+ * tauII = max(0, A p + B c) (+ eta_vp lambda_dot).  At the fixed point of
+ * the iteration tau = S / (Dp + Lambda), so the converged state is the
+ * solution of the increment's equations with the pseudo-time terms removed,
+ * whatever the pseudo-time steps are (the paper's Re and r only set the
+ * convergence).
+ *
+ * The iteration uses Lambda = Lambda_phys + blend (Lambda_pt - Lambda_phys),
+ * Lambda_pt being the radial return of the pseudo-time trial: the centre's
+ * normal T with the averaged shear trial scaled to the pseudo-time form it
+ * has at the fixed point, f S_shear, f = (D + Lambda_phys)/(Dp + Lambda_phys),
+ * against D.  At the fixed point Lambda_pt = Lambda_phys, so the blend only
+ * changes the path (blend = 0: the physical return alone); the pressure takes
+ * the same blend of the two dilatant corrections.
+ *
+ * nT2 = (1/2) sum of the squared normal components of T, nS2 the same of S,
+ * sh2 = sum of the squared averaged shear components of S.  Returns Lambda
+ * (0 elastic, +inf at the apex); *p the pressure; the diagnostics (*tII, *Y,
+ * *lamdot) are those of the physical return. */
+static double centre_return(const orc_state* s, double nT2, double nS2, double sh2, double Dp, double D,
+                            double k, double p_tr, double c, double* p, double* tII, double* Y, double* lamdot)
+{
+    const double A = s->A, B = s->B, C = s->C, vp = s->prm.eta_vp;
+    double Y0 = A * p_tr + B * c;
+    if (Y0 < 0.0) Y0 = 0.0;                  /* apex: nothing can be carried */
+    const double sqS = sqrt(nS2 + sh2);
+    *p = p_tr;
+    *Y = Y0;
+    *lamdot = 0.0;
+    if (!(sqS / Dp > Y0)) {                  /* elastic: yield only above the bound */
+        *tII = sqS / Dp;
+        return 0.0;
+    }
+    double lam = plastic_lambda(sqS, Dp, p_tr, c, A, B, C, k, vp, p, tII, Y, lamdot);
+    if (s->prm.pt_blend == 0.0 || D == Dp || isinf(lam)) return lam;
+    /* pseudo-time trial */
+    const double f = (D + lam) / (Dp + lam);
+    const double sqT = sqrt(nT2 + f * f * sh2);
+    double lam_t = 0.0, p_t = p_tr;
+    if (sqT / D > Y0) {
+        double t1, t2, t3;
+        lam_t = plastic_lambda(sqT, D, p_tr, c, A, B, C, k, vp, &p_t, &t1, &t2, &t3);
+    }
+    if (isinf(lam_t)) return lam;
+    *p = *p + s->prm.pt_blend * (p_t - *p);
+    return lam + s->prm.pt_blend * (lam_t - lam);
 }
 
 static double p_res_visc(const orc_state* s) { return isinf(s->prm.bulk) ? s->eta : s->prm.bulk * s->prm.dt; }
@@ -413,7 +454,6 @@ static double sweep2d(orc_state* s, int mode)
     const double igd = 1.0 / (s->prm.shear * s->prm.dt);
     const double ikd = 1.0 / (s->prm.bulk * s->prm.dt);
     const double kk = 1.0 / (ikt + ikd);      /* pressure compliance of one update */
-    const double A = s->A, B = s->B;
 
     /* 1. divergence and pressure at centres */
 #pragma omp parallel for
@@ -431,7 +471,8 @@ static double sweep2d(orc_state* s, int mode)
             if (i == 0 || i == nx || j == 0 || j == ny) { s->Txy[XY2(i, j)] = 0.0; continue; }
             double exy = 0.5 * ((s->vx[VX2(i, j)] - s->vx[VX2(i, j - 1)]) / dy
                               + (s->vy[VY2(i, j)] - s->vy[VY2(i - 1, j)]) / dx);
-            s->Txy[XY2(i, j)] = s->txy[XY2(i, j)] * igt + s->txy_old[XY2(i, j)] * igd_vertex(s, i, j, igd) + 2.0 * exy;
+            s->Sxy[XY2(i, j)] = s->txy_old[XY2(i, j)] * igd_vertex(s, i, j, igd) + 2.0 * exy;
+            s->Txy[XY2(i, j)] = s->txy[XY2(i, j)] * igt + s->Sxy[XY2(i, j)];
         }
     /* 3. normal trial and return mapping at centres */
     long long ny_count = 0;
@@ -444,27 +485,28 @@ static double sweep2d(orc_state* s, int mode)
             double exx = (s->vx[VX2(i + 1, j)] - s->vx[VX2(i, j)]) / dx - div / 3.0;
             double eyy = (s->vy[VY2(i, j + 1)] - s->vy[VY2(i, j)]) / dy - div / 3.0;
             const double igdc = s->igdc ? s->igdc[c] : igd;
-            const double D = igt + igdc + s->inv_mus;
-            double Txx = s->txx[c] * igt + s->txx_old[c] * igdc + 2.0 * exx;
-            double Tyy = s->tyy[c] * igt + s->tyy_old[c] * igdc + 2.0 * eyy;
-            double Tb = 0.25 * (s->Txy[XY2(i, j)] + s->Txy[XY2(i + 1, j)]
-                              + s->Txy[XY2(i, j + 1)] + s->Txy[XY2(i + 1, j + 1)]);
-            double J2 = 0.5 * (Txx * Txx + Tyy * Tyy) + Tb * Tb;
+            const double Dp = igdc + s->inv_mus;     /* physical compliance 1/eta */
+            const double D = igt + Dp;
+            double Sxx = s->txx_old[c] * igdc + 2.0 * exx;
+            double Syy = s->tyy_old[c] * igdc + 2.0 * eyy;
+            double Txx = s->txx[c] * igt + Sxx;
+            double Tyy = s->tyy[c] * igt + Syy;
+            double Sb = 0.25 * (s->Sxy[XY2(i, j)] + s->Sxy[XY2(i + 1, j)]
+                              + s->Sxy[XY2(i, j + 1)] + s->Sxy[XY2(i + 1, j + 1)]);
+            double J2 = 0.5 * (Sxx * Sxx + Syy * Syy) + Sb * Sb;   /* J2 of the physical trial */
             double tret, Y, ld;
             const double ptr = s->pn[c];
-            double lam = centre_lambda(J2, D, ptr, s->coh[c], A, B, &tret, &Y, &ld);
-            if (lam > 0.0 && (s->C > 0.0 || s->prm.eta_vp > 0.0))
-                lam = consistent_lambda(J2, D, ptr, s->coh[c], A, B, s->C, kk, s->prm.eta_vp, &s->pn[c], &tret, &Y,
-                                        &ld);
+            double lam = centre_return(s, 0.5 * (Txx * Txx + Tyy * Tyy), 0.5 * (Sxx * Sxx + Syy * Syy), Sb * Sb,
+                                       Dp, D, kk, ptr, s->coh[c], &s->pn[c], &tret, &Y, &ld);
             s->lamdot[c] = ld;
             s->tII[c] = tret;
             s->yld[c] = Y;
             if (lam > 0.0) ny_count++;
             if (mode == 0 && s->freeze == 1) s->lamf[c] = lam;
-            if (mode == 0 && s->freeze == 2) {
+            if (s->freeze == 2) {   /* held Lambda, also in the certificate */
                 lam = s->lamf[c];
                 /* held Lambda: lambda_dot = Lambda tauII = Lambda sqrt(J2) / (D + Lambda) */
-                if (s->C > 0.0) s->pn[c] = ptr + lam * sqrt(J2) / (D + lam) * s->C * kk;
+                if (s->C > 0.0) s->pn[c] = ptr + lam * sqrt(J2) / (Dp + lam) * s->C * kk;
             }
             s->lam[c] = lam;
             s->txxn[c] = Txx / (D + lam);
@@ -554,7 +596,6 @@ static double sweep3d(orc_state* s, int mode)
     const double igd = 1.0 / (s->prm.shear * s->prm.dt);
     const double ikd = 1.0 / (s->prm.bulk * s->prm.dt);
     const double kk = 1.0 / (ikt + ikd);      /* pressure compliance of one update */
-    const double A = s->A, B = s->B;
 
     /* 1. divergence and pressure */
 #pragma omp parallel for
@@ -577,7 +618,8 @@ static double sweep3d(orc_state* s, int mode)
                 if (i == 0 || i == nx || j == 0 || j == ny) { s->Txy[e] = 0.0; continue; }
                 double exy = 0.5 * ((s->vx[VX3(i, j, k)] - s->vx[VX3(i, j - 1, k)]) / dy
                                   + (s->vy[VY3(i, j, k)] - s->vy[VY3(i - 1, j, k)]) / dx);
-                s->Txy[e] = s->txy[e] * igt + s->txy_old[e] * igd_edge(s, 'z', i, j, k, igd) + 2.0 * exy;
+                s->Sxy[e] = s->txy_old[e] * igd_edge(s, 'z', i, j, k, igd) + 2.0 * exy;
+                s->Txy[e] = s->txy[e] * igt + s->Sxy[e];
             }
 #pragma omp parallel for
     for (int k = 0; k <= nz; ++k)
@@ -587,7 +629,8 @@ static double sweep3d(orc_state* s, int mode)
                 if (i == 0 || i == nx || k == 0 || k == nz) { s->Txz[e] = 0.0; continue; }
                 double exz = 0.5 * ((s->vx[VX3(i, j, k)] - s->vx[VX3(i, j, k - 1)]) / dz
                                   + (s->vz[VZ3(i, j, k)] - s->vz[VZ3(i - 1, j, k)]) / dx);
-                s->Txz[e] = s->txz[e] * igt + s->txz_old[e] * igd_edge(s, 'y', i, j, k, igd) + 2.0 * exz;
+                s->Sxz[e] = s->txz_old[e] * igd_edge(s, 'y', i, j, k, igd) + 2.0 * exz;
+                s->Txz[e] = s->txz[e] * igt + s->Sxz[e];
             }
 #pragma omp parallel for
     for (int k = 0; k <= nz; ++k)
@@ -597,7 +640,8 @@ static double sweep3d(orc_state* s, int mode)
                 if (j == 0 || j == ny || k == 0 || k == nz) { s->Tyz[e] = 0.0; continue; }
                 double eyz = 0.5 * ((s->vy[VY3(i, j, k)] - s->vy[VY3(i, j, k - 1)]) / dz
                                   + (s->vz[VZ3(i, j, k)] - s->vz[VZ3(i, j - 1, k)]) / dy);
-                s->Tyz[e] = s->tyz[e] * igt + s->tyz_old[e] * igd_edge(s, 'x', i, j, k, igd) + 2.0 * eyz;
+                s->Syz[e] = s->tyz_old[e] * igd_edge(s, 'x', i, j, k, igd) + 2.0 * eyz;
+                s->Tyz[e] = s->tyz[e] * igt + s->Syz[e];
             }
     /* 3. normal trials and return mapping at centres */
     long long ny_count = 0;
@@ -612,32 +656,36 @@ static double sweep3d(orc_state* s, int mode)
                 double eyy = (s->vy[VY3(i, j + 1, k)] - s->vy[VY3(i, j, k)]) / dy - div / 3.0;
                 double ezz = (s->vz[VZ3(i, j, k + 1)] - s->vz[VZ3(i, j, k)]) / dz - div / 3.0;
                 const double igdc = s->igdc ? s->igdc[c] : igd;
-                const double D = igt + igdc + s->inv_mus;
-                double Txx = s->txx[c] * igt + s->txx_old[c] * igdc + 2.0 * exx;
-                double Tyy = s->tyy[c] * igt + s->tyy_old[c] * igdc + 2.0 * eyy;
-                double Tzz = s->tzz[c] * igt + s->tzz_old[c] * igdc + 2.0 * ezz;
-                double Txyb = 0.25 * (s->Txy[XY3(i, j, k)] + s->Txy[XY3(i + 1, j, k)]
-                                    + s->Txy[XY3(i, j + 1, k)] + s->Txy[XY3(i + 1, j + 1, k)]);
-                double Txzb = 0.25 * (s->Txz[XZ3(i, j, k)] + s->Txz[XZ3(i + 1, j, k)]
-                                    + s->Txz[XZ3(i, j, k + 1)] + s->Txz[XZ3(i + 1, j, k + 1)]);
-                double Tyzb = 0.25 * (s->Tyz[YZ3(i, j, k)] + s->Tyz[YZ3(i, j + 1, k)]
-                                    + s->Tyz[YZ3(i, j, k + 1)] + s->Tyz[YZ3(i, j + 1, k + 1)]);
-                double J2 = 0.5 * (Txx * Txx + Tyy * Tyy + Tzz * Tzz)
-                          + Txyb * Txyb + Txzb * Txzb + Tyzb * Tyzb;
+                const double Dp = igdc + s->inv_mus;     /* physical compliance 1/eta */
+                const double D = igt + Dp;
+                double Sxx = s->txx_old[c] * igdc + 2.0 * exx;
+                double Syy = s->tyy_old[c] * igdc + 2.0 * eyy;
+                double Szz = s->tzz_old[c] * igdc + 2.0 * ezz;
+                double Txx = s->txx[c] * igt + Sxx;
+                double Tyy = s->tyy[c] * igt + Syy;
+                double Tzz = s->tzz[c] * igt + Szz;
+                double Sxyb = 0.25 * (s->Sxy[XY3(i, j, k)] + s->Sxy[XY3(i + 1, j, k)]
+                                    + s->Sxy[XY3(i, j + 1, k)] + s->Sxy[XY3(i + 1, j + 1, k)]);
+                double Sxzb = 0.25 * (s->Sxz[XZ3(i, j, k)] + s->Sxz[XZ3(i + 1, j, k)]
+                                    + s->Sxz[XZ3(i, j, k + 1)] + s->Sxz[XZ3(i + 1, j, k + 1)]);
+                double Syzb = 0.25 * (s->Syz[YZ3(i, j, k)] + s->Syz[YZ3(i, j + 1, k)]
+                                    + s->Syz[YZ3(i, j, k + 1)] + s->Syz[YZ3(i, j + 1, k + 1)]);
+                double J2 = 0.5 * (Sxx * Sxx + Syy * Syy + Szz * Szz)
+                          + Sxyb * Sxyb + Sxzb * Sxzb + Syzb * Syzb;   /* J2 of the physical trial */
                 double tret, Y, ld;
                 const double ptr = s->pn[c];
-                double lam = centre_lambda(J2, D, ptr, s->coh[c], A, B, &tret, &Y, &ld);
-                if (lam > 0.0 && (s->C > 0.0 || s->prm.eta_vp > 0.0))
-                    lam = consistent_lambda(J2, D, ptr, s->coh[c], A, B, s->C, kk, s->prm.eta_vp, &s->pn[c], &tret,
-                                            &Y, &ld);
+                double lam = centre_return(s, 0.5 * (Txx * Txx + Tyy * Tyy + Tzz * Tzz),
+                                           0.5 * (Sxx * Sxx + Syy * Syy + Szz * Szz),
+                                           Sxyb * Sxyb + Sxzb * Sxzb + Syzb * Syzb, Dp, D, kk, ptr, s->coh[c],
+                                           &s->pn[c], &tret, &Y, &ld);
                 s->lamdot[c] = ld;
                 s->tII[c] = tret;
                 s->yld[c] = Y;
                 if (lam > 0.0) ny_count++;
                 if (mode == 0 && s->freeze == 1) s->lamf[c] = lam;
-                if (mode == 0 && s->freeze == 2) {
+                if (s->freeze == 2) {   /* held Lambda, also in the certificate */
                     lam = s->lamf[c];
-                    if (s->C > 0.0) s->pn[c] = ptr + lam * sqrt(J2) / (D + lam) * s->C * kk;
+                    if (s->C > 0.0) s->pn[c] = ptr + lam * sqrt(J2) / (Dp + lam) * s->C * kk;
                 }
                 s->lam[c] = lam;
                 s->txxn[c] = Txx / (D + lam);
@@ -1024,6 +1072,20 @@ void orc_objective_update(orc_state* s)
     else objective3d(s);
 }
 
+/* Copy the stresses of the last evaluation (orc_sweep modes 1 and 2 leave
+ * them in the new-value arrays) into the state. */
+static void commit_evaluated_stresses(orc_state* s)
+{
+    long nc = n_cells(s);
+    copy_n(s->p, s->pn, nc);
+    copy_n(s->txx, s->txxn, nc);
+    copy_n(s->tyy, s->tyyn, nc);
+    copy_n(s->tzz, s->tzzn, s->ndim == 3 ? nc : 0);
+    copy_n(s->txy, s->txyn, n_xy(s));
+    copy_n(s->txz, s->txzn, n_xz(s));
+    copy_n(s->tyz, s->tyzn, n_yz(s));
+}
+
 static void save_start(orc_state* s)
 {
     long nc = n_cells(s);
@@ -1059,8 +1121,8 @@ static void roll_back(orc_state* s)
 static void epilogue(orc_state* s, orc_stats* st)
 {
     /* centre diagnostics (Lambda, plastic rate, returned tauII, bound) of the
-     * accepted state: one PT evaluation that commits nothing */
-    orc_sweep(s, 2);
+     * accepted state: its physical evaluation, which commits nothing */
+    orc_sweep(s, 1);
     const int nx = s->nx, ny = s->ny, nz = s->nz;
     const double A = s->A, B = s->B;
     const double dt = s->prm.dt, dx = s->dx, dy = s->dy, dz = s->dz;
@@ -1166,29 +1228,43 @@ int orc_load_step(orc_state* s, orc_stats* st)
      * guessed velocities (the evaluation above), not from the previous
      * increment's stresses: same fixed point, no pseudo-time relaxation of
      * stresses that the guess already determines */
-    {
-        long nc = n_cells(s);
-        copy_n(s->p, s->pn, nc);
-        copy_n(s->txx, s->txxn, nc);
-        copy_n(s->tyy, s->tyyn, nc);
-        copy_n(s->tzz, s->tzzn, s->ndim == 3 ? nc : 0);
-        copy_n(s->txy, s->txyn, n_xy(s));
-        copy_n(s->txz, s->txzn, n_xz(s));
-        copy_n(s->tyz, s->tyzn, n_yz(s));
-    }
+    commit_evaluated_stresses(s);
 
     const int nchk = s->prm.n_check;
     int status = -4;
     double res = NAN;
     int it;
     s->freeze = 0;
+    /* a starting state that already meets the tolerance is accepted as it
+     * is (its residual is the certificate): pseudo-time sweeps would first
+     * roughen it (its stresses are already the physical ones) */
+    if (st->r_ref <= s->prm.tol * st->ref) {
+        st->iters = 0;
+        st->resid = st->cert = st->r_ref;
+        st->eps_rel = 0.0;
+        st->status = 0;
+        epilogue(s, st);
+        return 0;
+    }
     for (it = 1; it <= s->prm.max_iter; ++it) {
         res = orc_sweep(s, 0);
         if (s->freeze == 1) s->freeze = 2;   /* that sweep stored its Lambda */
         if (it % nchk == 0) {
             if (s->hist && s->hist_len < s->hist_cap) s->hist[s->hist_len++] = res;
             if (!(res == res) || isinf(res) || res > 1e8 * st->ref) { status = -5; break; }
-            if (res <= s->prm.tol * st->ref) { status = 0; break; }
+            if (res <= s->prm.tol * st->ref) {
+                /* acceptance: the momentum residual of the physical stresses
+                 * of the current velocities (pseudo-time terms removed) must
+                 * meet the tolerance too; that evaluation is the accepted
+                 * state's certificate, and its stresses the accepted ones */
+                double cert = orc_sweep(s, 1);
+                if (cert <= s->prm.tol * st->ref) {
+                    st->cert = cert;
+                    commit_evaluated_stresses(s);
+                    status = 0;
+                    break;
+                }
+            }
             /* frozen plasticity: an increment still iterating after
              * freeze_iter iterations continues with the plastic multiplier
              * of the next sweep held fixed (a linear problem) */

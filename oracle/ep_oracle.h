@@ -39,6 +39,9 @@ typedef struct orc_params {
     double eta_vp;           /* consistency regularisation of the return: yielding points
                                 carry tauII = A p + B c + eta_vp lambda_dot (0: perfect
                                 plasticity) */
+    double pt_blend;         /* weight in [0, 1] of the pseudo-time trial in the centre plastic
+                                multiplier during the iteration (0: the physical trial alone);
+                                the converged state does not depend on it */
 } orc_params;
 
 typedef struct orc_stats {
@@ -46,12 +49,14 @@ typedef struct orc_stats {
     int    iters;            /* PT iterations performed */
     double r_ref;            /* residual of the physical stresses of the plain guess */
     double ref;              /* max(r_ref, dsigma_ref / L) */
-    double resid;            /* final L-inf momentum residual (absolute) */
+    double resid;            /* residual of the iteration at the accepted check (absolute) */
+    double cert;             /* momentum residual of the accepted state's physical stresses
+                                (pseudo-time terms removed): the certificate, <= tol * ref */
     double eps_rel;          /* max|v^{k+1}-v^k| / max|v| at the final check */
     double sxx_centre;       /* integral of sigma_xx over the centre column */
     double sxx_left;         /* ... over the first column */
     double sxx_right;        /* ... over the last column */
-    long long n_yield;       /* cells on the yield surface in a PT evaluation of the accepted state */
+    long long n_yield;       /* yielding cells in the physical evaluation of the accepted state */
     double max_violation;    /* max over cells of tauII(stored stresses) - max(0, A p + B c) */
     int    frozen_at;        /* iteration whose check froze Lambda (0: not frozen) */
 } orc_stats;

@@ -35,13 +35,14 @@ class OrcParams(C.Structure):
         ("max_iter", C.c_int), ("n_check", C.c_int),
         ("re", C.c_double), ("r", C.c_double), ("cfl", C.c_double),
         ("freeze_iter", C.c_int), ("objective", C.c_int), ("eta_vp", C.c_double),
+        ("pt_blend", C.c_double),
     ]
 
 
 class OrcStats(C.Structure):
     _fields_ = [
         ("status", C.c_int), ("iters", C.c_int),
-        ("r_ref", C.c_double), ("ref", C.c_double), ("resid", C.c_double),
+        ("r_ref", C.c_double), ("ref", C.c_double), ("resid", C.c_double), ("cert", C.c_double),
         ("eps_rel", C.c_double), ("sxx_centre", C.c_double), ("sxx_left", C.c_double),
         ("sxx_right", C.c_double), ("n_yield", C.c_longlong), ("max_violation", C.c_double),
         ("frozen_at", C.c_int),
@@ -97,6 +98,7 @@ def params_from_model(m) -> OrcParams:
     p.freeze_iter = m.freeze_iter
     p.objective = m.objective
     p.eta_vp = m.eta_vp
+    p.pt_blend = m.pt_blend
     return p
 
 

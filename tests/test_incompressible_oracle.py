@@ -3,8 +3,9 @@ pressure equation A2ssP2, the K -> infinity limit of A2ssP) in the oracle.
 
 The oracle takes K = +inf as the incompressible case (1/(K dt) = 0 in the
 pressure update; readings for the residual and the physical evaluation).  Its
-converged states must be the limit of the compressible ones: over four
-increments of a small yielding 2D model, the gap to the K = +inf state falls by
+converged states must be the limit of the compressible ones: over three
+increments of a small yielding 2D model (up to the point where the increment
+stops having a unique solution), the gap to the K = +inf state falls by
 the factor by which K grows (O(1/K)), down to 1e-4 of the field scales at
 K = 1e4 — a dropped pressure term or a wrong sign would leave an O(1) gap or a
 different rate."""
@@ -32,8 +33,11 @@ def gaps(ref, got):
 
 
 def test_incompressible_state_is_the_stiff_limit():
+    # three increments: the inclusion yields in the second; in the fourth the
+    # plastic zone reaches the walls and the increment has more than one
+    # solution, so states of different K no longer compare (one branch each)
     base = Model(ndim=2, nx=31, ny=31, tol=1e-9, n_check=10, incl_centre=(0.05, 0.03, 0.0), incl_radius=0.15,
-                 dt=2e-4, steps=4)
+                 dt=2e-4, steps=3)
     st, ref = run(base.with_(bulk=math.inf))
     assert all(s["status"] == 0 for s in st)
     assert st[-1]["n_yield"] > 0

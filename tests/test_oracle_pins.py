@@ -319,6 +319,9 @@ def test_residual_envelope_plastic_is_bounded(c1_run):
     m, _, stats, hists, _ = c1_run
     per = m.nx // 10                      # checks per nx iterations (n_check = 10)
     for s, h in zip(stats, hists):
+        if s["iters"] == 0:               # the starting state met the tolerance
+            assert len(h) == 0 and s["cert"] <= m.tol * s["ref"]
+            continue
         assert h[-1] <= m.tol * s["ref"]
         if len(h) > 2 * per:
             assert h[per:].max() <= 2.0 * h[:per].max()

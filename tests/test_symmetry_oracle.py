@@ -36,7 +36,7 @@ def run(m, sign):
 
 
 def test_branches_are_mirror_images():
-    m = e2_symmetry(7, nx=95, ny=47)
+    m = e2_symmetry(7, nx=95, ny=47, tol=1e-10)
     sa, ea, va = run(m, +1.0)
     sb, eb, vb = run(m, -1.0)
     assert all(s["status"] == 0 for s in sa + sb)
@@ -51,7 +51,9 @@ def test_branches_are_mirror_images():
     # ... but symmetric under the point reflection
     assert np.abs(ea[-1] - ea[-1][::-1, ::-1]).max() <= 1e-9 * top
     # the two branches are x-mirror images of each other
-    assert [s["iters"] for s in sa] == [s["iters"] for s in sb]
+    # (iteration counts equal up to one check: the mirror images differ by
+    # rounding, which can move an acceptance at the tolerance by one check)
+    assert all(abs(x["iters"] - y["iters"]) <= m.n_check for x, y in zip(sa, sb))
     for x, y in zip(sa, sb):
         assert abs(x["sxx_centre"] - y["sxx_centre"]) <= 1e-9 * abs(x["sxx_centre"])
         assert x["n_yield"] == y["n_yield"]
