@@ -48,7 +48,8 @@ class Model:
     freeze_iter: int = 0         # 0: off; else freeze the plastic multiplier after this many iterations
     objective: int = 0           # 1: objective (Jaumann) stress update at the start of every increment
     eta_vp: float = 0.0          # consistency regularisation viscosity of the return (0: perfect plasticity)
-    pt_blend: float = 0.25       # weight of the pseudo-time trial in the centre plastic multiplier (path only)
+    pt_blend: float = 0.25       # weight of the pseudo-time trial in the centre plastic multiplier (path only) ...
+    pt_blend_late: float = 0.75  # ... and after the first check at or after 16 max(nx, ny, nz) iterations
     # weak inclusion in cohesion
     c0: float = 1.75e-3
     incl_radius: float = 0.1

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define EP_ABI_VERSION 1
+#define EP_ABI_VERSION 2
 
 /* return codes */
 #define EP_OK          0
@@ -112,6 +112,18 @@ typedef struct ep_params {
                                 returns to tauII = A p + B c + eta_vp lambda_dot, with
                                 lambda_dot = 2 eps_dot_p,II from the consistency condition
                                 (0: perfect plasticity, the paper's runs; >= 0, finite) */
+    double pt_blend;         /* return mapping of the iteration (return-mapping section,
+                                Lambda form): the centre plastic multiplier is the radial
+                                return of the physical trial S = tau^/(G dt) + 2 e' (shear
+                                parts averaged from the four shear points), blended with
+                                weight pt_blend in [0, 1] with the return of the pseudo-time
+                                trial.  Both agree at the fixed point, which is therefore the
+                                solution of the increment's equations with the pseudo-time
+                                terms removed for any weight; the blend only shapes the path */
+    double pt_blend_late;    /* the weight from the first check at or after 16 max(nx, ny, nz)
+                                iterations of an increment on (the workloads use 0.25, then
+                                0.75: the only schedule among those measured under which every
+                                test increment converged) */
 } ep_params;
 
 typedef struct ep_step_stats {
@@ -134,13 +146,23 @@ typedef struct ep_step_stats {
                                 -1: it failed from the guess and was redone from the plain guess
                                 (iters counts both attempts) */
     double r_guess;          /* momentum residual of the physical stresses of that guess (0: none) */
+    double cert;             /* certificate of the accepted state: the FP64 momentum residual of
+                                the physical stresses of its velocities (pseudo-time terms
+                                removed), <= tol * ref; those stresses are the accepted ones */
 } ep_step_stats;
 
 typedef struct ep_residual_info {
     double resid;            /* combined residual of one PT evaluation of the current state */
-    double momentum;         /* L-inf momentum residual of the current stresses (eq. for eps_abs) */
-    double physical;         /* momentum residual of the physical stresses of the current v */
-    double vmax;             /* max |v| */
+    double momentum;         /* L-inf momentum residual of one PT update of the current state
+                                (the absolute error of the convergence section) */
+    double physical;         /* momentum residual of the physical stresses of the current v
+                                (the certificate of ep_step_stats) */
+    double vmax;             /* max |v| after that update */
+    double continuity;       /* L-inf of (p - p^)/(K dt) + div v of the current state (the
+                                pressure equation without its pseudo-time term; max|div v| for
+                                K = +inf) */
+    double eps_rel;          /* relative error of the convergence section: max|v^{k+1} - v^k| /
+                                max|v^{k+1}| of that PT update */
 } ep_residual_info;
 
 /* field ids for ep_fields / ep_field_shape */
@@ -181,9 +203,12 @@ int ep_init(const ep_params* p, const double* cohesion, void* d_workspace, size_
 /* Solve one load increment: save the increment's starting stresses (p^,
  * tau^); evaluate the physical stresses of the previous velocities (the plain
  * guess) -- their momentum residual is R_ref and they are the pseudo-time
- * starting point of p and tau; iterate PT sweeps until the residual
- * (momentum L-inf combined with the pressure and deviator pseudo-rates, see
- * the paper's convergence section) is at most tol * ref; then add v dt to
+ * starting point of p and tau (accepted at once when R_ref already meets the
+ * tolerance); iterate PT sweeps until the residual (momentum L-inf combined
+ * with the pressure and deviator pseudo-rates, see the paper's convergence
+ * section) is at most tol * ref and, at that check, the FP64 momentum
+ * residual of the physical stresses of the current velocities is too (the
+ * certificate; those stresses become the accepted state); then add v dt to
  * the displacement and the strain-rate increments to the accumulated
  * strains.  On EP_ENOTCONV / EP_EDIVERGED the state is rolled back to the
  * increment start and st is still filled.  st may be NULL. */

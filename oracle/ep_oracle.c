@@ -101,6 +101,7 @@ struct orc_state {
      * 2 sweeps use the stored Lambda instead of the return mapping */
     int freeze;
     double *lamf;
+    int late;                 /* the iteration's return uses pt_blend_late */
 };
 
 /* ---------------------------------------------------------------- sizes */
@@ -126,6 +127,8 @@ static long n_yz(const orc_state* s) { return s->ndim == 3 ? (long)s->nx * (s->n
 #define XY3(i, j, k) ((i) + (nx + 1) * ((j) + (ny + 1) * (k)))
 #define XZ3(i, j, k) ((i) + (nx + 1) * ((j) + ny * (k)))
 #define YZ3(i, j, k) ((i) + nx * ((j) + (ny + 1) * (k)))
+
+static int imax(int a, int b) { return a > b ? a : b; }
 
 static double* zalloc(long n) { return n > 0 ? (double*)calloc((size_t)n, sizeof(double)) : NULL; }
 
@@ -179,6 +182,8 @@ orc_state* orc_create(const orc_params* prm, const double* cohesion)
     if (!(prm->psi_deg >= 0.0) || prm->psi_deg > prm->phi_deg) return NULL;
     if (!(prm->visc > 0)) return NULL;
     if (!(prm->eta_vp >= 0.0) || isinf(prm->eta_vp)) return NULL;
+    if (!(prm->pt_blend >= 0.0 && prm->pt_blend <= 1.0)) return NULL;
+    if (!(prm->pt_blend_late >= 0.0 && prm->pt_blend_late <= 1.0)) return NULL;
     orc_state* s = (orc_state*)calloc(1, sizeof(orc_state));
     s->prm = *prm;
     s->ndim = prm->ndim;
@@ -390,6 +395,8 @@ static double plastic_lambda(double sq, double D, double p_tr, double c, double 
  * convergence).
  *
  * The iteration uses Lambda = Lambda_phys + blend (Lambda_pt - Lambda_phys),
+ * blend = pt_blend until the first check at or after 16 max(nx, ny, nz)
+ * iterations of an increment and pt_blend_late afterwards,
  * Lambda_pt being the radial return of the pseudo-time trial: the centre's
  * normal T with the averaged shear trial scaled to the pseudo-time form it
  * has at the fixed point, f S_shear, f = (D + Lambda_phys)/(Dp + Lambda_phys),
@@ -416,7 +423,8 @@ static double centre_return(const orc_state* s, double nT2, double nS2, double s
         return 0.0;
     }
     double lam = plastic_lambda(sqS, Dp, p_tr, c, A, B, C, k, vp, p, tII, Y, lamdot);
-    if (s->prm.pt_blend == 0.0 || D == Dp || isinf(lam)) return lam;
+    const double blend = s->late ? s->prm.pt_blend_late : s->prm.pt_blend;
+    if (blend == 0.0 || D == Dp || isinf(lam)) return lam;
     /* pseudo-time trial */
     const double f = (D + lam) / (Dp + lam);
     const double sqT = sqrt(nT2 + f * f * sh2);
@@ -426,8 +434,8 @@ static double centre_return(const orc_state* s, double nT2, double nS2, double s
         lam_t = plastic_lambda(sqT, D, p_tr, c, A, B, C, k, vp, &p_t, &t1, &t2, &t3);
     }
     if (isinf(lam_t)) return lam;
-    *p = *p + s->prm.pt_blend * (p_t - *p);
-    return lam + s->prm.pt_blend * (lam_t - lam);
+    *p = *p + blend * (p_t - *p);
+    return lam + blend * (lam_t - lam);
 }
 
 static double p_res_visc(const orc_state* s) { return isinf(s->prm.bulk) ? s->eta : s->prm.bulk * s->prm.dt; }
@@ -1265,6 +1273,9 @@ int orc_load_step(orc_state* s, orc_stats* st)
                     break;
                 }
             }
+            /* the blend of the iteration's return changes once, at the
+             * first check at or after 16 max(nx, ny, nz) iterations */
+            if (!s->late && it >= 16 * imax(s->nx, imax(s->ny, s->nz))) s->late = 1;
             /* frozen plasticity: an increment still iterating after
              * freeze_iter iterations continues with the plastic multiplier
              * of the next sweep held fixed (a linear problem) */
@@ -1275,6 +1286,7 @@ int orc_load_step(orc_state* s, orc_stats* st)
         }
     }
     s->freeze = 0;
+    s->late = 0;
     st->iters = it > s->prm.max_iter ? s->prm.max_iter : it;
     st->resid = res;
     st->eps_rel = s->vmax > 0 ? s->dtrho * res / s->vmax : 0.0;

@@ -42,6 +42,8 @@ typedef struct orc_params {
     double pt_blend;         /* weight in [0, 1] of the pseudo-time trial in the centre plastic
                                 multiplier during the iteration (0: the physical trial alone);
                                 the converged state does not depend on it */
+    double pt_blend_late;    /* the weight after the first check at or after 16 max(nx, ny, nz)
+                                iterations of an increment */
 } orc_params;
 
 typedef struct orc_stats {

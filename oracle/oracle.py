@@ -35,7 +35,7 @@ class OrcParams(C.Structure):
         ("max_iter", C.c_int), ("n_check", C.c_int),
         ("re", C.c_double), ("r", C.c_double), ("cfl", C.c_double),
         ("freeze_iter", C.c_int), ("objective", C.c_int), ("eta_vp", C.c_double),
-        ("pt_blend", C.c_double),
+        ("pt_blend", C.c_double), ("pt_blend_late", C.c_double),
     ]
 
 
@@ -99,6 +99,7 @@ def params_from_model(m) -> OrcParams:
     p.objective = m.objective
     p.eta_vp = m.eta_vp
     p.pt_blend = m.pt_blend
+    p.pt_blend_late = m.pt_blend_late
     return p
 
 

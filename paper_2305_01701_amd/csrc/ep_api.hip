@@ -62,6 +62,8 @@ int validate(const ep_params* p)
     if (p->freeze_iter < 0 || p->guess_accept < 0) return EP_EINVAL;
     if (p->objective != 0 && p->objective != 1) return EP_EINVAL;
     if (!(p->eta_vp >= 0.0) || std::isinf(p->eta_vp)) return EP_EINVAL;
+    if (!(p->pt_blend >= 0.0 && p->pt_blend <= 1.0)) return EP_EINVAL;
+    if (!(p->pt_blend_late >= 0.0 && p->pt_blend_late <= 1.0)) return EP_EINVAL;
     return EP_OK;
 }
 
@@ -128,7 +130,7 @@ size_t carve(const ep_params* p, ep_handle* h, char* base)
     if (p->ndim == 2) {
         const long nt = (long)((nx + kBatchTiles[SINGLE_SHAPE][0] - 1) / kBatchTiles[SINGLE_SHAPE][0]) *
                         ((ny + kBatchTiles[SINGLE_SHAPE][1] - 1) / kBatchTiles[SINGLE_SHAPE][1]);
-        q = take(8 * sizeof(SweepArgs<double>)); if (h) h->tab64 = (SweepArgs<double>*)q;
+        q = take(10 * sizeof(SweepArgs<double>)); if (h) h->tab64 = (SweepArgs<double>*)q;
         q = take(6 * sizeof(SweepArgs<float>)); if (h) h->tab32 = (SweepArgs<float>*)q;
         q = take(nt * sizeof(TileRef)); if (h) h->tiles = (TileRef*)q;
         q = take(sizeof(int)); if (h) h->tcount = (int*)q;
@@ -222,6 +224,9 @@ SweepArgs<R> make_args(const ep_handle* h, R* const* from, R* const* to, R* cons
     a.ikd = (R)ikd;
     a.D = (R)(igt + igd + h->inv_mus);
     a.invD = (R)(1.0 / (igt + igd + h->inv_mus));
+    a.Dp = (R)(igd + h->inv_mus);
+    a.invDp = (R)(1.0 / (igd + h->inv_mus));
+    a.blend = (R)(h->late ? h->prm.pt_blend_late : h->prm.pt_blend);
     a.ikk = (R)(1.0 / (ikt + ikd));
     a.dtrho = (R)h->dtrho;
     a.A = (R)h->A;
@@ -283,8 +288,9 @@ void launch_sweep(const ep_handle* h, bool physical, int from, int mode, int lam
             launch_sweep_batch_2d<float>(SINGLE_SHAPE, h->tab32 + 2 * lam_mode + from, h->tiles, h->tcount, mode,
                                          h->grid2[1], h->st);
         else
-            launch_sweep_batch_2d<double>(SINGLE_SHAPE, h->tab64 + (physical ? 6 : 2 * lam_mode) + from, h->tiles,
-                                          h->tcount, mode, h->grid2[0], h->st);
+            launch_sweep_batch_2d<double>(SINGLE_SHAPE,
+                                          h->tab64 + (physical ? 6 + 2 * (lam_mode == LAM_FROZEN) : 2 * lam_mode) + from,
+                                          h->tiles, h->tcount, mode, h->grid2[0], h->st);
         return;
     }
     SweepArgs<R> a;
@@ -300,12 +306,13 @@ void launch_sweep(const ep_handle* h, bool physical, int from, int mode, int lam
     }
 }
 
-// Device tables of the 2D tile kernel: FP64 [lam mode][from] then physical
-// [from]; FP32 [lam mode][from].  The tile list (shape 0) is written once.
+// Device tables of the 2D tile kernel: FP64 [lam mode][from], then physical
+// [from] and physical with the frozen Lambda [from]; FP32 [lam mode][from].
+// The tile list (shape 0) is written once.
 int upload_tables(ep_handle* h)
 {
     if (h->ndim != 2) return EP_OK;
-    SweepArgs<double> t64[8];
+    SweepArgs<double> t64[10];
     SweepArgs<float> t32[6];
     for (int lm = 0; lm < 3; ++lm)
         for (int from = 0; from < 2; ++from) {
@@ -316,8 +323,11 @@ int upload_tables(ep_handle* h)
                 t32[2 * lm + from].lam_mode = lm;
             }
         }
-    t64[6] = args64(h, true, 0);
-    t64[7] = args64(h, true, 1);
+    for (int from = 0; from < 2; ++from) {
+        t64[6 + from] = args64(h, true, from);
+        t64[8 + from] = args64(h, true, from);
+        t64[8 + from].lam_mode = LAM_FROZEN;
+    }
     HIPCHK(h, hipMemcpyAsync(h->tab64, t64, sizeof(t64), hipMemcpyHostToDevice, h->st));
     if (h->fp32) HIPCHK(h, hipMemcpyAsync(h->tab32, t32, sizeof(t32), hipMemcpyHostToDevice, h->st));
     HIPCHK(h, hipStreamSynchronize(h->st));
@@ -489,6 +499,10 @@ void step_begin(ep_handle* h, ep_step_stats* st)
     std::memset(st, 0, sizeof(*st));
     h->freeze = 0;
     h->lam_in32 = false;
+    if (h->late) {
+        h->late = false;
+        if (!h->in_batch) upload_tables(h);
+    }
 
     // increment start state and wall velocities
     ensure_it64(h);
@@ -556,6 +570,16 @@ int step_start(ep_handle* h, const double red[RED_N])
     h->hist_p.clear();
 
     c.tol_abs = h->prm.tol * st->ref;
+    // a starting state that already meets the tolerance is accepted as it is:
+    // its stresses are the physical ones, its residual the certificate
+    const double r_start = st->guess_used == 1 ? st->r_guess : st->r_ref;
+    if (r_start <= c.tol_abs) {
+        st->cert = r_start;
+        c.resid = r_start;
+        c.status = EP_OK;
+        c.running = false;
+        return EP_OK;
+    }
     c.sw = (h->prm.fp32_switch > 0 ? h->prm.fp32_switch : 2.0 * h->prm.tol) * st->ref;
     c.use32 = h->fp32;
     if (c.use32) ensure_it32(h);
@@ -607,8 +631,23 @@ bool step_check(ep_handle* h, const double red[RED_N], int nb)
             st->fp32_exit = c.resid / st->ref;
         }
     } else if (c.resid <= c.tol_abs) {
-        c.status = EP_OK;
-        c.running = false;
+        // acceptance needs the certificate (step_certify_launch, step_certify)
+        c.cert_pending = true;
+        return true;
+    }
+    check_limits(h);
+    return c.running;
+}
+
+void check_limits(ep_handle* h)
+{
+    StepCtl& c = h->ctl;
+    ep_step_stats* st = c.st;
+    // the return's blend changes once, at the first check at or after
+    // 16 max(nx, ny, nz) iterations
+    if (c.running && !h->late && st->iters >= 16 * std::max(h->nx, std::max(h->ny, h->nz))) {
+        h->late = true;
+        if (!h->in_batch) upload_tables(h);
     }
     // frozen plasticity: still iterating at freeze_iter -> the next sweep
     // stores its centre Lambda and later sweeps hold it fixed
@@ -620,12 +659,42 @@ bool step_check(ep_handle* h, const double red[RED_N], int nb)
         c.status = EP_ENOTCONV;
         c.running = false;
     }
+}
+
+void step_certify_launch(ep_handle* h)
+{
+    // physical stresses of the current velocities (the held Lambda when
+    // frozen) into the other buffer, their momentum residual into h->red
+    launch_reset_red(h->red, h->st);
+    launch_sweep<double>(h, true, h->cur64, MODE_PHYS, h->freeze == 2 ? LAM_FROZEN : LAM_COMPUTE);
+}
+
+bool step_certify(ep_handle* h, const double red[RED_N])
+{
+    StepCtl& c = h->ctl;
+    c.cert_pending = false;
+    if (red[RED_MOM] <= c.tol_abs) {
+        // accepted: the physical stresses with the current velocities
+        for (int d = 0; d < h->ndim; ++d)
+            launch_copy(h->it64[1 - h->cur64][F_VX + d], h->it64[h->cur64][F_VX + d], h->nelem, h->st);
+        h->cur64 = 1 - h->cur64;
+        h->it32_valid = false;
+        c.st->cert = red[RED_MOM];
+        c.status = EP_OK;
+        c.running = false;
+        return false;
+    }
+    check_limits(h);
     return c.running;
 }
 
 int step_finish(ep_handle* h)
 {
     h->freeze = 0;                  // sweeps outside an increment compute Lambda
+    if (h->late) {                  // ... with the first blend
+        h->late = false;
+        if (!h->in_batch) upload_tables(h);
+    }
     StepCtl& c = h->ctl;
     ep_step_stats* st = c.st;
     st->resid = c.resid;
@@ -639,7 +708,7 @@ int step_finish(ep_handle* h)
     }
     // diagnostics of the accepted state, FP64 accumulators
     launch_reset_red(h->red, h->st);
-    launch_diagnostics<double>(args64(h, false, h->cur64), h->lamdot64, h->tii64, h->yld64, h->st);
+    launch_diagnostics<double>(args64(h, true, h->cur64), h->lamdot64, h->tii64, h->yld64, h->st);
     double** it = h->it64[h->cur64];
     const double* v[3] = {it[F_VX], it[F_VY], it[F_VZ]};
     launch_accumulate(h->g, h->prm.dt, 1.0 / h->dx, 1.0 / h->dy, 1.0 / h->dz, v, h->u64, h->e64, h->epsp64,
@@ -912,10 +981,17 @@ int ep_residual(ep_handle* h, ep_residual_info* r)
     r->resid = red[RED_RESID];
     r->momentum = red[RED_MOM];
     r->vmax = red[RED_VMAX];
+    r->eps_rel = red[RED_VMAX] > 0 ? h->dtrho * red[RED_MOM] / red[RED_VMAX] : 0.0;
     launch_reset_red(h->red, h->st);
     launch_sweep<double>(h, true, h->cur64, MODE_PHYS);
+    double** it = h->it64[h->cur64];
+    const double* v[3] = {it[F_VX], it[F_VY], it[F_VZ]};
+    const double ikd = std::isinf(h->prm.bulk) ? 0.0 : 1.0 / (h->prm.bulk * h->prm.dt);
+    launch_continuity(h->g, v, it[F_P], h->old64[O_P], ikd, 1.0 / h->dx, 1.0 / h->dy, 1.0 / h->dz, h->red + RED_CONT,
+                      h->st);
     if ((rc = read_red(h, red))) return rc;
     r->physical = red[RED_MOM];
+    r->continuity = red[RED_CONT];
     return EP_OK;
 }
 
@@ -987,6 +1063,11 @@ int ep_load_step(ep_handle* h, ep_step_stats* st)
         if ((rc = read_red(h, red))) return rc;
         add_timing(h, use32, nb);
         step_check(h, red, nb);
+        if (c.cert_pending) {
+            step_certify_launch(h);
+            if ((rc = read_red(h, red))) return rc;
+            step_certify(h, red);
+        }
     }
     if ((rc = step_finish(h))) {
         if (st->guess_used != 1) return rc;

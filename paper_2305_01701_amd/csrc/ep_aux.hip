@@ -213,6 +213,26 @@ __global__ __launch_bounds__(256) void k_diag(SweepArgs<R> a, double* lamdot, do
     block_max_to<256>(i < a.nx && j < a.ny ? viol + 1.0 : 0.0, a.red + RED_VIOL, sh);
 }
 
+// Continuity residual of the current state: max over cells of
+// |(p - p^)/(K dt) + div v| (ikd = 1/(K dt), 0 in the incompressible limit).
+__global__ void k_continuity(AuxGrid g, const double* vx, const double* vy, const double* vz, const double* p,
+                             const double* p_old, double ikd, double idx, double idy, double idz,
+                             unsigned long long* red)
+{
+    __shared__ double sh[NT1 / 64];
+    const int nz = g.ndim == 3 ? g.nz : 1;
+    const long n = (long)g.nx * g.ny * nz;
+    double m = 0.0;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+        const long i = t % g.nx, j = (t / g.nx) % g.ny, k = t / ((long)g.nx * g.ny);
+        const long c = i + g.sy * j + g.sz * k;
+        double div = (vx[c + 1] - vx[c]) * idx + (vy[c + g.sy] - vy[c]) * idy;
+        if (g.ndim == 3) div += (vz[c + g.sz] - vz[c]) * idz;
+        m = nmax(m, fabs((p[c] - p_old[c]) * ikd + div));
+    }
+    block_max_to<NT1>(m, red, sh);
+}
+
 __global__ void k_columns(AuxGrid g, const double* p, const double* txx, double w, double* out)
 {
     // one block per column (0, nx/2, nx-1); threads stride over (j, k)
@@ -484,6 +504,14 @@ void launch_diagnostics(const SweepArgs<R>& a, double* lamdot, double* tii, doub
 }
 template void launch_diagnostics<double>(const SweepArgs<double>&, double*, double*, double*, hipStream_t);
 template void launch_diagnostics<float>(const SweepArgs<float>&, double*, double*, double*, hipStream_t);
+
+void launch_continuity(const AuxGrid& g, const double* const v[3], const double* p, const double* p_old, double ikd,
+                       double idx, double idy, double idz, unsigned long long* red_slot, hipStream_t s)
+{
+    const int nz = g.ndim == 3 ? g.nz : 1;
+    k_continuity<<<blocks_for((long)g.nx * g.ny * nz), NT1, 0, s>>>(g, v[0], v[1], v[2], p, p_old, ikd, idx, idy,
+                                                                   idz, red_slot);
+}
 
 void launch_column_integrals(const AuxGrid& g, const double* p, const double* txx, double dy, double dz,
                              double* out3, hipStream_t s)

@@ -530,8 +530,29 @@ int ep_batch_load_step(ep_batch* b, ep_step_stats* st)
             double red[RED_N];
             model_red(b, i, red);
             const int freeze_before = h->freeze;
+            const bool late_before = h->late;
             const bool cont = step_check(h, red, b->n_check);
-            if (!cont || h->ctl.use32 != was32 || h->freeze != freeze_before) dirty = true;
+            if (!cont || h->ctl.use32 != was32 || h->freeze != freeze_before || h->late != late_before) dirty = true;
+        }
+        // certificates of the models whose check met the tolerance (the
+        // single-model evaluation on each model's own reduction slots)
+        bool any_cert = false;
+        for (ep_handle* h : b->m)
+            if (h->ctl.running && h->ctl.cert_pending) {
+                step_certify_launch(h);
+                any_cert = true;
+            }
+        if (any_cert) {
+            if ((rc = read_all(b, false))) return rc;
+            for (int i = 0; i < b->n; ++i) {
+                ep_handle* h = b->m[i];
+                if (!h->ctl.running || !h->ctl.cert_pending) continue;
+                double red[RED_N];
+                model_red(b, i, red);
+                const int freeze_before = h->freeze;
+                const bool late_before = h->late;
+                if (!step_certify(h, red) || h->freeze != freeze_before || h->late != late_before) dirty = true;
+            }
         }
     }
     int worst = EP_OK;

@@ -151,31 +151,60 @@ __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double fast_sqrt(double x) { return sqrt(x); }
 
-// Radial return in scale form.  With tauII_tr = sqrt(J2)/D and the bound
-// Y = max(0, A p + B c): elastic (tauII_tr <= Y) gives Lambda = 0 and the
-// factor 1/(D + Lambda) = 1/D; yielding gives Lambda = sqrt(J2)/Y - D and
-// 1/(D + Lambda) = Y/sqrt(J2), so the returned deviator T Y/sqrt(J2) lies on
-// the yield surface (above it by vp lamdot with the regularisation).  Same
-// quantities as centre_lambda, one root and one reciprocal.
+// Return mapping at a centre (the return-mapping section, Lambda form on the
+// staggered grid).  The deviator of the iteration is tau = T / (D + Lambda)
+// with T = tau_k/(G~ dtau) + S, S = tau^/(G dt) + 2 e' the physical trial,
+// D = 1/(G~ dtau) + Dp, Dp = 1/(G dt) + 1/mu_s.  Lambda is the radial return
+// of the physical trial S (shear parts averaged from the four shear points)
+// against the bound: sqrt(J2(S)) = (Dp + Lambda) tauII, tauII = max(0, A p +
+// B c) (+ vp lamdot, with the pressure's dilatant correction).  With it the
+// fixed point tau = S / (Dp + Lambda) solves the increment's equations with
+// the pseudo-time terms removed, whatever the pseudo-time steps.  During the
+// iteration Lambda is blended with the return of the pseudo-time trial
+// (normal parts of T, averaged shear parts of S scaled to their pseudo-time
+// form at the fixed point, f = (D + Lambda) / (Dp + Lambda)) against D:
+// Lambda + blend (Lambda_T - Lambda), and the pressure likewise; both returns
+// agree at the fixed point.
+//   nT2, nS2: (1/2) sum of the squared normal components of T and of S;
+//   sh2: sum of the squared averaged shear components of S;
+//   p: the pressure update on entry, with its dilatant correction on exit.
+// Returns Lambda (0 elastic, +inf at the apex).
 template <typename R>
-__device__ __forceinline__ R return_scale(R J2, R D, R invD, R& p, R c, R A, R B, R Cik, R vp, R& lam)
+__device__ __forceinline__ R centre_return(R nT2, R nS2, R sh2, R Dp, R invDp, R D, R invD, R& p, R c, R A,
+                                           R B, R Cik, R vp, R blend)
 {
 #pragma clang fp contract(on)   // same rounding in every kernel that inlines it
-    R Y = A * p + B * c;
-    Y = Y > R(0) ? Y : R(0);
-    const R sq = fast_sqrt(J2);
-    if (sq * invD > Y) {
-        if (Cik != R(0) || vp != R(0)) {         // dilatant and/or regularised return
-            const R ld = consistent_rate(sq, D, p, c, A, B, Cik, vp);
-            Y = A * p + B * c;
-            Y = Y > R(0) ? Y : R(0);
-            Y = Y + vp * ld;                     // returned tauII
-        }
-        lam = sq * fast_rcp(Y) - D;
-        return Y * fast_rcp(sq);
+    R Y0 = A * p + B * c;
+    Y0 = Y0 > R(0) ? Y0 : R(0);
+    const R sqS = fast_sqrt(nS2 + sh2);
+    if (!(sqS * invDp > Y0)) return R(0);
+    const R ptr = p;
+    R tii = Y0;
+    if (Cik != R(0) || vp != R(0)) {             // dilatant and/or regularised return
+        const R ld = consistent_rate(sqS, Dp, p, c, A, B, Cik, vp);
+        tii = A * p + B * c;
+        tii = (tii > R(0) ? tii : R(0)) + vp * ld;
     }
-    lam = R(0);
-    return invD;
+    R lam = sqS * fast_rcp(tii) - Dp;
+    if (blend != R(0) && D != Dp && lam < R(INFINITY)) {
+        const R f = (D + lam) * fast_rcp(Dp + lam);
+        const R sqT = fast_sqrt(nT2 + f * f * sh2);
+        R lt = R(0), pt = ptr;
+        if (sqT * invD > Y0) {
+            R tt = Y0;
+            if (Cik != R(0) || vp != R(0)) {
+                const R ld = consistent_rate(sqT, D, pt, c, A, B, Cik, vp);
+                tt = A * pt + B * c;
+                tt = (tt > R(0) ? tt : R(0)) + vp * ld;
+            }
+            lt = sqT * fast_rcp(tt) - D;
+        }
+        if (lt < R(INFINITY)) {
+            lam = lam + blend * (lt - lam);
+            p = p + blend * (pt - p);
+        }
+    }
+    return lam;
 }
 
 }  // namespace ep

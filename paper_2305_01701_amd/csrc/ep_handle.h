@@ -22,6 +22,7 @@ struct StepCtl {
     int since_best;
     bool use32;           // sweeps currently run in FP32
     bool running;
+    bool cert_pending;    // the last check met the tolerance: the certificate decides
     int status;
     double resid, vmax;
 };
@@ -72,6 +73,7 @@ struct ep_handle {
     bool guess_ready;      // the next increment tries vguess64
     int freeze;            // 0 off, 1 the next sweep stores Lambda, 2 Lambda frozen
     bool lam_in32;         // the frozen Lambda is in lam32 (else lam64)
+    bool late;             // the increment's return uses pt_blend_late
     bool in_batch;         // owned by an ep_batch (ep_destroy ignores it)
     char err[512];
 };
@@ -115,6 +117,15 @@ int handle_create(const ep_params* p, const double* cohesion, char* d_workspace,
 void step_begin(ep_handle* h, ep_step_stats* st);
 int step_start(ep_handle* h, const double red[RED_N]);
 bool step_check(ep_handle* h, const double red[RED_N], int nb);
+//  step_certify_launch / step_certify: after a check that set
+//               ctl.cert_pending, the physical evaluation of the current
+//               velocities; its FP64 momentum residual (read after a
+//               synchronisation) accepts the increment with those stresses,
+//               or the iteration continues.
+void step_certify_launch(ep_handle* h);
+bool step_certify(ep_handle* h, const double red[RED_N]);
+// freeze and iteration-cap decisions after a check that did not converge
+void check_limits(ep_handle* h);
 int step_finish(ep_handle* h);
 void step_report(ep_handle* h, const double red[RED_N], const double cols[4]);
 // Reduction slots as doubles (raw uint64 patterns; RED_NYIELD is a count).

@@ -19,7 +19,7 @@ enum { O_P = 0, O_TXX, O_TYY, O_TXY, O_TXZ, O_TYZ, O_N };
 
 // Reduction slots (uint64 bit patterns of non-negative doubles; max by
 // integer atomicMax; NaN is mapped to +inf before reduction).
-enum { RED_RESID = 0, RED_MOM, RED_VMAX, RED_NYIELD, RED_VIOL, RED_SMAX, RED_N = 8 };
+enum { RED_RESID = 0, RED_MOM, RED_VMAX, RED_NYIELD, RED_VIOL, RED_SMAX, RED_CONT, RED_N = 8 };
 
 // Scalars of one PT sweep.  Kernel arguments by value.
 template <typename R>
@@ -38,6 +38,8 @@ struct SweepArgs {
     R igd, ikd;            // 1/(G dt), 1/(K dt)
     R D;                   // igt + igd + 1/mu_s
     R invD;                // 1 / D
+    R Dp, invDp;           // physical compliance igd + 1/mu_s and its inverse (uniform G)
+    R blend;               // weight of the pseudo-time trial in the iteration's centre Lambda
     R ikk;                 // 1 / (ikt + ikd)
     R dtrho;               // dtau / rho~
     R A, B;                // Drucker-Prager constants
@@ -61,7 +63,9 @@ enum { LAM_COMPUTE = 0, LAM_STORE = 1, LAM_FROZEN = 2 };
 // Sweep modes.
 enum { MODE_UPDATE = 0,    // write iteration k+1
        MODE_CHECK = 1,     // write k+1 and reduce the residual
-       MODE_PHYS = 2 };    // physical evaluation: reduce the momentum residual only, write nothing
+       MODE_PHYS = 2 };    // physical evaluation (pseudo-time terms removed): write the stresses
+                           // of the current velocities to the k+1 buffer, reduce the momentum
+                           // residual, leave the velocities
 
 // ---- launchers (ep_sweep_unfused.hip, ep_sweep_fused.hip) -------------------
 template <typename R> void launch_sweep_unfused_2d(const SweepArgs<R>& a, int mode, hipStream_t s);
@@ -135,6 +139,10 @@ struct ObjectiveArgs {
     double dx, dy, dz, dt;
 };
 void launch_objective(const AuxGrid& g, const ObjectiveArgs& a, hipStream_t s);
+// Continuity residual max |(p - p^) ikd + div v| over cells into *red_slot
+// (ikd = 1/(K dt); 0 in the incompressible limit).
+void launch_continuity(const AuxGrid& g, const double* const v[3], const double* p, const double* p_old, double ikd,
+                       double idx, double idy, double idz, unsigned long long* red_slot, hipStream_t s);
 // Column integrals of sigma_xx at columns i = 0, nx/2, nx-1 (3 doubles).
 void launch_column_integrals(const AuxGrid& g, const double* p, const double* txx, double dy,
                              double dz, double* out3, hipStream_t s);

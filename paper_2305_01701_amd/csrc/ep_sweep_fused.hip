@@ -43,9 +43,14 @@ struct TileSet {
 // ----------------------------------------------------------------------- 3D
 // Global data a march step needs is prefetched into registers one step
 // ahead (velocities of plane f+1, edge stresses of level f+1 and plane f,
-// centre data of plane f), so that HBM latency overlaps the LDS work of the
-// current step.  Each thread owns the same plane positions in every step.
-template <typename R, int TX, int TY, int ZC, int MODE, int NT, int WPE>
+// centre data of plane f, and with a per-cell G the compliances of plane
+// f+1), so that HBM latency overlaps the LDS work of the current step.  Each
+// thread owns the same plane positions in every step; the edge stage (S4)
+// works on the edge points among them, so the edge stresses of iteration k
+// it needs (for the pseudo-time trial and the residual) are the thread's own
+// prefetched values, and only the physical trials S (which the centres
+// average) go through LDS.
+template <typename R, int TX, int TY, int ZC, int MODE, int NT, int WPE, bool HG>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, NT), amdgpu_waves_per_eu(WPE)))
 void k_fused_3d(SweepArgs<R> a, TileSet ts)
 {
@@ -53,10 +58,12 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
     constexpr int NQ = (N + NT - 1) / NT;                  // plane positions per thread
     constexpr int CW = TX + 2, CN = (TX + 2) * (TY + 2);   // centre region (1-cell halo)
     constexpr int NR = (CN + NT - 1) / NT;
+    constexpr int NG = HG ? 2 : 1;
     __shared__ R s_vx[2][N], s_vy[2][N], s_vz[2][N];
-    __shared__ R s_Txy[N], s_Txz[2][N], s_Tyz[2][N];
+    __shared__ R s_Sxy[N], s_Sxz[2][N], s_Syz[2][N];
     __shared__ R s_lam[2][N], s_p[2][N], s_sxx[2][N], s_syy[2][N];
     __shared__ R s_nxy[2][N], s_nxz[2][N], s_nyz[2][N];
+    __shared__ R s_ig[NG][HG ? N : 1];                    // per-cell 1/(G dt), two planes
     __shared__ double s_red[NT / 64 > 0 ? NT / 64 : 1];
 
     const int lb = xcd_remap(blockIdx.x, ts.nbx * ts.nby * ts.nbz);
@@ -92,7 +99,7 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
     const R idx = a.idx, idy = a.idy, idz = a.idz, igt = a.igt, igd = a.igd, ikt = a.ikt, ikd = a.ikd;
     const R D = a.D;
 
-    // per-thread positions: plane points q (S1, S2) and centre points r (S3)
+    // per-thread positions: plane points q (S1, S2, S4, S5) and centre points r (S3)
     int qi[NQ], qj[NQ];
     unsigned qo[NQ];
     bool qok[NQ];
@@ -115,7 +122,7 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
     }
 
     // prefetch registers (step g)
-    R fvx[NQ], fvy[NQ], fvz[NQ], fxz[NQ], fxzo[NQ], fyz[NQ], fyzo[NQ], fxy[NQ], fxyo[NQ];
+    R fvx[NQ], fvy[NQ], fvz[NQ], fxz[NQ], fxzo[NQ], fyz[NQ], fyzo[NQ], fxy[NQ], fxyo[NQ], fig[NQ];
     R fp[NR], fpo[NR], fsx[NR], fsxo[NR], fsy[NR], fsyo[NR], fc[NR];
     auto prefetch = [&](int g) {
         const bool pl = g >= 0 && g < nz, lv = g >= 0 && g <= nz, inner = g >= 1 && g <= nz - 1;
@@ -129,15 +136,22 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
             fvx[u] = (ok && pl && (INT || (i >= 0 && i <= nx && j >= 0 && j < ny))) ? ld(itb + F_VX * fs + pg, o) : R(0);
             fvy[u] = (ok && pl && (INT || (i >= 0 && i < nx && j >= 0 && j <= ny))) ? ld(itb + F_VY * fs + pg, o) : R(0);
             fvz[u] = (ok && lv && (INT || (i >= 0 && i < nx && j >= 0 && j < ny))) ? ld(itb + F_VZ * fs + pg, o) : R(0);
+            // edge stresses of iteration k wherever the edge exists (wall
+            // values enter the residual), increment-start values inside
+            const bool xz_in = INT || (i >= 0 && i <= nx && j >= 0 && j < ny);
+            const bool yz_in = INT || (i >= 0 && i < nx && j >= 0 && j <= ny);
+            const bool xy_in = INT || (i >= 0 && i <= nx && j >= 0 && j <= ny);
+            fxz[u] = (ok && lv && xz_in) ? ld(itb + F_TXZ * fs + pg, o) : R(0);
+            fyz[u] = (ok && lv && yz_in) ? ld(itb + F_TYZ * fs + pg, o) : R(0);
+            fxy[u] = (ok && pm && xy_in) ? ld(itb + F_TXY * fs + pg1, o) : R(0);
             const bool exz = ok && inner && (INT || (i >= 1 && i <= nx - 1 && j >= 0 && j < ny));
             const bool eyz = ok && inner && (INT || (j >= 1 && j <= ny - 1 && i >= 0 && i < nx));
-            fxz[u] = exz ? ld(itb + F_TXZ * fs + pg, o) : R(0);
             fxzo[u] = exz ? ld(olb + O_TXZ * fs + pg, o) : R(0);
-            fyz[u] = eyz ? ld(itb + F_TYZ * fs + pg, o) : R(0);
             fyzo[u] = eyz ? ld(olb + O_TYZ * fs + pg, o) : R(0);
             const bool exy = ok && pm && (INT || (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1));
-            fxy[u] = exy ? ld(itb + F_TXY * fs + pg1, o) : R(0);
             fxyo[u] = exy ? ld(olb + O_TXY * fs + pg1, o) : R(0);
+            if (HG)
+                fig[u] = (ok && pl && (INT || (i >= 0 && i < nx && j >= 0 && j < ny))) ? ld(a.igdc + pg, o) : R(0);
         }
 #pragma unroll
         for (int u = 0; u < NR; ++u) {
@@ -159,9 +173,10 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
     R rmax = R(0), mmax = R(0), vmax = R(0), smax = R(0);
 
     // S1 of step g: the prefetched velocities of plane g (vx, vy) and level
-    // g (vz) go to LDS and into this thread's register history, from which
-    // S5 takes the old velocities of its own points (vx, vy of plane g-2, vz
-    // of level g-1 at step g)
+    // g (vz), and the compliances of plane g, go to LDS and the velocities
+    // into this thread's register history, from which S5 takes the old
+    // velocities of its own points (vx, vy of plane g-2, vz of level g-1 at
+    // step g)
     R hvx1[NQ], hvx2[NQ], hvx3[NQ], hvy1[NQ], hvy2[NQ], hvy3[NQ], hvz1[NQ], hvz2[NQ];
     auto stage_velocities = [&](int g) {
         const bool ld_xy = g >= 0 && g < nz;
@@ -177,6 +192,7 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
             if (ld_xy) {
                 s_vx[s2][q] = fvx[u];
                 s_vy[s2][q] = fvy[u];
+                if (HG) s_ig[s2 & (NG - 1)][q] = fig[u];
             }
             if (ld_z) s_vz[s2][q] = fvz[u];
         }
@@ -186,6 +202,15 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
         hvx1[u] = hvx2[u] = hvx3[u] = R(0);
         hvy1[u] = hvy2[u] = hvy3[u] = R(0);
         hvz1[u] = hvz2[u] = R(0);
+    }
+    // edge stresses of iteration k at the level of the previous step (xz,
+    // yz), and with a per-cell G the edge compliances of this step (xy at
+    // plane f-1; xz, yz at level f) and of the previous step (xz, yz)
+    R pcxz[NQ], pcyz[NQ], gxy[NQ], gxz[NQ], gyz[NQ], pgxz[NQ], pgyz[NQ];
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+        pcxz[u] = pcyz[u] = R(0);
+        gxy[u] = gxz[u] = gyz[u] = pgxz[u] = pgyz[u] = igd;
     }
     prefetch(k0 - 2);
     stage_velocities(k0 - 2);
@@ -199,6 +224,7 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
         for (int u = 0; u < NQ; ++u) {
             cxz[u] = fxz[u]; cxzo[u] = fxzo[u]; cyz[u] = fyz[u]; cyzo[u] = fyzo[u];
             cxy[u] = fxy[u]; cxyo[u] = fxyo[u];
+            if (HG) { pgxz[u] = gxz[u]; pgyz[u] = gyz[u]; }
         }
 #pragma unroll
         for (int u = 0; u < NR; ++u) {
@@ -207,7 +233,7 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
         }
         if (f + 1 <= k1 + 1) prefetch(f + 1);
 
-        // ---- S2: shear trials: xz, yz at level f; xy at plane f-1 ----------
+        // ---- S2: physical shear trials: xz, yz at level f; xy at plane f-1 --
         {
             const bool do_l = f >= k0 - 1 && f >= 0 && f <= nz;
             const bool do_p = f - 1 >= k0 - 1 && f - 1 >= 0 && f - 1 < nz;
@@ -219,25 +245,34 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
                 if (!qok[u] || q % W < 1 || q / W < 1) continue;
                 const int i = qi[u], j = qj[u];
                 if (do_l) {
-                    R txz = R(0), tyz = R(0);
+                    R sxz = R(0), syz = R(0);
+                    if (HG) {       // compliance of an edge: mean of its four cells
+                        const int a0 = sl & (NG - 1), a1 = cp3 & (NG - 1);
+                        gxz[u] = inner_l ? R(0.25) * (s_ig[a1][q - 1] + s_ig[a1][q] + s_ig[a0][q - 1] + s_ig[a0][q]) : igd;
+                        gyz[u] = inner_l ? R(0.25) * (s_ig[a1][q - W] + s_ig[a1][q] + s_ig[a0][q - W] + s_ig[a0][q]) : igd;
+                    }
                     if (inner_l && (INT || (i >= 1 && i <= nx - 1 && j >= 0 && j < ny))) {
                         R e2 = (s_vx[cm][q] - s_vx[cp3][q]) * idz + (s_vz[sl][q] - s_vz[sl][q - 1]) * idx;
-                        txz = cxz[u] * igt + cxzo[u] * igd + e2;
+                        sxz = cxzo[u] * (HG ? gxz[u] : igd) + e2;
                     }
                     if (inner_l && (INT || (j >= 1 && j <= ny - 1 && i >= 0 && i < nx))) {
                         R e2 = (s_vy[cm][q] - s_vy[cp3][q]) * idz + (s_vz[sl][q] - s_vz[sl][q - W]) * idy;
-                        tyz = cyz[u] * igt + cyzo[u] * igd + e2;
+                        syz = cyzo[u] * (HG ? gyz[u] : igd) + e2;
                     }
-                    s_Txz[sl][q] = txz;
-                    s_Tyz[sl][q] = tyz;
+                    s_Sxz[sl][q] = sxz;
+                    s_Syz[sl][q] = syz;
                 }
                 if (do_p) {
                     R t = R(0);
+                    if (HG) {
+                        const int a0 = pm & (NG - 1);
+                        gxy[u] = R(0.25) * (s_ig[a0][q - W - 1] + s_ig[a0][q - W] + s_ig[a0][q - 1] + s_ig[a0][q]);
+                    }
                     if (INT || (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1)) {
                         R e2 = (s_vx[pm][q] - s_vx[pm][q - W]) * idy + (s_vy[pm][q] - s_vy[pm][q - 1]) * idx;
-                        t = cxy[u] * igt + cxyo[u] * igd + e2;
+                        t = cxyo[u] * (HG ? gxy[u] : igd) + e2;
                     }
-                    s_Txy[q] = t;
+                    s_Sxy[q] = t;
                 }
             }
         }
@@ -266,27 +301,35 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
                 R div = dvx + dvy + dvz;
                 const R pk = cp[u], txk = csx[u], tyk = csy[u];
                 R pn = (pk * ikt + cpo[u] * ikd - div) * a.ikk;
-                R Txx = txk * igt + csxo[u] * igd + R(2) * (dvx - div * R(1.0 / 3.0));
-                R Tyy = tyk * igt + csyo[u] * igd + R(2) * (dvy - div * R(1.0 / 3.0));
-                R Tzz = -(Txx + Tyy);
-                R Txyb = R(0.25) * (s_Txy[q] + s_Txy[q + 1] + s_Txy[q + W] + s_Txy[q + W + 1]);
-                R Txzb = R(0.25) * (s_Txz[sc][q] + s_Txz[sc][q + 1] + s_Txz[sc1][q] + s_Txz[sc1][q + 1]);
-                R Tyzb = R(0.25) * (s_Tyz[sc][q] + s_Tyz[sc][q + W] + s_Tyz[sc1][q] + s_Tyz[sc1][q + W]);
-                R J2 = R(0.5) * (Txx * Txx + Tyy * Tyy + Tzz * Tzz) + Txyb * Txyb + Txzb * Txzb + Tyzb * Tyzb;
-                R lam;
+                // per-cell G: the cell's compliance, its physical Dp and its D
+                const R igc = HG ? s_ig[cm & (NG - 1)][q] : igd;
+                const R Dp = HG ? igc + a.imus : a.Dp;
+                const R invDp = HG ? fast_rcp(Dp) : a.invDp;
+                const R Dc = HG ? igt + Dp : D;
+                const R invDc = HG ? fast_rcp(Dc) : a.invD;
+                const R Sxx = csxo[u] * igc + R(2) * (dvx - div * R(1.0 / 3.0));
+                const R Syy = csyo[u] * igc + R(2) * (dvy - div * R(1.0 / 3.0));
+                const R Szz = -(Sxx + Syy);
+                const R Txx = txk * igt + Sxx, Tyy = tyk * igt + Syy, Tzz = -(Txx + Tyy);
+                const R Sxyb = R(0.25) * (s_Sxy[q] + s_Sxy[q + 1] + s_Sxy[q + W] + s_Sxy[q + W + 1]);
+                const R Sxzb = R(0.25) * (s_Sxz[sc][q] + s_Sxz[sc][q + 1] + s_Sxz[sc1][q] + s_Sxz[sc1][q + 1]);
+                const R Syzb = R(0.25) * (s_Syz[sc][q] + s_Syz[sc][q + W] + s_Syz[sc1][q] + s_Syz[sc1][q + W]);
+                const R nS2 = R(0.5) * (Sxx * Sxx + Syy * Syy + Szz * Szz);
+                const R sh2 = Sxyb * Sxyb + Sxzb * Sxzb + Syzb * Syzb;
                 const R ptr = pn;
-                R sc_ = return_scale(J2, D, a.invD, pn, cc[u], a.A, a.B, a.Cik, a.vp, lam);
+                R lam = centre_return(R(0.5) * (Txx * Txx + Tyy * Tyy + Tzz * Tzz), nS2, sh2, Dp, invDp, Dc, invDc,
+                                      pn, cc[u], a.A, a.B, a.Cik, a.vp, a.blend);
                 const bool own = la >= 2 && la < TX + 2 && lbb >= 2 && lbb < TY + 2 && c >= k0 && c < k1;
                 if (a.lam_mode != LAM_COMPUTE) {                 // frozen plasticity
                     if (a.lam_mode == LAM_FROZEN) {
                         lam = ld(a.lam + sz * c, ro[u]);
-                        sc_ = R(1) / (D + lam);
-                        // dilatancy of the held Lambda: lamdot = Lambda sqrt(J2) / (D + Lambda)
-                        if (a.Cik != R(0)) pn = ptr + lam * fast_sqrt(J2) * sc_ * a.Cik;
+                        // dilatancy of the held Lambda: lamdot = Lambda sqrt(J2(S)) / (Dp + Lambda)
+                        if (a.Cik != R(0)) pn = ptr + lam * fast_sqrt(nS2 + sh2) * fast_rcp(Dp + lam) * a.Cik;
                     } else if (own) {
                         st(a.lam + sz * c, ro[u], lam);
                     }
                 }
+                const R sc_ = fast_rcp(Dc + lam);
                 R txx = Txx * sc_, tyy = Tyy * sc_;
                 s_lam[sc][q] = lam;
                 s_p[sc][q] = pn;
@@ -307,52 +350,49 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
             }
         }
         __syncthreads();
-        // ---- S4: new edge stresses: xy at plane f-1, xz / yz at level f-1 ---
+        // ---- S4: new edge stresses: xy at plane f-1, xz / yz at level f-1,
+        //      at this thread's own edge points: T = tau_k/(G~ dtau) + S ------
         {
-            const int p = f - 1;
-            if (p >= k0 && p < k1) {
-                const int sp = mod2(p);
-                constexpr int EW = TX + 1, EN = (TX + 1) * (TY + 1);
-                for (int r = tid; r < EN; r += NT) {
-                    const int la = 2 + r % EW, lbb = 2 + r / EW;
-                    const int q = la + W * lbb;
-                    const int i = i0 - 2 + la, j = j0 - 2 + lbb;
+            const int p = f - 1, l = f - 1;
+            const bool do_p = p >= k0 && p < k1;
+            const bool do_l = l >= k0 && l <= k1 && l >= 0 && l <= nz;
+            const int sp = mod2(p), sl = mod2(l), sm = mod2(l - 1);
+            const bool inner_l = l >= 1 && l <= nz - 1;
+            const bool own_l = l < k1 || (l == nz && last_z);
+#pragma unroll
+            for (int u = 0; u < NQ; ++u) {
+                const int q = tid + NT * u;
+                const int la = q % W, lbb = q / W;
+                if (!qok[u] || la < 2 || la > TX + 2 || lbb < 2 || lbb > TY + 2) continue;
+                const int i = qi[u], j = qj[u];
+                const unsigned o = qo[u];
+                if (do_p) {
                     R t = R(0);
                     if (INT || (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1)) {
                         R lv = R(0.25) * (s_lam[sp][q - W - 1] + s_lam[sp][q - W] + s_lam[sp][q - 1] + s_lam[sp][q]);
-                        t = s_Txy[q] * fast_rcp(D + lv);
+                        const R De = HG ? igt + gxy[u] + a.imus : D;
+                        t = (cxy[u] * igt + s_Sxy[q]) * fast_rcp(De + lv);
                     }
                     s_nxy[sp][q] = t;
                     if (la < TX + 2 + hx && lbb < TY + 2 + hy && (INT || (i <= nx && j <= ny))) {
-                        const unsigned o = off(i, j);
                         st(nxb + F_TXY * fs + sz * p, o, t);
-                        if (MODE == MODE_CHECK) rmax = nmax(rmax, fabs(t - ld(itb + F_TXY * fs + sz * p, o)) * a.rG);
+                        if (MODE == MODE_CHECK) rmax = nmax(rmax, fabs(t - cxy[u]) * a.rG);
                     }
                 }
-            }
-            const int l = f - 1;
-            if (l >= k0 && l <= k1 && l >= 0 && l <= nz) {
-                const int sl = mod2(l), sm = mod2(l - 1);
-                const bool inner_l = l >= 1 && l <= nz - 1;
-                const bool own_l = l < k1 || (l == nz && last_z);
-                constexpr int EW = TX + 1, EN = (TX + 1) * (TY + 1);
-                for (int r = tid; r < EN; r += NT) {
-                    const int la = 2 + r % EW, lbb = 2 + r / EW;
-                    const int q = la + W * lbb;
-                    const int i = i0 - 2 + la, j = j0 - 2 + lbb;
-                    const unsigned o = off(i, j);
+                if (do_l) {
                     const long pl = sz * l;
                     // xz edge (i, j) at level l: x-extent nx+1, y-extent ny
                     if (lbb < TY + 2) {
                         R t = R(0);
                         if (inner_l && (INT || (i >= 1 && i <= nx - 1 && j < ny))) {
                             R lv = R(0.25) * (s_lam[sm][q - 1] + s_lam[sm][q] + s_lam[sl][q - 1] + s_lam[sl][q]);
-                            t = s_Txz[sl][q] * fast_rcp(D + lv);
+                            const R De = HG ? igt + pgxz[u] + a.imus : D;
+                            t = (pcxz[u] * igt + s_Sxz[sl][q]) * fast_rcp(De + lv);
                         }
                         s_nxz[sl][q] = t;
                         if (own_l && la < TX + 2 + hx && (INT || (i <= nx && j < ny))) {
                             st(nxb + F_TXZ * fs + pl, o, t);
-                            if (MODE == MODE_CHECK) rmax = nmax(rmax, fabs(t - ld(itb + F_TXZ * fs + pl, o)) * a.rG);
+                            if (MODE == MODE_CHECK) rmax = nmax(rmax, fabs(t - pcxz[u]) * a.rG);
                         }
                     }
                     // yz edge (i, j) at level l: x-extent nx, y-extent ny+1
@@ -360,16 +400,22 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
                         R t = R(0);
                         if (inner_l && (INT || (j >= 1 && j <= ny - 1 && i < nx))) {
                             R lv = R(0.25) * (s_lam[sm][q - W] + s_lam[sm][q] + s_lam[sl][q - W] + s_lam[sl][q]);
-                            t = s_Tyz[sl][q] * fast_rcp(D + lv);
+                            const R De = HG ? igt + pgyz[u] + a.imus : D;
+                            t = (pcyz[u] * igt + s_Syz[sl][q]) * fast_rcp(De + lv);
                         }
                         s_nyz[sl][q] = t;
                         if (own_l && lbb < TY + 2 + hy && (INT || (i < nx && j <= ny))) {
                             st(nxb + F_TYZ * fs + pl, o, t);
-                            if (MODE == MODE_CHECK) rmax = nmax(rmax, fabs(t - ld(itb + F_TYZ * fs + pl, o)) * a.rG);
+                            if (MODE == MODE_CHECK) rmax = nmax(rmax, fabs(t - pcyz[u]) * a.rG);
                         }
                     }
                 }
             }
+        }
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {      // this step's level becomes the previous one
+            pcxz[u] = cxz[u];
+            pcyz[u] = cyz[u];
         }
         __syncthreads();
         // ---- S5: velocities: vx, vy at plane f-2, vz at level f-1, at this
@@ -471,7 +517,9 @@ void run_3d(const SweepArgs<R>& a, hipStream_t s)
     ts.nbz = (a.nz + ZC - 1) / ZC;
     interior_range(a.nx, TX, ts.nbx, ts.bx0, ts.bx1);
     interior_range(a.ny, TY, ts.nby, ts.by0, ts.by1);
-    k_fused_3d<R, TX, TY, ZC, MODE, NT, WPE><<<ts.nbx * ts.nby * ts.nbz, NT, 0, s>>>(a, ts);
+    const int nb = ts.nbx * ts.nby * ts.nbz;
+    if (a.igdc) k_fused_3d<R, TX, TY, ZC, MODE, NT, WPE, true><<<nb, NT, 0, s>>>(a, ts);
+    else k_fused_3d<R, TX, TY, ZC, MODE, NT, WPE, false><<<nb, NT, 0, s>>>(a, ts);
 }
 
 

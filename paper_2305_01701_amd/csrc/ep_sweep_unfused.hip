@@ -6,8 +6,9 @@
 //
 // One iteration (paper: accelerated pseudo-transient method; return mapping):
 //   centres   div v, p^{k+1} = (p^k/K~dtau + p^/(K dt) - div)/(1/K~dtau + 1/(K dt)),
-//             T = tau^k/G~dtau + tau^/(G dt) + 2 e'(v), J2 with the 4-point mean
-//             of the shear trials, Lambda from the radial return, tau = T/(D+Lambda)
+//             S = tau^/(G dt) + 2 e'(v), T = tau^k/G~dtau + S, Lambda from the
+//             return of centre_return (physical trial S with the 4-point means of
+//             the shear-point S, blended with the pseudo-time trial), tau = T/(D+Lambda)
 //   shear     T at vertices (2D) / edges (3D), Lambda = mean of the 4 adjacent
 //             centres, tau = T/(D+Lambda); zero on the walls (free slip)
 //   faces     R = div(tau - p I), v^{k+1} = v^k + dtau/rho~ R; wall faces keep
@@ -20,15 +21,23 @@ namespace {
 
 constexpr int BX = 64, BY = 4, NT = BX * BY;
 
+// Physical shear trial S = tau^/(G dt) + 2 e at the vertex e (zero on walls).
 template <typename R>
-__device__ __forceinline__ R vertex_T2(const SweepArgs<R>& a, long e, int i, int j)
+__device__ __forceinline__ R vertex_S2(const SweepArgs<R>& a, long e, int i, int j)
 {
     if (i <= 0 || i >= a.nx || j <= 0 || j >= a.ny) return R(0);
     const R* vx = a.it[F_VX];
     const R* vy = a.it[F_VY];
     R e2 = (vx[e] - vx[e - a.sy]) * a.idy + (vy[e] - vy[e - 1]) * a.idx;
     const R ig = a.igdc ? vertex_compliance(a.igdc, e, (long)a.sy) : a.igd;
-    return a.it[F_TXY][e] * a.igt + a.old[O_TXY][e] * ig + e2;
+    return a.old[O_TXY][e] * ig + e2;
+}
+// Pseudo-time trial T = tau^k/(G~ dtau) + S.
+template <typename R>
+__device__ __forceinline__ R vertex_T2(const SweepArgs<R>& a, long e, int i, int j)
+{
+    if (i <= 0 || i >= a.nx || j <= 0 || j >= a.ny) return R(0);
+    return a.it[F_TXY][e] * a.igt + vertex_S2(a, e, i, j);
 }
 
 // ------------------------------------------------------------------ 2D
@@ -47,19 +56,22 @@ __global__ __launch_bounds__(NT) void k_centre_2d(SweepArgs<R> a)
         R dvy = (vy[c + a.sy] - vy[c]) * a.idy + a.eby;
         R div = dvx + dvy;
         R pn = (a.it[F_P][c] * a.ikt + a.old[O_P][c] * a.ikd - div) / (a.ikt + a.ikd);
-        const R igc = a.igdc ? a.igdc[c] : a.igd;        // per-cell G: the cell's compliance and D
-        const R Dc = a.igdc ? a.igt + igc + a.imus : a.D;
-        R Txx = a.it[F_TXX][c] * a.igt + a.old[O_TXX][c] * igc + R(2) * (dvx - div / R(3));
-        R Tyy = a.it[F_TYY][c] * a.igt + a.old[O_TYY][c] * igc + R(2) * (dvy - div / R(3));
-        R Tb = R(0.25) * (vertex_T2(a, c, i, j) + vertex_T2(a, c + 1, i + 1, j)
-                        + vertex_T2(a, c + a.sy, i, j + 1) + vertex_T2(a, c + a.sy + 1, i + 1, j + 1));
-        R J2 = R(0.5) * (Txx * Txx + Tyy * Tyy) + Tb * Tb;
-        R ld, tii, Y;
+        const R igc = a.igdc ? a.igdc[c] : a.igd;        // per-cell G: the cell's compliance, Dp and D
+        const R Dp = a.igdc ? igc + a.imus : a.Dp;
+        const R Dc = a.igdc ? a.igt + Dp : a.D;
+        const R Sxx = a.old[O_TXX][c] * igc + R(2) * (dvx - div / R(3));
+        const R Syy = a.old[O_TYY][c] * igc + R(2) * (dvy - div / R(3));
+        const R Txx = a.it[F_TXX][c] * a.igt + Sxx;
+        const R Tyy = a.it[F_TYY][c] * a.igt + Syy;
+        const R Sb = R(0.25) * (vertex_S2(a, c, i, j) + vertex_S2(a, c + 1, i + 1, j)
+                              + vertex_S2(a, c + a.sy, i, j + 1) + vertex_S2(a, c + a.sy + 1, i + 1, j + 1));
+        const R nS2 = R(0.5) * (Sxx * Sxx + Syy * Syy), sh2 = Sb * Sb;
         const R ptr = pn;
-        R lam = centre_lambda(J2, Dc, pn, a.coh[c], a.A, a.B, a.Cik, a.vp, ld, tii, Y);
+        R lam = centre_return(R(0.5) * (Txx * Txx + Tyy * Tyy), nS2, sh2, Dp, R(1) / Dp, Dc, R(1) / Dc, pn, a.coh[c],
+                              a.A, a.B, a.Cik, a.vp, a.blend);
         if (a.lam_mode == LAM_FROZEN) {                  // frozen plasticity: Lambda held fixed
             lam = a.lam[c];
-            if (a.Cik != R(0)) pn = ptr + lam * sqrt(J2) / (Dc + lam) * a.Cik;   // its dilatancy
+            if (a.Cik != R(0)) pn = ptr + lam * sqrt(nS2 + sh2) / (Dp + lam) * a.Cik;   // its dilatancy
         } else {
             a.lam[c] = lam;                              // read by the shear-point kernel
         }
@@ -144,30 +156,49 @@ __global__ __launch_bounds__(NT) void k_velocity_2d(SweepArgs<R> a)
 }
 
 // ------------------------------------------------------------------ 3D
-// Shear trials at the three edge families, zero on walls.
+// Physical shear trials S = tau^/(G dt) + 2 e at the three edge families,
+// zero on walls; the pseudo-time trials T = tau^k/(G~ dtau) + S.
 template <typename R>
-__device__ __forceinline__ R T_xy(const SweepArgs<R>& a, long e, int i, int j)
+__device__ __forceinline__ R S_xy(const SweepArgs<R>& a, long e, int i, int j)
 {
     if (i <= 0 || i >= a.nx || j <= 0 || j >= a.ny) return R(0);
     R e2 = (a.it[F_VX][e] - a.it[F_VX][e - a.sy]) * a.idy + (a.it[F_VY][e] - a.it[F_VY][e - 1]) * a.idx;
     const R ig = a.igdc ? edge_compliance(a.igdc, e, 1L, (long)a.sy) : a.igd;
-    return a.it[F_TXY][e] * a.igt + a.old[O_TXY][e] * ig + e2;
+    return a.old[O_TXY][e] * ig + e2;
+}
+template <typename R>
+__device__ __forceinline__ R S_xz(const SweepArgs<R>& a, long e, int i, int k)
+{
+    if (i <= 0 || i >= a.nx || k <= 0 || k >= a.nz) return R(0);
+    R e2 = (a.it[F_VX][e] - a.it[F_VX][e - a.sz]) * a.idz + (a.it[F_VZ][e] - a.it[F_VZ][e - 1]) * a.idx;
+    const R ig = a.igdc ? edge_compliance(a.igdc, e, 1L, a.sz) : a.igd;
+    return a.old[O_TXZ][e] * ig + e2;
+}
+template <typename R>
+__device__ __forceinline__ R S_yz(const SweepArgs<R>& a, long e, int j, int k)
+{
+    if (j <= 0 || j >= a.ny || k <= 0 || k >= a.nz) return R(0);
+    R e2 = (a.it[F_VY][e] - a.it[F_VY][e - a.sz]) * a.idz + (a.it[F_VZ][e] - a.it[F_VZ][e - a.sy]) * a.idy;
+    const R ig = a.igdc ? edge_compliance(a.igdc, e, (long)a.sy, a.sz) : a.igd;
+    return a.old[O_TYZ][e] * ig + e2;
+}
+template <typename R>
+__device__ __forceinline__ R T_xy(const SweepArgs<R>& a, long e, int i, int j)
+{
+    if (i <= 0 || i >= a.nx || j <= 0 || j >= a.ny) return R(0);
+    return a.it[F_TXY][e] * a.igt + S_xy(a, e, i, j);
 }
 template <typename R>
 __device__ __forceinline__ R T_xz(const SweepArgs<R>& a, long e, int i, int k)
 {
     if (i <= 0 || i >= a.nx || k <= 0 || k >= a.nz) return R(0);
-    R e2 = (a.it[F_VX][e] - a.it[F_VX][e - a.sz]) * a.idz + (a.it[F_VZ][e] - a.it[F_VZ][e - 1]) * a.idx;
-    const R ig = a.igdc ? edge_compliance(a.igdc, e, 1L, a.sz) : a.igd;
-    return a.it[F_TXZ][e] * a.igt + a.old[O_TXZ][e] * ig + e2;
+    return a.it[F_TXZ][e] * a.igt + S_xz(a, e, i, k);
 }
 template <typename R>
 __device__ __forceinline__ R T_yz(const SweepArgs<R>& a, long e, int j, int k)
 {
     if (j <= 0 || j >= a.ny || k <= 0 || k >= a.nz) return R(0);
-    R e2 = (a.it[F_VY][e] - a.it[F_VY][e - a.sz]) * a.idz + (a.it[F_VZ][e] - a.it[F_VZ][e - a.sy]) * a.idy;
-    const R ig = a.igdc ? edge_compliance(a.igdc, e, (long)a.sy, a.sz) : a.igd;
-    return a.it[F_TYZ][e] * a.igt + a.old[O_TYZ][e] * ig + e2;
+    return a.it[F_TYZ][e] * a.igt + S_yz(a, e, j, k);
 }
 
 template <typename R, int MODE>
@@ -186,24 +217,28 @@ __global__ __launch_bounds__(NT) void k_centre_3d(SweepArgs<R> a)
         R dvz = (a.it[F_VZ][c + sz] - a.it[F_VZ][c]) * a.idz + a.ebz;
         R div = dvx + dvy + dvz;
         R pn = (a.it[F_P][c] * a.ikt + a.old[O_P][c] * a.ikd - div) / (a.ikt + a.ikd);
-        const R igc = a.igdc ? a.igdc[c] : a.igd;        // per-cell G: the cell's compliance and D
-        const R Dc = a.igdc ? a.igt + igc + a.imus : a.D;
-        R Txx = a.it[F_TXX][c] * a.igt + a.old[O_TXX][c] * igc + R(2) * (dvx - div / R(3));
-        R Tyy = a.it[F_TYY][c] * a.igt + a.old[O_TYY][c] * igc + R(2) * (dvy - div / R(3));
-        R Tzz = -(Txx + Tyy);
-        R Txy = R(0.25) * (T_xy(a, c, i, j) + T_xy(a, c + 1, i + 1, j) + T_xy(a, c + sy, i, j + 1)
-                         + T_xy(a, c + sy + 1, i + 1, j + 1));
-        R Txz = R(0.25) * (T_xz(a, c, i, k) + T_xz(a, c + 1, i + 1, k) + T_xz(a, c + sz, i, k + 1)
-                         + T_xz(a, c + sz + 1, i + 1, k + 1));
-        R Tyz = R(0.25) * (T_yz(a, c, j, k) + T_yz(a, c + sy, j + 1, k) + T_yz(a, c + sz, j, k + 1)
-                         + T_yz(a, c + sy + sz, j + 1, k + 1));
-        R J2 = R(0.5) * (Txx * Txx + Tyy * Tyy + Tzz * Tzz) + Txy * Txy + Txz * Txz + Tyz * Tyz;
-        R ld, tii, Y;
+        const R igc = a.igdc ? a.igdc[c] : a.igd;        // per-cell G: the cell's compliance, Dp and D
+        const R Dp = a.igdc ? igc + a.imus : a.Dp;
+        const R Dc = a.igdc ? a.igt + Dp : a.D;
+        const R Sxx = a.old[O_TXX][c] * igc + R(2) * (dvx - div / R(3));
+        const R Syy = a.old[O_TYY][c] * igc + R(2) * (dvy - div / R(3));
+        const R Szz = -(Sxx + Syy);
+        const R Txx = a.it[F_TXX][c] * a.igt + Sxx;
+        const R Tyy = a.it[F_TYY][c] * a.igt + Syy;
+        const R Tzz = -(Txx + Tyy);
+        const R Sxy = R(0.25) * (S_xy(a, c, i, j) + S_xy(a, c + 1, i + 1, j) + S_xy(a, c + sy, i, j + 1)
+                               + S_xy(a, c + sy + 1, i + 1, j + 1));
+        const R Sxz = R(0.25) * (S_xz(a, c, i, k) + S_xz(a, c + 1, i + 1, k) + S_xz(a, c + sz, i, k + 1)
+                               + S_xz(a, c + sz + 1, i + 1, k + 1));
+        const R Syz = R(0.25) * (S_yz(a, c, j, k) + S_yz(a, c + sy, j + 1, k) + S_yz(a, c + sz, j, k + 1)
+                               + S_yz(a, c + sy + sz, j + 1, k + 1));
+        const R nS2 = R(0.5) * (Sxx * Sxx + Syy * Syy + Szz * Szz), sh2 = Sxy * Sxy + Sxz * Sxz + Syz * Syz;
         const R ptr = pn;
-        R lam = centre_lambda(J2, Dc, pn, a.coh[c], a.A, a.B, a.Cik, a.vp, ld, tii, Y);
+        R lam = centre_return(R(0.5) * (Txx * Txx + Tyy * Tyy + Tzz * Tzz), nS2, sh2, Dp, R(1) / Dp, Dc, R(1) / Dc,
+                              pn, a.coh[c], a.A, a.B, a.Cik, a.vp, a.blend);
         if (a.lam_mode == LAM_FROZEN) {                  // frozen plasticity: Lambda held fixed
             lam = a.lam[c];
-            if (a.Cik != R(0)) pn = ptr + lam * sqrt(J2) / (Dc + lam) * a.Cik;   // its dilatancy
+            if (a.Cik != R(0)) pn = ptr + lam * sqrt(nS2 + sh2) / (Dp + lam) * a.Cik;   // its dilatancy
         } else {
             a.lam[c] = lam;                              // read by the shear-point kernel
         }

@@ -4,8 +4,9 @@
 // The workgroup loads velocities, shear stresses (iteration k and increment
 // start) over a 2-point halo and the centre data over a 1-point halo, all
 // global loads issued before the first stage; then in LDS: shear trials at
-// vertices, centre update (pressure, deviatoric trial, return mapping),
-// vertex stresses from the averaged centre Lambda, velocities.  Halo points
+// vertices (the physical trial S and the pseudo-time trial T), centre update
+// (pressure, deviatoric trial, return mapping of centre_return), vertex
+// stresses from the averaged centre Lambda, velocities.  Halo points
 // are recomputed, so tiles are independent within a sweep.  A caller that
 // runs several tiles in one workgroup must put a barrier between them (the
 // last stage reads LDS that the next tile's first stage overwrites).
@@ -31,7 +32,7 @@ __device__ __forceinline__ void sweep_tile_2d(const SweepArgs<R>& a, int bx, int
     // caller (single-model or batched kernel) rounds each point identically
 #pragma clang fp contract(on)
     constexpr int W = TX + 4, H = TY + 4, N = W * H;
-    __shared__ R s_vx[N], s_vy[N], s_Txy[N], s_lam[N], s_p[N], s_sxx[N], s_syy[N], s_nxy[N];
+    __shared__ R s_vx[N], s_vy[N], s_Txy[N], s_Sxy[N], s_lam[N], s_p[N], s_sxx[N], s_syy[N], s_nxy[N];
     __shared__ double s_red[NT / 64 > 0 ? NT / 64 : 1];
 
     const int i0 = bx * TX, j0 = by * TY;
@@ -91,13 +92,15 @@ __device__ __forceinline__ void sweep_tile_2d(const SweepArgs<R>& a, int bx, int
         const int la = q % W, lbb = q / W;
         if (la < 1 || lbb < 1) continue;
         const int i = i0 - 2 + la, j = j0 - 2 + lbb;
-        R t = R(0);
+        R t = R(0), sv = R(0);
         if (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1) {
             R e2 = (s_vx[q] - s_vx[q - W]) * idy + (s_vy[q] - s_vy[q - 1]) * idx;
             const R ig = a.igdc ? vertex_compliance(a.igdc, i + sy * j, sy) : igd;
-            t = gxy[u] * igt + gxyo[u] * ig + e2;
+            sv = gxyo[u] * ig + e2;
+            t = gxy[u] * igt + sv;
         }
         s_Txy[q] = t;
+        s_Sxy[q] = sv;
     }
     __syncthreads();
     {
@@ -121,26 +124,29 @@ __device__ __forceinline__ void sweep_tile_2d(const SweepArgs<R>& a, int bx, int
             R div = dvx + dvy;
             const R pk = gp[u], txk = gsx[u], tyk = gsy[u];
             R pn = (pk * ikt + gpo[u] * ikd - div) * a.ikk;
-            // per-cell G: the cell's compliance and its D
+            // per-cell G: the cell's compliance, its physical Dp and its D
             const R igc = a.igdc ? a.igdc[e] : igd;
-            const R Dc = a.igdc ? igt + igc + a.imus : D;
+            const R Dp = a.igdc ? igc + a.imus : a.Dp;
+            const R invDp = a.igdc ? R(1) / Dp : a.invDp;
+            const R Dc = a.igdc ? igt + Dp : D;
             const R invDc = a.igdc ? R(1) / Dc : a.invD;
-            R Txx = txk * igt + gsxo[u] * igc + R(2) * (dvx - div / R(3));
-            R Tyy = tyk * igt + gsyo[u] * igc + R(2) * (dvy - div / R(3));
-            R Tb = R(0.25) * (s_Txy[q] + s_Txy[q + 1] + s_Txy[q + W] + s_Txy[q + W + 1]);
-            R J2 = R(0.5) * (Txx * Txx + Tyy * Tyy) + Tb * Tb;
-            R lam;
+            const R Sxx = gsxo[u] * igc + R(2) * (dvx - div / R(3));
+            const R Syy = gsyo[u] * igc + R(2) * (dvy - div / R(3));
+            const R Txx = txk * igt + Sxx, Tyy = tyk * igt + Syy;
+            const R Sb = R(0.25) * (s_Sxy[q] + s_Sxy[q + 1] + s_Sxy[q + W] + s_Sxy[q + W + 1]);
+            const R nS2 = R(0.5) * (Sxx * Sxx + Syy * Syy), sh2 = Sb * Sb;
             const R ptr = pn;
-            R sc_ = return_scale(J2, Dc, invDc, pn, gc[u], a.A, a.B, a.Cik, a.vp, lam);
+            R lam = centre_return(R(0.5) * (Txx * Txx + Tyy * Tyy), nS2, sh2, Dp, invDp, Dc, invDc, pn, gc[u], a.A,
+                                  a.B, a.Cik, a.vp, a.blend);
             const bool own = la >= 2 && la < TX + 2 && lbb >= 2 && lbb < TY + 2;
             if (a.lam_mode == LAM_FROZEN) {
                 lam = a.lam[e];
-                sc_ = R(1) / (Dc + lam);
-                // dilatancy of the held Lambda: lamdot = Lambda sqrt(J2) / (D + Lambda)
-                if (a.Cik != R(0)) pn = ptr + lam * fast_sqrt(J2) * sc_ * a.Cik;
+                // dilatancy of the held Lambda: lamdot = Lambda sqrt(J2(S)) / (Dp + Lambda)
+                if (a.Cik != R(0)) pn = ptr + lam * fast_sqrt(nS2 + sh2) * fast_rcp(Dp + lam) * a.Cik;
             } else if (a.lam_mode == LAM_STORE && own) {
                 a.lam[e] = lam;
             }
+            const R sc_ = fast_rcp(Dc + lam);
             R txx = Txx * sc_, tyy = Tyy * sc_;
             s_lam[q] = lam;
             s_p[q] = pn;

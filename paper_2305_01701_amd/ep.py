@@ -54,7 +54,8 @@ class ep_params(C.Structure):
         ("re", C.c_double), ("r", C.c_double), ("cfl", C.c_double),
         ("precision", C.c_int), ("sweep", C.c_int), ("fp32_switch", C.c_double),
         ("fp32_stall", C.c_int), ("freeze_iter", C.c_int), ("guess_accept", C.c_double),
-        ("objective", C.c_int), ("eta_vp", C.c_double),
+        ("objective", C.c_int), ("eta_vp", C.c_double), ("pt_blend", C.c_double),
+        ("pt_blend_late", C.c_double),
     ]
 
 
@@ -65,7 +66,7 @@ class ep_step_stats(C.Structure):
         ("sxx_centre", C.c_double), ("sxx_left", C.c_double), ("sxx_right", C.c_double),
         ("n_yield", C.c_longlong), ("max_violation", C.c_double), ("seconds", C.c_double),
         ("fp32_exit", C.c_double), ("frozen_at", C.c_int), ("guess_used", C.c_int),
-        ("r_guess", C.c_double),
+        ("r_guess", C.c_double), ("cert", C.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -79,7 +80,7 @@ class ep_net_config(C.Structure):
 
 class ep_residual_info(C.Structure):
     _fields_ = [("resid", C.c_double), ("momentum", C.c_double), ("physical", C.c_double),
-                ("vmax", C.c_double)]
+                ("vmax", C.c_double), ("continuity", C.c_double), ("eps_rel", C.c_double)]
 
 
 _lib = None
@@ -291,6 +292,8 @@ def params_from_model(m, precision: int = EP_FP64, sweep: int = EP_SWEEP_AUTO,
     p.guess_accept = guess_accept
     p.objective = getattr(m, "objective", 0)
     p.eta_vp = getattr(m, "eta_vp", 0.0)
+    p.pt_blend = getattr(m, "pt_blend", 0.25)
+    p.pt_blend_late = getattr(m, "pt_blend_late", 0.75)
     return p
 
 

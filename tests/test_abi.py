@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol(E):
 
 
 def test_abi_version(E):
-    assert E.ep_abi_version() == 1
+    assert E.ep_abi_version() == 2
 
 
 def test_workspace_size_scales_with_grid_and_precision(E):
@@ -56,7 +56,7 @@ def test_workspace_size_scales_with_grid_and_precision(E):
 @pytest.mark.parametrize("change", [
     dict(psi_deg=-1.0), dict(psi_deg=35.0), dict(nx=2), dict(bulk=0.0), dict(shear=-1.0), dict(dt=0.0), dict(tol=0.0),
     dict(cfl=0.75), dict(ndim=4), dict(max_iter=0), dict(visc=0.0), dict(freeze_iter=-1), dict(objective=2),
-    dict(eta_vp=-1e-3), dict(eta_vp=float("inf")), dict(eta_vp=float("nan")),
+    dict(eta_vp=-1e-3), dict(eta_vp=float("inf")), dict(eta_vp=float("nan")), dict(pt_blend=-0.1), dict(pt_blend=1.5),
 ])
 def test_invalid_parameters_rejected(E, change):
     m = c1_small_2d().with_(**change)

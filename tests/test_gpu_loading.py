@@ -16,7 +16,11 @@ FP64, FP32 = 0, 1
 @pytest.mark.parametrize("prec", [FP64, FP32], ids=["fp64", "fp32"])
 @pytest.mark.parametrize("ndim", [2, 3])
 def test_trajectory_with_rate_schedule(prec, ndim):
-    m = (c1_small_2d().with_(n_check=10, incl_centre=(0.05, 0.03, -0.02)) if ndim == 2 else
+    # 2D: the matrix localises in the 8th increment, where the perfectly plastic
+    # increment has a near-flat set of solutions (the iteration drifts on a
+    # residual plateau of 2e-5 of the reference); frozen plasticity after
+    # 16 nx iterations (the accelerated-PT section's remedy) makes it linear
+    m = (c1_small_2d().with_(n_check=10, incl_centre=(0.05, 0.03, -0.02), freeze_iter=16 * 63) if ndim == 2 else
          Model(ndim=3, nx=17, ny=15, nz=13, dt=2e-4, tol=1e-8, n_check=10, incl_radius=0.25,
                incl_centre=(0.04, -0.03, 0.02), steps=5))
     say("rate schedule, ndim", ndim, "prec", prec)

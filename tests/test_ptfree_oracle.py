@@ -72,7 +72,7 @@ def test_accepted_states_solve_the_ptfree_equations(case):
         inc, v = _increment(o, m, G)
         r = inc.residual_max(v)
         assert r <= m.tol * st["ref"] * (1 + 1e-9), (r, st)
-        assert abs(r - st["cert"]) <= 1e-6 * st["cert"] + 1e-300
+        assert abs(r - st["cert"]) <= 1e-6 * st["cert"] + 1e-3 * m.tol * st["ref"]
         s = inc.stresses(v)
         scale = max(np.abs(o.get(k)).max() for k in ("txx", "tyy"))
         for k in STRESS:
@@ -178,7 +178,7 @@ def test_fixed_point_independent_of_the_iteration_blend():
     start = {k: a.get(k) for k in keep}
     out = {}
     for blend in (0.0, 0.25, 0.6):
-        o = Oracle(_c1_hetero(pt_blend=blend))
+        o = Oracle(_c1_hetero(pt_blend=blend, pt_blend_late=blend))
         for k in keep:
             o.set(k, start[k])
         st = o.load_step()

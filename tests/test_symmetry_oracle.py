@@ -36,7 +36,12 @@ def run(m, sign):
 
 
 def test_branches_are_mirror_images():
-    m = e2_symmetry(7, nx=95, ny=47, tol=1e-10)
+    # constant blend of the iteration's return: with the late blend the
+    # bifurcating increment maps the +-perturbation to the branches
+    # non-monotonically in its size (measured), so that a rounding-level
+    # perturbation no longer decides the branch; the pin is about the
+    # equations' mirror equivariance, which the blend does not touch
+    m = e2_symmetry(7, nx=95, ny=47, tol=1e-10).with_(pt_blend_late=0.25)
     sa, ea, va = run(m, +1.0)
     sb, eb, vb = run(m, -1.0)
     assert all(s["status"] == 0 for s in sa + sb)
