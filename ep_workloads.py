@@ -165,8 +165,10 @@ def c2_2d(seed: int = 0, visc: float = math.inf) -> Model:
 
 
 def c3_3d(n: int = 255, bulk: float = 2.0) -> Model:
+    # more than 10^6 cells: frozen plasticity after 16 nx iterations (the
+    # accelerated-PT section applies it to every run of that size)
     return Model(ndim=3, nx=n, ny=n, nz=n, dt=5e-5, tol=1e-6, steps=40, bulk=bulk,
-                 name=f"3d-{n}^3-K{bulk:g}")
+                 freeze_iter=16 * n if n ** 3 > 10 ** 6 else 0, name=f"3d-{n}^3-K{bulk:g}")
 
 
 def c5_3d() -> Model:

@@ -266,9 +266,9 @@ int ep_set_strain_rate(ep_handle* h, const double erate[3]);
  * caller keeps ownership.  A cell's physical compliance 1/(G dt) replaces the
  * uniform one in its stress update; a vertex (2D) or edge (3D) takes the mean
  * compliance of its four cells; the pseudo-time steps and the residual scales
- * stay those of ep_params.shear (which therefore bounds every G).  In 3D the
- * model's sweeps then run the unfused kernels (the fused kernel takes a
- * uniform G).  Applies from the next sweep on; may be called again.
+ * stay those of ep_params.shear (which therefore bounds every G).  The fused
+ * 3D sweep reads the compliance of every cell once per sweep (one more field
+ * access per cell).  Applies from the next sweep on; may be called again.
  * EP_EINVAL for a batch model, a NULL array or a value out of range (nothing
  * is changed then). */
 int ep_set_shear_modulus(ep_handle* h, const double* shear);

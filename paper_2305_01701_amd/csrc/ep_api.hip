@@ -300,8 +300,7 @@ void launch_sweep(const ep_handle* h, bool physical, int from, int mode, int lam
     if (h->ndim == 2) {
         launch_sweep_unfused_2d<R>(a, mode, h->st);
     } else {
-        // the fused 3D kernel has no per-cell shear modulus: such models run the unfused kernels
-        if (fused && a.fs > 0 && !a.igdc) launch_sweep_fused_3d<R>(a, mode, h->st);
+        if (fused && a.fs > 0) launch_sweep_fused_3d<R>(a, mode, h->st);
         else launch_sweep_unfused_3d<R>(a, mode, h->st);
     }
 }
