@@ -239,6 +239,21 @@ int ep_sweep(ep_handle* h, int n, double* resid);
 /* FP64 norms of the current state (no state change).  Synchronous. */
 int ep_residual(ep_handle* h, ep_residual_info* r);
 
+/* Allocation-free variant of ep_residual, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same norms as ep_residual, computed by the same
+ * kernels; the reduction counters, the two sweep-argument tables and (2D
+ * models) the tile list are staged in a static device array of the library
+ * (64 KiB per GPU, held until the process ends) instead of the handle's
+ * workspace.  Calls no hipMalloc, hipFree or allocating routine; like
+ * ep_residual it writes the handle's second iteration buffer (the state is
+ * unchanged).  EP_EINVAL (message in ep_last_error) for a 2D model whose tile
+ * list exceeds the array (more than 8,000 tiles of 64 x 16 cells).  The
+ * array is shared by every call on the same GPU: calls that overlap on one
+ * GPU (other streams or threads) race and must be serialised by the caller.
+ * Synchronous. */
+int ep_residual_noalloc(ep_handle* h, ep_residual_info* r);
+
 /* Objective stress update of the current state with its current velocities,
  * in place (paper: Jaumann rate of stress, equations j1-j14, and the
  * appendix on the objective stress terms; the discretisation of the

@@ -897,6 +897,38 @@ void handle_free(ep_handle* h)
     delete h;
 }
 
+// ---- allocation-free residual: the static device scratch ------------------
+// File-scope device array that ep_residual_noalloc stages its reduction
+// counters, sweep-argument tables and 2D tile list in (each GPU the library
+// runs on holds one copy until the process ends).  Host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device.
+constexpr size_t NOALLOC_SCRATCH_BYTES = 64 * 1024;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+// Layout: reduction counters, then two FP64 argument tables (PT and physical
+// evaluation), then the tile count and the tile list (2D models).
+constexpr size_t NA_RED = 0;
+constexpr size_t NA_TAB = 256;
+constexpr size_t NA_CNT = NA_TAB + (2 * sizeof(SweepArgs<double>) + 255) / 256 * 256;
+constexpr size_t NA_TILES = NA_CNT + 256;
+constexpr long NOALLOC_MAX_TILES = (long)((NOALLOC_SCRATCH_BYTES - NA_TILES) / sizeof(TileRef));
+
+// Device address of `scratch` on the current device, looked up once per device.
+int noalloc_scratch(ep_handle* h, char** out)
+{
+    static char* addr[64] = {};
+    int dev = 0;
+    HIPCHK(h, hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return set_err(h, EP_EDEVICE, "device %d out of range", dev);
+    if (!addr[dev]) {
+        void* ptr = nullptr;
+        HIPCHK(h, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        addr[dev] = (char*)ptr;
+    }
+    *out = addr[dev];
+    return EP_OK;
+}
+
 }  // namespace ep
 
 // =========================================================================
@@ -991,6 +1023,71 @@ int ep_residual(ep_handle* h, ep_residual_info* r)
     if ((rc = read_red(h, red))) return rc;
     r->physical = red[RED_MOM];
     r->continuity = red[RED_CONT];
+    return EP_OK;
+}
+
+int ep_residual_noalloc(ep_handle* h, ep_residual_info* r)
+{
+    if (!h || !r) return EP_EINVAL;
+    char* base = nullptr;
+    int rc;
+    if ((rc = noalloc_scratch(h, &base))) return rc;
+    const bool tiles2d = h->ndim == 2 && h->fused64;
+    if (tiles2d && h->ntiles > NOALLOC_MAX_TILES)
+        return set_err(h, EP_EINVAL, "ep_residual_noalloc: %ld tiles exceed the scratch capacity of %ld (%zu bytes)",
+                       h->ntiles, NOALLOC_MAX_TILES, NOALLOC_SCRATCH_BYTES);
+    ensure_it64(h);
+    auto* red = (unsigned long long*)(base + NA_RED);
+    auto* tab = (SweepArgs<double>*)(base + NA_TAB);
+    auto* cnt = (int*)(base + NA_CNT);
+    auto* tiles = (TileRef*)(base + NA_TILES);
+    SweepArgs<double> a[2] = {args64(h, false, h->cur64), args64(h, true, h->cur64)};
+    for (auto& x : a) x.red = red;
+    if (tiles2d) {
+        // stage the two argument tables and this model's tile list
+        const int n = (int)h->ntiles;
+        HIPCHK(h, hipMemcpyAsync(tab, a, sizeof(a), hipMemcpyHostToDevice, h->st));
+        HIPCHK(h, hipMemcpyAsync(cnt, &n, sizeof(int), hipMemcpyHostToDevice, h->st));
+        HIPCHK(h, hipMemcpyAsync(tiles, h->tiles, h->ntiles * sizeof(TileRef), hipMemcpyDeviceToDevice, h->st));
+        HIPCHK(h, hipStreamSynchronize(h->st));          // the host tables leave scope
+    }
+    auto sweep = [&](int q, int mode) {
+        if (tiles2d)
+            launch_sweep_batch_2d<double>(SINGLE_SHAPE, tab + q, tiles, cnt, mode, h->grid2[0], h->st);
+        else if (h->ndim == 2)
+            launch_sweep_unfused_2d<double>(a[q], mode, h->st);
+        else if (h->fused64 && a[q].fs > 0)
+            launch_sweep_fused_3d<double>(a[q], mode, h->st);
+        else
+            launch_sweep_unfused_3d<double>(a[q], mode, h->st);
+    };
+    unsigned long long raw[RED_N];
+    double v[RED_N];
+    // one PT evaluation (written to the second iteration buffer; state untouched)
+    launch_reset_red(red, h->st);
+    sweep(0, MODE_CHECK);
+    HIPCHK(h, hipMemcpyAsync(raw, red, sizeof(raw), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    HIPCHK(h, hipGetLastError());
+    decode_red(raw, v);
+    r->resid = v[RED_RESID];
+    r->momentum = v[RED_MOM];
+    r->vmax = v[RED_VMAX];
+    r->eps_rel = v[RED_VMAX] > 0 ? h->dtrho * v[RED_MOM] / v[RED_VMAX] : 0.0;
+    // physical evaluation and the continuity residual
+    launch_reset_red(red, h->st);
+    sweep(1, MODE_PHYS);
+    double** it = h->it64[h->cur64];
+    const double* vv[3] = {it[F_VX], it[F_VY], it[F_VZ]};
+    const double ikd = std::isinf(h->prm.bulk) ? 0.0 : 1.0 / (h->prm.bulk * h->prm.dt);
+    launch_continuity(h->g, vv, it[F_P], h->old64[O_P], ikd, 1.0 / h->dx, 1.0 / h->dy, 1.0 / h->dz, red + RED_CONT,
+                      h->st);
+    HIPCHK(h, hipMemcpyAsync(raw, red, sizeof(raw), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    HIPCHK(h, hipGetLastError());
+    decode_red(raw, v);
+    r->physical = v[RED_MOM];
+    r->continuity = v[RED_CONT];
     return EP_OK;
 }
 

@@ -33,7 +33,7 @@ FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
 
 # every symbol include/ep.h declares
 SYMBOLS = ["ep_abi_version", "ep_workspace_size", "ep_init", "ep_load_step", "ep_sweep",
-           "ep_residual", "ep_fields", "ep_field_shape", "ep_destroy", "ep_last_error",
+           "ep_residual", "ep_residual_noalloc", "ep_fields", "ep_field_shape", "ep_destroy", "ep_last_error",
            "ep_enable_timing", "ep_sweep_timing", "ep_step_history", "ep_set_guess", "ep_objective_update", "ep_set_strain_rate", "ep_set_shear_modulus",
            "ep_batch_workspace_size", "ep_batch_init", "ep_batch_tune", "ep_batch_tile_shape",
            "ep_batch_load_step", "ep_batch_model", "ep_batch_enable_timing", "ep_batch_timing",
@@ -101,6 +101,7 @@ def lib():
         L.ep_load_step.argtypes = [vp, C.POINTER(ep_step_stats)]
         L.ep_sweep.argtypes = [vp, C.c_int, C.POINTER(C.c_double)]
         L.ep_residual.argtypes = [vp, C.POINTER(ep_residual_info)]
+        L.ep_residual_noalloc.argtypes = [vp, C.POINTER(ep_residual_info)]
         L.ep_fields.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_double), C.c_size_t]
         L.ep_field_shape.restype = C.c_long
         L.ep_field_shape.argtypes = [vp, C.c_int, C.POINTER(C.c_int)]
@@ -188,6 +189,12 @@ def ep_sweep(h, n: int) -> tuple:
 def ep_residual(h) -> tuple:
     r = ep_residual_info()
     rc = lib().ep_residual(h, C.byref(r))
+    return rc, {k: getattr(r, k) for k, _ in r._fields_}
+
+
+def ep_residual_noalloc(h) -> tuple:
+    r = ep_residual_info()
+    rc = lib().ep_residual_noalloc(h, C.byref(r))
     return rc, {k: getattr(r, k) for k, _ in r._fields_}
 
 
