@@ -70,6 +70,43 @@ def test_single_sweep_matches_oracle(name, m, prec, sweep):
     g.close()
 
 
+# Single sweeps with every option of the return on a grid whose tiles lie
+# strictly inside the domain (the fused 3D sweep's interior code path):
+# dilatancy, consistency regularisation and a per-cell shear modulus, alone
+# and together, from random yielding states (small cohesion).
+OPTIONS = [
+    ("psi", dict(psi_deg=10.0), False),
+    ("eta_vp", dict(eta_vp=1e-3), False),
+    ("G", dict(shear=1.2), True),
+    ("all", dict(psi_deg=8.0, eta_vp=1e-3, shear=1.2), True),
+]
+
+
+@pytest.mark.parametrize("name,opts,with_g", OPTIONS, ids=[o[0] for o in OPTIONS])
+@pytest.mark.parametrize("prec", [FP64, FP32], ids=["fp64", "fp32"])
+def test_single_sweep_options_interior_tiles(name, opts, with_g, prec):
+    from ep_workloads import gaussian_shear
+    m = Model(ndim=3, nx=100, ny=60, nz=20, ly=0.7, lz=0.4, c0=1e-4, incl_radius=0.2, **opts)
+    say("single sweep with options", name, "prec", prec)
+    st = random_state(m, seed=21, amp_v=2e-3, amp_s=1.2e-3)
+    g = solver(m, precision=prec, sweep=1)
+    o = Oracle(m)
+    if with_g:
+        G = gaussian_shear(m, centre=(0.03, -0.02, 0.01))
+        g.set_shear_modulus(G)
+        o.set_shear_modulus(G)
+    set_state(g, m, st, settable_tzz=False)
+    set_state(o, m, st, settable_tzz=True)
+    tol = 1e-11 if prec == FP64 else 2e-5
+    for n in (1, 4):
+        g.sweep(n)
+        for _ in range(n):
+            o.sweep()
+        names = it_names(m)
+        compare(m, g.fields(names), o.fields(names), names, tol, f"{name} after sweeps")
+    g.close()
+
+
 # ------------------------------------------------------- whole increments
 def run_both(m, steps, prec=FP64, sweep=0, start=None):
     g = solver(m, precision=prec, sweep=sweep)
@@ -85,6 +122,30 @@ def run_both(m, steps, prec=FP64, sweep=0, start=None):
         if sg["status"] != 0 or so["status"] != 0:
             break
     return g, o, out
+
+
+def test_3d_fp32_trajectory_through_the_handover():
+    """FP32 fields against the FP64 oracle over six increments of a 3D model
+    with interior tiles (100 x 60 x 24): four elastic increments, then the
+    first two plastic ones (about 4000 yielding cells), in each of which the
+    FP32 sweeps hand over to FP64 sweeps near the FP32 rounding floor and the
+    FP64 certificate accepts the state.  Every field and accumulator within
+    1e-4 of its scale."""
+    m = Model(ndim=3, nx=100, ny=60, nz=24, ly=0.6, lz=0.24, dt=1.25e-4, tol=1e-6, n_check=10, incl_radius=0.12,
+              incl_centre=(0.05, 0.03, -0.02), steps=6, max_iter=200000)
+    say("3d fp32 trajectory through the hand-over")
+    g, o, out = run_both(m, m.steps, FP32)
+    for n, (sg, so) in enumerate(out):
+        assert sg["status"] == 0 and so["status"] == 0, (n, sg, so)
+        if so["iters"] > 0:
+            assert sg["iters_fp32"] > 0 and sg["iters"] > sg["iters_fp32"] and sg["fp32_exit"] > 0, (n, sg)
+            assert sg["cert"] <= m.tol * sg["ref"], (n, sg["cert"], sg["ref"])
+            assert abs(sg["n_yield"] - so["n_yield"]) <= 0.01 * so["n_yield"], (n, sg["n_yield"], so["n_yield"])
+    assert out[-1][1]["n_yield"] > 1000
+    names = it_names(m)
+    compare(m, g.fields(names), o.fields(names), names, 1e-4, "fields")
+    compare_accumulators(m, g.fields(accum_names(m)), o.fields(accum_names(m)), 1e-4)
+    g.close()
 
 
 @pytest.mark.parametrize("prec", [FP64, FP32], ids=["fp64", "fp32"])
