@@ -224,6 +224,31 @@ int ep_load_step(ep_handle* h, ep_step_stats* st);
  * NULL array. */
 int ep_set_guess(ep_handle* h, const double* vx, const double* vy, const double* vz);
 
+#define EP_GUESS_VELOCITY 0   /* the arrays are the guessed face velocities */
+#define EP_GUESS_CHANGE   1   /* the arrays are velocity changes, added to the current
+                                 velocities (those of the last accepted increment) */
+#define EP_GUESS_ZERO     2   /* zero velocities inside the domain; no arrays */
+#define EP_GUESS_F64      0
+#define EP_GUESS_F32      1
+
+/* Starting guess of the next ep_load_step from device memory (e.g. a
+ * predictor's output tensor), with the same acceptance rule as ep_set_guess
+ * (paper, accelerated pseudo-transient method: the iteration starts from the
+ * previous increment's velocities; a better starting point shortens it).
+ *  kind: EP_GUESS_VELOCITY, EP_GUESS_CHANGE or EP_GUESS_ZERO (above).
+ *  dtype: EP_GUESS_F64 (double) or EP_GUESS_F32 (float) elements.
+ *  vx, vy, vz: device pointers to compact arrays at the shapes of EP_F_VX,
+ *    EP_F_VY, EP_F_VZ (x fastest; vz NULL in 2D; all NULL for EP_GUESS_ZERO),
+ *    on the handle's device; the caller keeps ownership.
+ * The arrays are read by a kernel enqueued on the handle's stream by this
+ * call, so they must stay valid and unchanged until that stream has passed
+ * it (for instance until the next ep_load_step returns).  Wall normal
+ * velocities are reset to their prescribed values whatever the arrays hold.
+ * Used once.  EP_EINVAL for a bad kind or dtype, a NULL array where one is
+ * needed, or a pointer that HIP does not report as device memory;
+ * EP_EDEVICE for a launch failure. */
+int ep_set_guess_device(ep_handle* h, int kind, int dtype, const void* vx, const void* vy, const void* vz);
+
 /* Residual history of the last ep_load_step: for each check, the normalised
  * residual (resid / ref) and the precision of the sweeps that produced it
  * (EP_FP64 or EP_FP32_FIELDS).  Copies at most cap entries; returns the

@@ -1222,6 +1222,45 @@ int ep_set_guess(ep_handle* h, const double* vx, const double* vy, const double*
     return EP_OK;
 }
 
+// a device array of the current device (rejects host and foreign memory
+// before a kernel could dereference it)
+static bool is_device_array(const void* p)
+{
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    return (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) && a.device == dev;
+}
+
+int ep_set_guess_device(ep_handle* h, int kind, int dtype, const void* vx, const void* vy, const void* vz)
+{
+    if (!h) return EP_EINVAL;
+    if (kind != EP_GUESS_VELOCITY && kind != EP_GUESS_CHANGE && kind != EP_GUESS_ZERO)
+        return set_err(h, EP_EINVAL, "ep_set_guess_device: bad kind %d", kind);
+    if (dtype != EP_GUESS_F64 && dtype != EP_GUESS_F32)
+        return set_err(h, EP_EINVAL, "ep_set_guess_device: bad dtype %d", dtype);
+    const void* src[3] = {vx, vy, vz};
+    if (kind != EP_GUESS_ZERO)
+        for (int d = 0; d < h->ndim; ++d)
+            if (!src[d] || !is_device_array(src[d]))
+                return set_err(h, EP_EINVAL, "ep_set_guess_device: velocity array %d is not device memory", d);
+    ensure_it64(h);
+    const int nz1 = h->ndim == 3 ? h->nz : 1;
+    double** it = h->it64[h->cur64];
+    for (int d = 0; d < h->ndim; ++d) {
+        const int ext[3] = {h->nx + (d == 0), h->ny + (d == 1), nz1 + (d == 2)};
+        launch_guess_in(h->vguess64[d], kind == EP_GUESS_ZERO ? nullptr : src[d], dtype == EP_GUESS_F32,
+                        kind == EP_GUESS_CHANGE ? it[F_VX + d] : nullptr, ext, h->sy, h->sz, h->st);
+    }
+    HIPCHK(h, hipGetLastError());
+    h->guess_ready = true;
+    return EP_OK;
+}
+
 int ep_fields(ep_handle* h, int field, int dir, double* host, size_t count)
 {
     if (!h || !host || field < 0 || field >= EP_F_COUNT || (dir != EP_GET && dir != EP_SET)) return EP_EINVAL;

@@ -21,6 +21,21 @@ __global__ void k_copy(double* d, const double* s, long n)
 {
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) d[q] = s[q];
 }
+// compact (x fastest) guess array -> padded FP64 field, optionally added to a
+// base field of the padded layout; src == nullptr gives the base (or zero)
+template <typename T>
+__global__ void k_guess_in(double* d, const T* __restrict__ src, const double* __restrict__ base, int e0, int e1,
+                           int e2, long sy, long sz)
+{
+    const long n = (long)e0 * e1 * e2;
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(q % e0);
+        const long r = q / e0;
+        const int j = (int)(r % e1), k = (int)(r / e1);
+        const long e = i + sy * j + sz * k;
+        d[e] = (base ? base[e] : 0.0) + (src ? (double)src[q] : 0.0);
+    }
+}
 __global__ void k_to_f32(float* d, const double* s, long n)
 {
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) d[q] = (float)s[q];
@@ -454,6 +469,15 @@ __global__ void k_objective_3d(AuxGrid g, ObjectiveArgs a)
 }  // namespace
 
 void launch_fill(double* p, double v, long n, hipStream_t s) { k_fill<<<blocks_for(n), NT1, 0, s>>>(p, v, n); }
+void launch_guess_in(double* d, const void* src, bool f32, const double* base, const int ext[3], long sy, long sz,
+                     hipStream_t s)
+{
+    const long n = (long)ext[0] * ext[1] * ext[2];
+    if (f32)
+        k_guess_in<float><<<blocks_for(n), NT1, 0, s>>>(d, (const float*)src, base, ext[0], ext[1], ext[2], sy, sz);
+    else
+        k_guess_in<double><<<blocks_for(n), NT1, 0, s>>>(d, (const double*)src, base, ext[0], ext[1], ext[2], sy, sz);
+}
 void launch_copy(double* d, const double* src, long n, hipStream_t s) { k_copy<<<blocks_for(n), NT1, 0, s>>>(d, src, n); }
 void launch_to_f32(float* d, const double* src, long n, hipStream_t s) { k_to_f32<<<blocks_for(n), NT1, 0, s>>>(d, src, n); }
 void launch_to_f64(double* d, const float* src, long n, hipStream_t s) { k_to_f64<<<blocks_for(n), NT1, 0, s>>>(d, src, n); }

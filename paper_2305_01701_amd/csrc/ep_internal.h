@@ -100,6 +100,10 @@ struct AuxGrid {
 
 void launch_fill(double* p, double v, long n, hipStream_t s);
 void launch_copy(double* dst, const double* src, long n, hipStream_t s);
+// compact array of extents ext (x fastest; FP32 when f32, else FP64; nullptr:
+// none) plus a padded base field (nullptr: none) -> padded FP64 field
+void launch_guess_in(double* dst, const void* src, bool f32, const double* base, const int ext[3], long sy, long sz,
+                     hipStream_t s);
 void launch_to_f32(float* dst, const double* src, long n, hipStream_t s);
 void launch_to_f64(double* dst, const float* src, long n, hipStream_t s);
 // Velocity component d (0 x, 1 y, 2 z) between the full FP64 field and the

@@ -34,7 +34,7 @@ FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
 # every symbol include/ep.h declares
 SYMBOLS = ["ep_abi_version", "ep_workspace_size", "ep_init", "ep_load_step", "ep_sweep",
            "ep_residual", "ep_residual_noalloc", "ep_fields", "ep_field_shape", "ep_destroy", "ep_last_error",
-           "ep_enable_timing", "ep_sweep_timing", "ep_step_history", "ep_set_guess", "ep_objective_update", "ep_set_strain_rate", "ep_set_shear_modulus",
+           "ep_enable_timing", "ep_sweep_timing", "ep_step_history", "ep_set_guess", "ep_set_guess_device", "ep_objective_update", "ep_set_strain_rate", "ep_set_shear_modulus",
            "ep_batch_workspace_size", "ep_batch_init", "ep_batch_tune", "ep_batch_tile_shape",
            "ep_batch_load_step", "ep_batch_model", "ep_batch_enable_timing", "ep_batch_timing",
            "ep_batch_destroy", "ep_batch_last_error",
@@ -113,6 +113,7 @@ def lib():
         L.ep_sweep_timing.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_long)]
         L.ep_step_history.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_int]
         L.ep_set_guess.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.ep_set_guess_device.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp]
         L.ep_objective_update.argtypes = [vp]
         L.ep_set_strain_rate.argtypes = [vp, C.POINTER(C.c_double)]
         L.ep_set_shear_modulus.argtypes = [vp, C.POINTER(C.c_double)]
@@ -355,6 +356,21 @@ class ModelView:
         arrs.append(None if vz is None else np.ascontiguousarray(vz, dtype=np.float64))
         ptr = lambda a: None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
         self._check(lib().ep_set_guess(self.h, ptr(arrs[0]), ptr(arrs[1]), ptr(arrs[2])), "ep_set_guess")
+
+    GUESS_KIND = {"velocity": 0, "change": 1, "zero": 2}
+
+    def set_guess_device(self, kind: str, vx=None, vy=None, vz=None) -> None:
+        """Starting guess from device tensors (float64 or float32, contiguous,
+        at the face-velocity shapes); kind "velocity", "change" or "zero"."""
+        import torch
+        ts = [t for t in (vx, vy, vz) if t is not None]
+        dtype = 1 if ts and ts[0].dtype == torch.float32 else 0
+        for t in ts:
+            if not t.is_contiguous() or t.dtype != ts[0].dtype or t.dtype not in (torch.float32, torch.float64):
+                raise ValueError("guess tensors must be contiguous float32 or float64 tensors of one dtype")
+        ptr = lambda t: None if t is None else t.data_ptr()
+        self._check(lib().ep_set_guess_device(self.h, self.GUESS_KIND[kind], dtype, ptr(vx), ptr(vy), ptr(vz)),
+                    "ep_set_guess_device")
 
     def set_strain_rate(self, erate) -> None:
         """Background strain rate of the next increments (loading schedule)."""

@@ -358,42 +358,34 @@ def test_c3_full_size_sweep_matches_oracle(prec):
     assert rg == pytest.approx(ro, rel=1e-9 if prec == FP64 else 1e-3)
 
 
+def _guess_model(ndim):
+    if ndim == 2:
+        return offcentre(c1_small_2d().with_(n_check=10, dt=2e-4)), ["vx", "vy"]
+    return Model(ndim=3, nx=17, ny=15, nz=13, dt=2e-4, tol=1e-8, n_check=10, incl_radius=0.25,
+                 incl_centre=(0.04, -0.03, 0.02)), ["vx", "vy", "vz"]
+
+
 @pytest.mark.parametrize("ndim", [2, 3])
 def test_supplied_guess(ndim):
     """ep_set_guess: the converged velocities of an increment as its guess
-    converge at the first check to the same state; a poor guess is rejected
-    and the increment is then bitwise the plain one."""
-    if ndim == 2:
-        m = offcentre(c1_small_2d().with_(n_check=10, dt=2e-4))
-        names = ["vx", "vy"]
-    else:
-        m = Model(ndim=3, nx=17, ny=15, nz=13, dt=2e-4, tol=1e-8, n_check=10, incl_radius=0.25,
-                  incl_centre=(0.04, -0.03, 0.02))
-        names = ["vx", "vy", "vz"]
+    are accepted without a sweep (their physical stresses are the accepted
+    state, which meets the tolerance) and give that state again; a poor guess
+    is rejected and the increment is then bitwise the plain one."""
+    m, names = _guess_model(ndim)
     say("supplied guess", ndim)
     a, b, c = solver(m), solver(m), solver(m)
     for _ in range(3):
         for s in (a, b, c):
             assert s.load_step()["status"] == 0
     sa = a.load_step()                       # a plastic increment, plain
-    assert sa["iters"] > 10
+    assert sa["iters"] > 10 and sa["n_yield"] > 0
     good = [a.get(k) for k in names]
     b.set_guess(*good)
     sb = b.load_step()
-    assert sb["status"] == 0 and sb["guess_used"] == 1 and sb["iters"] < sa["iters"]
-    # the physical stresses of the converged velocities do not balance exactly
-    # in yielding cells (the PT fixed point's Lambda mixes the averaged shear
-    # points), but far better than those of the previous velocities
-    assert sb["r_guess"] < 0.5 * sb["r_ref"]
+    assert sb["status"] == 0 and sb["guess_used"] == 1 and sb["iters"] == 0
+    assert sb["r_guess"] == sb["cert"] <= m.tol * sb["ref"]
     fa = a.fields(it_names(m))
-    if ndim == 3:
-        compare(m, b.fields(it_names(m)), fa, it_names(m), 1e-6)
-    else:
-        # this 2D plastic increment has more than one converged state (started
-        # from the guess's physical stresses the iteration settles in another
-        # one): check that the state is a converged one
-        assert b.residual()["resid"] <= 10 * m.tol * sb["ref"]
-        assert sb["max_violation"] <= 2 * max(sa["max_violation"], 1e-9)
+    compare(m, b.fields(it_names(m)), fa, it_names(m), 1e-12)
     r = np.random.Generator(np.random.PCG64(3))
     poor = [g + r.standard_normal(g.shape) * 0.1 for g in good]
     c.set_guess(*poor)
@@ -402,6 +394,61 @@ def test_supplied_guess(ndim):
     fc = c.fields(it_names(m))
     for k in it_names(m):
         assert np.array_equal(fc[k], fa[k]), k
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_device_guess(ndim):
+    """ep_set_guess_device: FP64 device velocities give bitwise the increment
+    of the same host guess; FP32 velocity changes (added to the previous
+    velocities) are accepted and converge to the plain increment's state; a
+    zero guess is rejected (its residual is far above the plain one) and the
+    increment is bitwise the plain one; host memory and bad kinds are
+    rejected before any kernel runs."""
+    import torch
+    m, names = _guess_model(ndim)
+    say("device guess", ndim)
+    a, b, d, e, z = (solver(m) for _ in range(5))
+    for _ in range(3):
+        for s in (a, b, d, e, z):
+            assert s.load_step()["status"] == 0
+    prev = [a.get(k) for k in names]
+    sa = a.load_step()
+    good = [a.get(k) for k in names]
+    fa = a.fields(it_names(m))
+
+    b.set_guess(*good)
+    sb = b.load_step()
+    dev = [torch.from_numpy(np.ascontiguousarray(g)).to("cuda") for g in good]
+    d.set_guess_device("velocity", *dev)
+    sd = d.load_step()
+    assert sd["guess_used"] == 1 and sd["iters"] == sb["iters"] and sd["r_guess"] == sb["r_guess"]
+    fb, fd = b.fields(it_names(m)), d.fields(it_names(m))
+    for k in it_names(m):
+        assert np.array_equal(fd[k], fb[k]), k
+
+    dv = [torch.from_numpy((g - p).astype(np.float32)).to("cuda") for g, p in zip(good, prev)]
+    e.set_guess_device("change", *dv)
+    se = e.load_step()
+    assert se["status"] == 0 and se["guess_used"] == 1 and se["iters"] < sa["iters"]
+    assert se["cert"] <= m.tol * se["ref"]
+    compare(m, e.fields(it_names(m)), fa, it_names(m), 1e-6)
+
+    z.set_guess_device("zero")
+    sz = z.load_step()
+    assert sz["guess_used"] == 0 and sz["r_guess"] > sz["r_ref"] and sz["iters"] == sa["iters"]
+    fz = z.fields(it_names(m))
+    for k in it_names(m):
+        assert np.array_equal(fz[k], fa[k]), k
+
+    E = ep()
+    L = E.lib()
+    assert L.ep_set_guess_device(z.h, 7, 0, None, None, None) == E.EP_EINVAL
+    assert L.ep_set_guess_device(z.h, 0, 5, None, None, None) == E.EP_EINVAL
+    assert L.ep_set_guess_device(z.h, 0, 0, None, None, None) == E.EP_EINVAL
+    host = [np.ascontiguousarray(g) for g in good] + [None]
+    assert L.ep_set_guess_device(z.h, 0, 0, *[None if h is None else h.ctypes.data for h in host[:3]]) == E.EP_EINVAL
+    for s in (a, b, d, e, z):
+        s.close()
 
 
 FROZEN_CASES = [
