@@ -61,6 +61,7 @@
 #include "ep_oracle.h"
 
 #include <float.h>
+#include <stdio.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -1259,6 +1260,10 @@ int orc_load_step(orc_state* s, orc_stats* st)
         if (s->freeze == 1) s->freeze = 2;   /* that sweep stored its Lambda */
         if (it % nchk == 0) {
             if (s->hist && s->hist_len < s->hist_cap) s->hist[s->hist_len++] = res;
+            if (s->prm.progress > 0 && it % s->prm.progress == 0) {
+                fprintf(stderr, "oracle: iteration %d residual/ref %.3e\n", it, res / st->ref);
+                fflush(stderr);
+            }
             if (!(res == res) || isinf(res) || res > 1e8 * st->ref) { status = -5; break; }
             if (res <= s->prm.tol * st->ref) {
                 /* acceptance: the momentum residual of the physical stresses

@@ -44,6 +44,8 @@ typedef struct orc_params {
                                 the converged state does not depend on it */
     double pt_blend_late;    /* the weight after the first check at or after 16 max(nx, ny, nz)
                                 iterations of an increment */
+    int    progress;         /* 0: silent; else one line on stderr (iteration, normalised
+                                residual) at every check whose iteration is a multiple of it */
 } orc_params;
 
 typedef struct orc_stats {

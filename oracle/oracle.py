@@ -35,7 +35,7 @@ class OrcParams(C.Structure):
         ("max_iter", C.c_int), ("n_check", C.c_int),
         ("re", C.c_double), ("r", C.c_double), ("cfl", C.c_double),
         ("freeze_iter", C.c_int), ("objective", C.c_int), ("eta_vp", C.c_double),
-        ("pt_blend", C.c_double), ("pt_blend_late", C.c_double),
+        ("pt_blend", C.c_double), ("pt_blend_late", C.c_double), ("progress", C.c_int),
     ]
 
 
@@ -84,7 +84,7 @@ def lib():
     return _lib
 
 
-def params_from_model(m) -> OrcParams:
+def params_from_model(m, progress: int = 0) -> OrcParams:
     p = OrcParams()
     p.ndim, p.nx, p.ny = m.ndim, m.nx, m.ny
     p.nz = m.nz if m.ndim == 3 else 1
@@ -100,6 +100,7 @@ def params_from_model(m) -> OrcParams:
     p.eta_vp = m.eta_vp
     p.pt_blend = m.pt_blend
     p.pt_blend_late = m.pt_blend_late
+    p.progress = progress
     return p
 
 
@@ -110,9 +111,9 @@ def _dptr(a: np.ndarray):
 class Oracle:
     """One model held by the C oracle."""
 
-    def __init__(self, model, cohesion: Optional[np.ndarray] = None):
+    def __init__(self, model, cohesion: Optional[np.ndarray] = None, progress: int = 0):
         self.model = model
-        self._p = params_from_model(model)
+        self._p = params_from_model(model, progress)
         if cohesion is None:
             from ep_workloads import cohesion_field
             cohesion = cohesion_field(model)
