@@ -10,10 +10,10 @@
 // Convolution = implicit GEMM: rows are voxels, columns output channels,
 // the reduction runs over 27 taps x input channels.  One wave computes 64
 // voxels (4 MFMA row blocks of 16) x all output channels with
-// v_mfma_f32_16x16x16_bf16: the A operand of a lane is 4 consecutive input
+// v_mfma_f32_16x16x32_bf16: the A operand of a lane is 8 consecutive input
 // channels of one voxel (read from an LDS copy of the block's input with
-// halo), the B operand 4 consecutive input channels of one output channel's
-// weights.  The gradient with respect to
+// halo), the B operand 8 consecutive input channels of one output channel's
+// weights (the 16-channel input layer uses the K = 16 form).  The gradient with respect to
 // the input is the same kernel on the output gradient with the weights
 // transposed (input <-> output channels) and the taps mirrored.  The weight
 // gradient reduces over voxels: a workgroup stages 64 voxels of the output
@@ -42,7 +42,11 @@ namespace {
 
 typedef unsigned short bf16_t;
 typedef __attribute__((ext_vector_type(4))) short s4;
+typedef __attribute__((ext_vector_type(8))) __bf16 b8;
 typedef __attribute__((ext_vector_type(4))) float f4;
+
+// 8 bfloat16 values (16 bytes) as the operand of a K = 32 MFMA
+__device__ __forceinline__ b8 ld_b8(const bf16_t* p) { return __builtin_bit_cast(b8, *(const uint4*)p); }
 
 constexpr int NL = 11;      // convolutions
 constexpr int CIN0 = 16;    // input channels (11 used)
@@ -152,18 +156,40 @@ __global__ __launch_bounds__(256) void k_conv(const bf16_t* __restrict__ X, int 
             *(uint4*)(tile + tv * CT_ROW + q * 8) = val;
         }
         __syncthreads();
-        for (int t = 0; t < 27; ++t) {
-            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;     // 0..2: tap offset + 1
-            for (int cs = 0; cs < kc; cs += 16) {
+        if (kc == 32) {
+            // K = 32: lane (r, kq) holds channels kq*8 .. kq*8+7 of voxel row r
+            // (A) and of output channel r (B); A and B share the lane-to-
+            // channel map, so the reduction covers the 32 channels whatever
+            // order the matrix core takes them in
+            for (int t = 0; t < 27; ++t) {
+                const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;     // 0..2: tap offset + 1
+                b8 a[4];
+#pragma unroll
+                for (int mb = 0; mb < 4; ++mb) {
+                    const int tv = ((wave + dz) * CT_Y + (mb + dy)) * CT_X + (r + dx);
+                    a[mb] = ld_b8(tile + tv * CT_ROW + kq * 8);
+                }
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const b8 bw = ld_b8(Wt + ((long)(nb * 16 + r) * 27 + t) * cin + c0 + kq * 8);
+#pragma unroll
+                    for (int mb = 0; mb < 4; ++mb)
+                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], bw, acc[mb][nb], 0, 0, 0);
+                }
+            }
+        } else {
+            // a 16-channel chunk (the 16-channel input layer): K = 16
+            for (int t = 0; t < 27; ++t) {
+                const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
                 s4 a[4];
 #pragma unroll
                 for (int mb = 0; mb < 4; ++mb) {
                     const int tv = ((wave + dz) * CT_Y + (mb + dy)) * CT_X + (r + dx);
-                    a[mb] = *(const s4*)(tile + tv * CT_ROW + cs + kq * 4);
+                    a[mb] = *(const s4*)(tile + tv * CT_ROW + kq * 4);
                 }
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
-                    const s4 bw = *(const s4*)(Wt + ((long)(nb * 16 + r) * 27 + t) * cin + c0 + cs + kq * 4);
+                    const s4 bw = *(const s4*)(Wt + ((long)(nb * 16 + r) * 27 + t) * cin + c0 + kq * 4);
 #pragma unroll
                     for (int mb = 0; mb < 4; ++mb)
                         acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mb], bw, acc[mb][nb], 0, 0, 0);
@@ -207,9 +233,11 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16_t* __restrict__ X, con
                                                float* __restrict__ dW, Vol g, long vchunk)
 {
     constexpr int CO = NBO * 16, CI = NBI * 16;
-    constexpr int SO = CO + 8, SI = CI + 8;          // padded LDS rows
+    constexpr int RW = 72;                             // 64 voxels + 8: rows of 144 bytes
     constexpr int NP = NBO * NBI, PW = (NP + 3) / 4;   // block pairs, per wave
-    __shared__ bf16_t sG[64 * SO], sX[64 * SI];
+    // channel-major (transposed) stage: a lane's 8 voxels of one channel are
+    // one 16-byte LDS read
+    __shared__ __attribute__((aligned(16))) bf16_t sG[CO * RW], sX[CI * RW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, kq = lane >> 4;
     const int t = blockIdx.y;
@@ -221,20 +249,25 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16_t* __restrict__ X, con
     for (int q = 0; q < PW; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
     for (long vs = v0; vs < v1; vs += 64) {
         __syncthreads();
-        // stage 64 voxels: 8 channels (16 bytes) per thread and step
+        // stage 64 voxels: 8 channels (16 bytes) per thread and step, written
+        // transposed
         for (int e = threadIdx.x; e < 64 * (CO / 8); e += 256) {
             const int row = e / (CO / 8), q = e % (CO / 8);
             const long v = vs + row;
             uint4 val = {0u, 0u, 0u, 0u};
             if (v < v1) val = *(const uint4*)(G + pidx(g, v) * CO + q * 8);
-            *(uint4*)(sG + row * SO + q * 8) = val;
+            const bf16_t* h = (const bf16_t*)&val;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) sG[(q * 8 + k) * RW + row] = h[k];
         }
         for (int e = threadIdx.x; e < 64 * (CI / 8); e += 256) {
             const int row = e / (CI / 8), q = e % (CI / 8);
             const long v = vs + row;
             uint4 val = {0u, 0u, 0u, 0u};
             if (v < v1) val = *(const uint4*)(X + (pidx(g, v) + off) * CI + q * 8);
-            *(uint4*)(sX + row * SI + q * 8) = val;
+            const bf16_t* h = (const bf16_t*)&val;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) sX[(q * 8 + k) * RW + row] = h[k];
         }
         __syncthreads();
 #pragma unroll
@@ -243,15 +276,12 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16_t* __restrict__ X, con
             if (pr >= NP) break;
             const int ob = pr / NBI, ib = pr % NBI;
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                s4 a, b;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int row = ks * 16 + kq * 4 + j;
-                    a[j] = (short)sG[row * SO + ob * 16 + r];
-                    b[j] = (short)sX[row * SI + ib * 16 + r];
-                }
-                acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[q], 0, 0, 0);
+            for (int ks = 0; ks < 2; ++ks) {
+                // K = 32 voxels: lane (r, kq) holds voxels ks*32 + kq*8 .. +7 of
+                // output channel ob*16 + r (A) and input channel ib*16 + r (B)
+                const b8 a = ld_b8(sG + (ob * 16 + r) * RW + ks * 32 + kq * 8);
+                const b8 b = ld_b8(sX + (ib * 16 + r) * RW + ks * 32 + kq * 8);
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[q], 0, 0, 0);
             }
         }
     }
@@ -271,96 +301,110 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16_t* __restrict__ X, con
 // db[c] += sum over voxels of G[v][c]
 __global__ void k_bias_grad(const bf16_t* __restrict__ G, int C, float* __restrict__ db, Vol g)
 {
-    __shared__ float s[256];
-    const int c = blockIdx.y;
-    float acc = 0.f;
-    for (long v = (long)blockIdx.x * 256 + threadIdx.x; v < g.V; v += (long)gridDim.x * 256)
-        acc += bf2f(G[pidx(g, v) * C + c]);
-    s[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
-        __syncthreads();
+    // thread = (voxel slot, group of 8 channels): 16-byte loads, a block
+    // covers 256 / (C / 8) voxels per step (C in {16, 32, 64, 128})
+    __shared__ float s[256 * 8];
+    const int ng = C / 8, grp = threadIdx.x % ng, vq = threadIdx.x / ng, nv = 256 / ng;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (long v = (long)blockIdx.x * nv + vq; v < g.V; v += (long)gridDim.x * nv) {
+        const uint4 val = *(const uint4*)(G + pidx(g, v) * C + grp * 8);
+        const bf16_t* h = (const bf16_t*)&val;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] += bf2f(h[k]);
     }
-    if (threadIdx.x == 0) atomicAdd(db + c, s[0]);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s[threadIdx.x * 8 + k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x < C) {
+        const int gq = threadIdx.x / 8, k = threadIdx.x % 8;
+        float sum = 0.f;
+        for (int q = 0; q < nv; ++q) sum += s[(q * ng + gq) * 8 + k];
+        atomicAdd(db + threadIdx.x, sum);
+    }
 }
 
 // ------------------------------------------------------------ elementwise
 // pool: out (level g2) = mean of the 8 children in level g
 __global__ void k_pool(const bf16_t* __restrict__ in, bf16_t* __restrict__ out, int C, Vol g, Vol g2)
 {
-    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= g2.V * C) return;
-    const int c = (int)(e % C);
-    const long v = e / C;
-    const int x = (int)(v % g2.W), y = (int)((v / g2.W) % g2.H), z = (int)(v / ((long)g2.W * g2.H));
-    float s = 0.f;
-    for (int q = 0; q < 8; ++q) {
-        const int zz = 2 * z + (q >> 2), yy = 2 * y + ((q >> 1) & 1), xx = 2 * x + (q & 1);
-        s += bf2f(in[(((long)(zz + 1) * g.Hp + yy + 1) * g.Wp + xx + 1) * C + c]);
+    // grid-stride: the element count can exceed 2^32 work-items
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < g2.V * C; e += (long)gridDim.x * blockDim.x) {
+        const int c = (int)(e % C);
+        const long v = e / C;
+        const int x = (int)(v % g2.W), y = (int)((v / g2.W) % g2.H), z = (int)(v / ((long)g2.W * g2.H));
+        float s = 0.f;
+        for (int q = 0; q < 8; ++q) {
+            const int zz = 2 * z + (q >> 2), yy = 2 * y + ((q >> 1) & 1), xx = 2 * x + (q & 1);
+            s += bf2f(in[(((long)(zz + 1) * g.Hp + yy + 1) * g.Wp + xx + 1) * C + c]);
+        }
+        out[pidx(g2, v) * C + c] = f2bf(s * 0.125f);
     }
-    out[pidx(g2, v) * C + c] = f2bf(s * 0.125f);
 }
 
 // up: out (level g) = parent value (level g2)
 __global__ void k_up(const bf16_t* __restrict__ in, bf16_t* __restrict__ out, int C, Vol g, Vol g2)
 {
-    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= g.V * C) return;
-    const int c = (int)(e % C);
-    const long v = e / C;
-    const int x = (int)(v % g.W), y = (int)((v / g.W) % g.H), z = (int)(v / ((long)g.W * g.H));
-    out[pidx(g, v) * C + c] = in[(((long)(z / 2 + 1) * g2.Hp + y / 2 + 1) * g2.Wp + x / 2 + 1) * C + c];
+    // grid-stride: the element count can exceed 2^32 work-items
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < g.V * C; e += (long)gridDim.x * blockDim.x) {
+        const int c = (int)(e % C);
+        const long v = e / C;
+        const int x = (int)(v % g.W), y = (int)((v / g.W) % g.H), z = (int)(v / ((long)g.W * g.H));
+        out[pidx(g, v) * C + c] = in[(((long)(z / 2 + 1) * g2.Hp + y / 2 + 1) * g2.Wp + x / 2 + 1) * C + c];
+    }
 }
 
 // gradient of up: out (level g2) = sum of the 8 children (level g)
 __global__ void k_up_dx(const bf16_t* __restrict__ in, bf16_t* __restrict__ out, int C, Vol g, Vol g2)
 {
-    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= g2.V * C) return;
-    const int c = (int)(e % C);
-    const long v = e / C;
-    const int x = (int)(v % g2.W), y = (int)((v / g2.W) % g2.H), z = (int)(v / ((long)g2.W * g2.H));
-    float s = 0.f;
-    for (int q = 0; q < 8; ++q) {
-        const int zz = 2 * z + (q >> 2), yy = 2 * y + ((q >> 1) & 1), xx = 2 * x + (q & 1);
-        s += bf2f(in[(((long)(zz + 1) * g.Hp + yy + 1) * g.Wp + xx + 1) * C + c]);
+    // grid-stride: the element count can exceed 2^32 work-items
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < g2.V * C; e += (long)gridDim.x * blockDim.x) {
+        const int c = (int)(e % C);
+        const long v = e / C;
+        const int x = (int)(v % g2.W), y = (int)((v / g2.W) % g2.H), z = (int)(v / ((long)g2.W * g2.H));
+        float s = 0.f;
+        for (int q = 0; q < 8; ++q) {
+            const int zz = 2 * z + (q >> 2), yy = 2 * y + ((q >> 1) & 1), xx = 2 * x + (q & 1);
+            s += bf2f(in[(((long)(zz + 1) * g.Hp + yy + 1) * g.Wp + xx + 1) * C + c]);
+        }
+        out[pidx(g2, v) * C + c] = f2bf(s);
     }
-    out[pidx(g2, v) * C + c] = f2bf(s);
 }
 
 // out (level g) = a + pool gradient of t (level g2): a + t(parent) / 8
 __global__ void k_add_pool_dx(const bf16_t* __restrict__ a, const bf16_t* __restrict__ t, bf16_t* __restrict__ out,
                               int C, Vol g, Vol g2)
 {
-    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= g.V * C) return;
-    const int c = (int)(e % C);
-    const long v = e / C;
-    const int x = (int)(v % g.W), y = (int)((v / g.W) % g.H), z = (int)(v / ((long)g.W * g.H));
-    const long p = pidx(g, v) * C + c;
-    const float tv = bf2f(t[(((long)(z / 2 + 1) * g2.Hp + y / 2 + 1) * g2.Wp + x / 2 + 1) * C + c]);
-    out[p] = f2bf(bf2f(a[p]) + tv * 0.125f);
+    // grid-stride: the element count can exceed 2^32 work-items
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < g.V * C; e += (long)gridDim.x * blockDim.x) {
+        const int c = (int)(e % C);
+        const long v = e / C;
+        const int x = (int)(v % g.W), y = (int)((v / g.W) % g.H), z = (int)(v / ((long)g.W * g.H));
+        const long p = pidx(g, v) * C + c;
+        const float tv = bf2f(t[(((long)(z / 2 + 1) * g2.Hp + y / 2 + 1) * g2.Wp + x / 2 + 1) * C + c]);
+        out[p] = f2bf(bf2f(a[p]) + tv * 0.125f);
+    }
 }
 
 // out = a + b
 __global__ void k_add(const bf16_t* __restrict__ a, const bf16_t* __restrict__ b, bf16_t* __restrict__ out, int C,
                       Vol g)
 {
-    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= g.V * C) return;
-    const long p = pidx(g, e / C) * C + e % C;
-    out[p] = f2bf(bf2f(a[p]) + bf2f(b[p]));
+    // grid-stride: the element count can exceed 2^32 work-items
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < g.V * C; e += (long)gridDim.x * blockDim.x) {
+        const long p = pidx(g, e / C) * C + e % C;
+        out[p] = f2bf(bf2f(a[p]) + bf2f(b[p]));
+    }
 }
 
 // out = a where m > 0, else 0
 __global__ void k_mask(const bf16_t* __restrict__ a, const bf16_t* __restrict__ m, bf16_t* __restrict__ out, int C,
                        Vol g)
 {
-    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= g.V * C) return;
-    const long p = pidx(g, e / C) * C + e % C;
-    out[p] = bf2f(m[p]) > 0.f ? a[p] : (bf16_t)0;
+    // grid-stride: the element count can exceed 2^32 work-items
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < g.V * C; e += (long)gridDim.x * blockDim.x) {
+        const long p = pidx(g, e / C) * C + e % C;
+        out[p] = bf2f(m[p]) > 0.f ? a[p] : (bf16_t)0;
+    }
 }
 
 // Loss: mean squared error over the interior faces; gy = its gradient.
@@ -511,7 +555,9 @@ __global__ void k_apply_guess(SolverView s, const float* __restrict__ y, double*
     if (i < s.nx && j < s.ny) gz[e] = s.vz[e] + ((k >= 1 && k < s.nz) ? (double)(so * yv(2)) : 0.0);
 }
 
-inline unsigned nblk(long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+// blocks for n elements, capped at 2^22 (2^30 work-items, below the 2^32
+// limit of a dispatch); kernels whose n can exceed that loop grid-stride
+inline unsigned nblk(long n, int t = 256) { return (unsigned)std::min<long>((n + t - 1) / t, 1L << 22); }
 
 }  // namespace
 
@@ -676,6 +722,8 @@ void conv(int epi, int cout, const bf16_t* X, int cin, const bf16_t* W, const fl
 template <int NBO>
 void wgrad_o(int nbi, const bf16_t* X, const bf16_t* G, float* dW, const Vol& g, hipStream_t s)
 {
+    // up to 512 voxel chunks per tap (27 x 512 workgroups keep the staging
+    // latency hidden); each adds its 16 x 16 blocks to the FP32 gradient once
     const long vchunk = std::max<long>(2048, (g.V + 511) / 512 / 64 * 64);
     dim3 grid((unsigned)((g.V + vchunk - 1) / vchunk), 27);
     switch (nbi) {
@@ -694,8 +742,7 @@ void wgrad(int cout, int cin, const bf16_t* X, const bf16_t* G, float* dW, float
     case 4: wgrad_o<4>(cin / 16, X, G, dW, g, s); break;
     default: wgrad_o<8>(cin / 16, X, G, dW, g, s); break;
     }
-    dim3 grid((unsigned)std::min<long>(64, nblk(g.V)), cout);
-    k_bias_grad<<<grid, 256, 0, s>>>(G, cout, db, g);
+    k_bias_grad<<<(unsigned)std::min<long>(2048, (g.V * (cout / 8) + 255) / 256), 256, 0, s>>>(G, cout, db, g);
 }
 
 void refresh_bf16(ep_net* n)

@@ -76,6 +76,27 @@ def test_forward_matches_oracle(grid, base):
     n.close()
 
 
+@pytest.mark.parametrize("grid,base", [((67, 35, 29), 32), ((95, 63, 45), 16)], ids=["67x35x29-C32", "95x63x45-C16"])
+def test_forward_matches_oracle_many_blocks(grid, base):
+    """Volumes of many convolution blocks (16 x 4 x 4 voxels) with ragged
+    x blocks at some level (68 = 4 x 16 + 4 at level 0; 24 = 16 + 8 at level
+    2 of 96 x 64 x 48): every output voxel against the oracle."""
+    nx, ny, nz = grid
+    say("net forward", grid, base)
+    n = net(nx, ny, nz, base=base)
+    ps = random_net(n, base, seed=5)
+    r = np.random.Generator(np.random.PCG64(6))
+    x = r.standard_normal(n.dims + (16,))
+    n.set_sample(0, x=x)
+    y = n.forward(0)
+    yr, _ = W.forward(ps, x, store=W.bf16)
+    err = rel(y, yr)
+    say("forward rel err", err, "max", np.abs(y - yr).max() / np.abs(yr).max())
+    assert err < 2e-2
+    assert np.abs(y - yr).max() < 5e-2 * np.abs(yr).max()
+    n.close()
+
+
 @pytest.mark.parametrize("grid", GRIDS[1:], ids=["12x8x16", "13x9x11"])
 def test_gradient_matches_oracle(grid):
     nx, ny, nz = grid
