@@ -81,7 +81,8 @@ def workload(name):
     if name.startswith("3d-") and name.endswith("-warm"):
         n = int(name[3:-5])
         return c3_3d(n), (f"3d-{n}^3 pure shear, spherical weak inclusion, strain increment 5e-5, tol 1e-6; "
-                          "plain guess vs learned warm start (network trained on two other inclusion positions)")
+                          "plain guess vs learned warm start (network trained on the plastic increments of "
+                          "three 127^3 models with other inclusion positions)")
     if name.startswith("3d-"):
         n = int(name[3:])
         return c3_3d(n), f"3d-{n}^3 pure shear, spherical weak inclusion"
@@ -211,21 +212,29 @@ def net_flops_per_voxel(base):
     return 2 * 27 * (l0 + l1 / 8 + l2 / 64)
 
 
-def warm_compare(E, base_model, T, t_from, prec, steps_train=1200):
-    """Plain vs learned warm start on a 3D model: the network is trained on
-    trajectories of two models with other inclusion positions, then the
-    held-out model is solved both ways.  Returns the per-increment results."""
+def warm_compare(E, base_model, T, t_from, prec, train_n=127, steps_train=3000, lr=1e-3):
+    """Plain vs learned warm start.  The network (C = 32) is trained on the
+    plastic increments of three train_n^3 trajectories with other inclusion
+    positions (samples the solver generates itself); the held-out model at
+    the named size is then solved three ways: plain guesses, the network's
+    guesses under the residual gate (used when their physical residual is
+    below the plain guess's), and the network's guesses always used.  At
+    sizes up to 160^3 the run also measures the accuracy a guess needs: from
+    the plain run's states, guesses v_prev + beta * dv_true (dv_true the
+    plain run's converged change) for several beta, always used."""
     import numpy as np
     import torch
     n = base_model.nx
-    mk = lambda c: base_model.with_(incl_centre=c, max_iter=2_000_000)
-    train_models = [mk((0.06, -0.04, 0.03)), mk((-0.05, 0.05, -0.02))]
-    held = mk((0.02, 0.03, -0.04))
-    # scales of the features and targets from the first training trajectory
+    mk = lambda m, c: m.with_(incl_centre=c, max_iter=2_000_000)
+    tm = c3_3d_model(train_n)
+    train_models = [mk(tm, (0.06, -0.04, 0.03)), mk(tm, (-0.05, 0.05, -0.02)), mk(tm, (0.03, 0.06, 0.04))]
+    held = mk(base_model, (0.02, 0.03, -0.04))
+    Tt = max(T, 30)
+    # feature and target scales from the first training trajectory
     s = E.Solver(train_models[0], precision=prec)
     v0 = {k: s.get(k) for k in ("vx", "vy", "vz")}
     smax = emax = dvmax = 0.0
-    for k in range(T):
+    for k in range(Tt):
         s.load_step()
         v1 = {q: s.get(q) for q in v0}
         dvmax = max(dvmax, max(float(np.abs(v1[q] - v0[q]).max()) for q in v0))
@@ -235,70 +244,134 @@ def warm_compare(E, base_model, T, t_from, prec, steps_train=1200):
     s.close()
     scale = (smax, max(emax, 1e-12), max(dvmax, 1e-12), max(dvmax, 1e-12))
     log("feature scales", scale)
-    net = E.Net(n, n, n, base=32, max_samples=len(train_models) * T, scale=scale, seed=0)
+    net = E.Net(train_n, train_n, train_n, base=32, max_samples=len(train_models) * Tt, scale=scale, seed=0)
     t0 = time.perf_counter()
     slots = []
     for q, m in enumerate(train_models):
         s = E.Solver(m, precision=prec)
         net.reset()
         net.observe(s)
-        for k in range(T):
-            net.record(s, q * T + k)
-            s.load_step()
-            net.observe(s, q * T + k)
-            slots.append(q * T + k)
+        for k in range(Tt):
+            net.record(s, q * Tt + k)
+            st = s.load_step()
+            net.observe(s, q * Tt + k)
+            if st["iters"] > 0:          # elastic increments do not change the velocities
+                slots.append(q * Tt + k)
         s.close()
         log(f"training trajectory {q + 1}/{len(train_models)} generated ({time.perf_counter() - t0:.1f}s)")
     t1 = time.perf_counter()
-    losses = net.train(slots, steps_train, lr=3e-4)
+    losses = net.train(slots, steps_train, lr=lr)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t1
-    log(f"trained {steps_train} Adam steps in {train_s:.1f}s, loss {losses[:len(slots)].mean():.3e} -> "
-        f"{losses[-len(slots):].mean():.3e}")
+    ns = len(slots)
+    log(f"trained {steps_train} Adam steps on {ns} samples in {train_s:.1f}s, loss {losses[:ns].mean():.3e} -> "
+        f"{losses[-ns:].mean():.3e}")
+    if n != train_n:
+        # the convolutional weights serve any grid: an inference-only network
+        # of the held-out size takes the trained parameters
+        w = net.get_params()
+        net.close()
+        del net
+        torch.cuda.empty_cache()
+        net = E.Net(n, n, n, base=32, max_samples=0, scale=scale, seed=0)
+        net.set_params(w)
 
-    def solve(warm):
-        s = E.Solver(held, precision=prec)
-        if warm:
+    def solve(mode):
+        s = E.Solver(held, precision=prec, guess_accept=1e30 if mode == "always" else 0.0)
+        if mode != "plain":
             net.reset()
             net.observe(s)
-        its, secs, used, pred = [], [], [], []
+        its, secs, used, pred, rg = [], [], [], [], []
         for k in range(T):
             torch.cuda.synchronize()
             t = time.perf_counter()
-            if warm:
+            if mode != "plain":
                 net.predict(s)
                 torch.cuda.synchronize()
                 pred.append(time.perf_counter() - t)
             st = s.load_step()
-            if warm:
+            if mode != "plain":
                 net.observe(s)
             torch.cuda.synchronize()
             its.append(st["iters"])
             secs.append(time.perf_counter() - t)
             used.append(st["guess_used"])
+            rg.append(st["r_guess"] / st["r_ref"] if st["r_ref"] > 0 and mode != "plain" else None)
+            log(f"{mode} increment {k + 1}: iters {st['iters']} guess used {st['guess_used']} "
+                f"yielding {st['n_yield']} ({secs[-1]:.2f}s)")
         s.close()
-        return its, secs, used, pred
+        return its, secs, used, pred, rg
 
-    ip, sp, _, _ = solve(False)
-    iw, sw, used, pred = solve(True)
+    ip, sp, _, _, _ = solve("plain")
+    iw, sw, used, pred, rgw = solve("gate")
+    if n <= 160:
+        # guesses used without the gate (at larger sizes this costs minutes:
+        # the elastic increments the plain guess solves exactly then sweep)
+        ia, sa, _, preda, rga = solve("always")
+    else:
+        ia, sa, preda, rga = [0] * T, [0.0] * T, [], [None] * T
+    flops = net_flops_per_voxel(32) * net.nvox
     net.close()
-    log(f"plain iters {ip}")
-    log(f"warm  iters {iw}, guess used {used}")
     timed = slice(t_from, T)
     steps = T - t_from
-    pred_ms = 1e3 * sum(pred) / len(pred)
-    flops = net_flops_per_voxel(32) * net.nvox
-    return {
+    pred_ms = 1e3 * sum(pred + preda) / len(pred + preda)
+    out = {
         "grid": f"{n}^3", "increments_timed": f"{t_from + 1}..{T}", "cells": held.n_cells,
-        "plain": {"iters_per_step": sum(ip[timed]) / steps, "s_per_step": round(sum(sp[timed]) / steps, 4)},
+        "plain": {"iters_per_step": sum(ip[timed]) / steps, "s_per_step": round(sum(sp[timed]) / steps, 4),
+                  "iters": ip[timed]},
         "warm": {"iters_per_step": sum(iw[timed]) / steps, "s_per_step": round(sum(sw[timed]) / steps, 4),
-                 "guesses_used": sum(1 for u in used[timed] if u == 1)},
-        "training": {"samples": len(slots), "adam_steps": steps_train, "seconds": round(train_s, 2),
-                     "loss_first": float(losses[:len(slots)].mean()), "loss_last": float(losses[-len(slots):].mean())},
+                 "guesses_used": sum(1 for u in used[timed] if u == 1), "iters": iw[timed],
+                 "r_guess_over_r_ref": [None if x is None else round(x, 3) for x in rgw[timed]]},
+        "warm_always": None if n > 160 else {
+            "iters_per_step": sum(ia[timed]) / steps, "s_per_step": round(sum(sa[timed]) / steps, 4),
+            "iters": ia[timed], "r_guess_over_r_ref": [None if x is None else round(x, 3) for x in rga[timed]]},
+        "training": {"grid": f"{train_n}^3", "trajectories": len(train_models), "samples": ns,
+                     "adam_steps": steps_train, "lr": lr, "seconds": round(train_s, 2),
+                     "loss_first": float(losses[:ns].mean()), "loss_last": float(losses[-ns:].mean())},
         "inference": {"ms": round(pred_ms, 3), "flops": flops,
                       "tflops": round(flops / (pred_ms * 1e-3) / 1e12, 2)},
         "_iters_warm": iw, "_secs_warm": sw,
     }
+    if n <= 160:
+        out["guess_accuracy"] = guess_accuracy(E, held, prec, [k for k in range(t_from, T) if ip[k] > 0][:4])
+    return out
+
+
+def c3_3d_model(n):
+    from ep_workloads import c3_3d
+    return c3_3d(n)
+
+
+def guess_accuracy(E, m, prec, incs, betas=(0.5, 0.9, 0.99, 0.999)):
+    """Iterations of an increment started from v_prev + beta * dv_true (always
+    used), from the plain run's state before it (increment indices 0-based)."""
+    import numpy as np
+    names = ["vx", "vy", "vz"]
+    ro = ("lambda_dot", "tau_ii", "yield", "lambda_frozen", "tzz", "tzz_old")
+    a = E.Solver(m, precision=prec)
+    b = E.Solver(m, precision=prec, guess_accept=1e30)
+    out, done = {}, 0
+    for inc in incs:
+        while done < inc:
+            a.load_step()
+            done += 1
+        keep = {k: v for k, v in a.fields().items() if k not in ro}
+        prev = [keep[q] for q in names]
+        st = a.load_step()
+        done += 1
+        dv = [a.get(q) - p for q, p in zip(names, prev)]
+        row = {"plain": st["iters"], "frozen_at": st["frozen_at"], "yielding": st["n_yield"]}
+        for beta in betas:
+            for k, v in keep.items():
+                b.set(k, v)
+            b.set_guess(*[p + beta * d for p, d in zip(prev, dv)])
+            sb = b.load_step()
+            row[f"beta={beta:g}"] = sb["iters"]
+        log(f"guess accuracy, increment {inc + 1}: {row}")
+        out[str(inc + 1)] = row
+    a.close()
+    b.close()
+    return out
 
 
 def mirror_asymmetry(f):
@@ -375,7 +448,8 @@ def run_warm(args, E, name):
         "dtype": "f32" if prec == E.EP_FP32_FIELDS else "f64", "data": "synthetic",
         "config": {"workload": desc, "cells": w["cells"], "increments_timed": w["increments_timed"],
                    "precision": args.precision},
-        "plain": w["plain"], "warm": w["warm"], "training": w["training"],
+        "plain": w["plain"], "warm": w["warm"], "warm_always": w["warm_always"], "training": w["training"],
+        "guess_accuracy": w.get("guess_accuracy"),
         "roofline": {"bound": "mfma", "achieved": inf["tflops"], "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": round(inf["tflops"] / 2500.0, 5), "traffic": None,
                      "kernel": "warm-start network inference (bf16 MFMA convolutions)",

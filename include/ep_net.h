@@ -48,7 +48,9 @@ extern "C" {
 typedef struct ep_net_config {
     int   nx, ny, nz;        /* solver grid (cells), each >= 4 */
     int   base;              /* level-0 channels C: 16 or 32 */
-    int   max_samples;       /* training samples held on the device (>= 1) */
+    int   max_samples;       /* training samples held on the device (>= 0); 0: an inference-only
+                                network (no sample slots, no activation gradients: about half
+                                the workspace); ep_net_train and ep_net_gradient then fail */
     float scale[4];          /* stress, plastic strain, input velocity change, output velocity change (> 0) */
     int   seed;              /* weight initialisation: He-normal, zero head */
 } ep_net_config;

@@ -614,7 +614,7 @@ int validate_cfg(const ep_net_config* c)
     if (!c) return EP_EINVAL;
     if (c->nx < 4 || c->ny < 4 || c->nz < 4) return EP_EINVAL;
     if (c->base != 16 && c->base != 32) return EP_EINVAL;
-    if (c->max_samples < 1) return EP_EINVAL;
+    if (c->max_samples < 0) return EP_EINVAL;
     for (int q = 0; q < 4; ++q)
         if (!(c->scale[q] > 0)) return EP_EINVAL;
     return EP_OK;
@@ -669,7 +669,8 @@ size_t net_carve(const ep_net_config* c, ep_net* n, char* base)
     const Vol* gg[21] = {&g0, &g0, &g0, &g0, &g0, &g1, &g1, &g1, &g1, &g1, &g2, &g2, &g2, &g2, &g1, &g1, &g1, &g1, &g0,
                          &g0, &g0};
     const int cg[21] = {COUT, C, C, C, C2, C2, C2, C2, C2, C4, C4, C4, C4, C2, C2, C2, C2, C, C, C, C};
-    for (int q = 0; q < 21; ++q) G[q] = act(*gg[q], cg[q]);
+    // gradient tensors only for a network that trains (max_samples > 0)
+    for (int q = 0; q < 21; ++q) G[q] = c->max_samples > 0 ? act(*gg[q], cg[q]) : nullptr;
     bf16_t* sx = (bf16_t*)take((size_t)c->max_samples * g0.Vp * 16 * 2);
     float* stg = (float*)take((size_t)c->max_samples * g0.V * 4 * 4);
     double* vlast = (double*)take((size_t)g0.V * 3 * 8);
