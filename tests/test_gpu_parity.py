@@ -451,6 +451,42 @@ def test_device_guess(ndim):
         s.close()
 
 
+def test_guess_accuracy_sets_the_gain():
+    """What a starting guess gains (the learned warm start feeds this
+    mechanism): a plastic increment of a 3D model without frozen plasticity
+    restarted from v_prev + beta * dv_true (dv_true its converged change)
+    takes fewer sweeps the closer beta is to 1, down to none for beta = 1,
+    and ends in the plain increment's state."""
+    m, names = _guess_model(3)
+    ro = ("lambda_dot", "tau_ii", "yield", "lambda_frozen", "tzz", "tzz_old")
+    say("guess accuracy")
+    a = solver(m)
+    b = solver(m, guess_accept=1e30)
+    for _ in range(3):
+        a.load_step()
+    keep = {k: v for k, v in a.fields().items() if k not in ro}
+    prev = [keep[q] for q in names]
+    sa = a.load_step()
+    assert sa["n_yield"] > 0 and sa["iters"] > 50
+    fa = a.fields(it_names(m))
+    dv = [a.get(q) - p for q, p in zip(names, prev)]
+    its = {}
+    for beta in (0.0, 0.9, 0.99, 1.0):
+        for k, v in keep.items():
+            b.set(k, v)
+        b.set_guess(*[p + beta * d for p, d in zip(prev, dv)])
+        sb = b.load_step()
+        assert sb["status"] == 0
+        its[beta] = sb["iters"]
+        compare(m, b.fields(it_names(m)), fa, it_names(m), 1e-6)
+    say("sweeps by beta", its)
+    assert its[0.0] == sa["iters"]
+    assert its[1.0] == 0
+    assert its[0.99] < its[0.9] < its[0.0]
+    a.close()
+    b.close()
+
+
 FROZEN_CASES = [
     ("3d-fp64-unfused", 3, FP64, 2), ("3d-fp64-fused", 3, FP64, 1), ("3d-fp32", 3, FP32, 0),
     ("2d-fp64-unfused", 2, FP64, 2),
