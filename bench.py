@@ -73,11 +73,19 @@ def workload(name):
     if name.startswith("e2-"):
         from ep_workloads import e2_symmetry
         n = int(name[3:])
-        # tol 1e-9: the FP64 rounding floor of the normalised residual of the
-        # small increments at this resolution lies near 1e-10
-        return e2_symmetry(n, tol=1e-9), (f"symmetry study: 2d-383x191 (2:1 domain) pure shear, uniform c=2e-3, G=1, "
-                                          f"K=2, phi=30, mu_s=1e6, central pressure anomaly p=c/2 (r=0.1), total "
-                                          f"strain 2e-3 in {n} increments, tol 1e-9, FP64")
+        # tol 1e-7: the FP64 physical residual (the acceptance certificate) of
+        # this setup's small increments has a floor of 0.5-1e-8 of the
+        # reference, rising with the stress: the pseudo-time trial
+        # tau/(G~ dtau) + S is about 1e6 here against S of about 45, so
+        # tau = T / (D + Lambda) keeps some 11 significant digits.  Frozen
+        # plasticity after 16 nx iterations: the localising increments of this
+        # setup (uniform cohesion, perfect plasticity) have no unique solution
+        # and the iteration wanders at about twice the reference residual
+        # without it
+        return e2_symmetry(n, tol=1e-7).with_(freeze_iter=16 * 383), (
+            f"symmetry study: 2d-383x191 (2:1 domain) pure shear, uniform c=2e-3, G=1, K=2, phi=30, mu_s=1e6, "
+            f"central pressure anomaly p=c/2 (r=0.1), total strain 2e-3 in {n} increments, tol 1e-7, frozen "
+            f"plasticity after 16 nx iterations, FP64")
     if name.startswith("3d-") and name.endswith("-warm"):
         n = int(name[3:-5])
         return c3_3d(n), (f"3d-{n}^3 pure shear, spherical weak inclusion, strain increment 5e-5, tol 1e-6; "

@@ -1271,6 +1271,10 @@ int orc_load_step(orc_state* s, orc_stats* st)
                  * meet the tolerance too; that evaluation is the accepted
                  * state's certificate, and its stresses the accepted ones */
                 double cert = orc_sweep(s, 1);
+                if (s->prm.progress > 0 && it % s->prm.progress == 0) {
+                    fprintf(stderr, "oracle: iteration %d certificate/ref %.3e\n", it, cert / st->ref);
+                    fflush(stderr);
+                }
                 if (cert <= s->prm.tol * st->ref) {
                     st->cert = cert;
                     commit_evaluated_stresses(s);
