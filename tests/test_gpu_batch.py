@@ -135,6 +135,48 @@ def test_batch_matches_single_and_oracle(prec, freeze):
     b.close()
 
 
+def larger_models():
+    """Models of many tiles with ragged edges (127^2, 95 x 130, 160 x 73);
+    each yields within three increments (the fourth localises and needs
+    frozen plasticity)."""
+    base = dict(ndim=2, dt=2e-4, tol=1e-8, n_check=10, steps=3)
+    return [Model(nx=127, ny=127, phi_deg=30.0, incl_radius=0.12, incl_centre=(0.06, -0.03, 0), **base),
+            Model(nx=95, ny=130, ly=1.3, phi_deg=25.0, c0=1.5e-3, incl_radius=0.15, incl_centre=(-0.05, 0.08, 0),
+                  **base),
+            Model(nx=160, ny=73, lx=2.0, phi_deg=35.0, c0=2e-3, incl_radius=0.1, incl_centre=(0.1, 0.02, 0), **base)]
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32], ids=["fp64", "fp32"])
+def test_batch_of_larger_models_matches_oracle(prec):
+    """A batch of three models of up to 160 x 73 cells (18 to 30 tiles each)
+    over three increments against the oracle: FP64 with equal iteration
+    counts (or a tie at the tolerance level) and yielding cells, fields and
+    accumulators within 1e-6; FP32 fields within 1e-4."""
+    models = larger_models()
+    say("batch of larger models, prec", prec)
+    b, out, _ = run_batch(models, prec, 3)
+    tol = 1e-6 if prec == FP64 else 1e-4
+    for i, m in enumerate(models):
+        assert max(out[n][i]["n_yield"] for n in range(3)) > 50, i
+        view = b.model(i)
+        o = Oracle(m)
+        so, hist = [], []
+        for _ in range(3):
+            o.record_history()
+            so.append(o.load_step())
+            hist.append(o.history() / so[-1]["ref"])
+        for n in range(3):
+            assert out[n][i]["status"] == 0 and so[n]["status"] == 0, (i, n)
+            if prec == FP64:
+                assert iters_agree(out[n][i]["iters"], so[n]["iters"], hist[n], m), (i, n, out[n][i]["iters"],
+                                                                                      so[n]["iters"])
+                assert out[n][i]["n_yield"] == so[n]["n_yield"], (i, n)
+        compare(m, view.fields(IT2), o.fields(IT2), IT2, tol, f"model {i}")
+        compare_accumulators(m, view.fields(accum_names(m)), o.fields(accum_names(m)), tol, f"model {i}")
+        o.close()
+    b.close()
+
+
 def test_batch_tuned_shapes_give_identical_results():
     models = batch_models()
     b0, out0, shapes0 = run_batch(models, FP32, 3)
