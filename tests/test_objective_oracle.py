@@ -316,3 +316,52 @@ def test_rigid_rotation_of_linear_fields_3d_matches_the_continuum_rate():
         np.testing.assert_allclose(got[inner], expected(name, X, Y, Z)[inner], rtol=1e-7, atol=1e-9,
                                    err_msg=name)
     o.close()
+
+
+def _checkerboard(shape, amp):
+    """Face velocities alternating in sign along every axis: their means at
+    centres and shear points vanish exactly (no advection), their
+    differences do not (vorticity at every shear point)."""
+    return amp * (-1.0) ** np.indices(shape).sum(axis=0)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_rotation_terms_preserve_j2_in_nonhomogeneous_states(ndim):
+    """The co-rotational terms Wτ - τW do no work on the stress:
+    τ : (Wτ - τW) = 0 pointwise for any symmetric τ and antisymmetric W.  On
+    the staggered grid the centre terms (4-point means of shear products) and
+    the shear-point terms (vorticity times 4-point means of centre stresses,
+    and in 3D products of means of the other shear components) pair up so
+    that the grid sum of τ : τ^R vanishes exactly for any stress field, not
+    only homogeneous or linear ones.  Random non-homogeneous stresses with a
+    checkerboard velocity field (vorticity everywhere, zero advection): the
+    sum over centres and (twice) over shear points cancels to rounding while
+    each part is of the size of the terms; a dropped term, a wrong sign or a
+    mean taken over other points breaks the cancellation."""
+    from fieldtools import shapes
+    if ndim == 2:
+        m = Model(ndim=2, nx=13, ny=11, lx=1.3, dt=1e-3, objective=1)
+    else:
+        m = Model(ndim=3, nx=9, ny=8, nz=7, ly=0.9, lz=0.8, dt=1e-3, objective=1)
+    sh = shapes(m)
+    r = np.random.Generator(np.random.PCG64(11))
+    shear = ["txy"] + (["txz", "tyz"] if ndim == 3 else [])
+    tau = {k: r.standard_normal(sh[k]) * 1e-3 for k in ["txx", "tyy"] + shear}
+    p = r.standard_normal(sh["p"]) * 1e-3
+    vel = {"vx": _checkerboard(sh["vx"], 0.7), "vy": _checkerboard(sh["vy"], -0.4)}
+    if ndim == 3:
+        vel["vz"] = _checkerboard(sh["vz"], 0.3)
+    o = Oracle(m)
+    for k, v in list(tau.items()) + list(vel.items()) + [("p", p)]:
+        o.set(k, v.ravel())
+    cent = ["txx", "tyy"] + (["tzz"] if ndim == 3 else [])
+    t0 = {k: o.get(k).reshape(sh[k]) for k in cent + shear}
+    o.objective_update()
+    rate = {k: (o.get(k).reshape(sh[k]) - t0[k]) / m.dt for k in cent + shear}
+    assert np.array_equal(o.get("p").reshape(sh["p"]), p)          # no advection
+    c = sum((t0[k] * rate[k]).sum() for k in cent)
+    s = 2.0 * sum((t0[k] * rate[k]).sum() for k in shear)
+    size = sum(np.abs(t0[k] * rate[k]).sum() for k in cent) + 2.0 * sum(np.abs(t0[k] * rate[k]).sum() for k in shear)
+    assert abs(c) > 1e-3 * size and abs(s) > 1e-3 * size       # both parts work ...
+    assert abs(c + s) <= 1e-13 * size, (c, s, size)              # ... and cancel
+    o.close()
