@@ -129,3 +129,27 @@ def test_freeze_accepted_in_every_sweep_form(E, case):
     p = E.params_from_model(m, sweep=E.EP_SWEEP_UNFUSED if case == "unfused" else E.EP_SWEEP_AUTO)
     n = C.c_size_t(0)
     assert E.lib().ep_workspace_size(C.byref(p), C.byref(n)) == E.EP_OK
+
+
+def _net_config(E, n, samples, base=32):
+    c = E.ep_net_config()
+    c.nx = c.ny = c.nz = n
+    c.base, c.max_samples, c.seed = base, samples, 0
+    for q, v in enumerate((1e-3, 1e-4, 1e-5, 1e-5)):
+        c.scale[q] = v
+    return c
+
+
+def test_inference_only_network_needs_less_workspace(E):
+    """max_samples = 0 holds no sample slots and no activation gradients:
+    at 511^3 about half the workspace of a one-sample training network;
+    negative counts are rejected."""
+    L = E.lib()
+    sizes = {}
+    for s in (0, 1, 2):
+        b = C.c_size_t(0)
+        assert L.ep_net_workspace_size(C.byref(_net_config(E, 511, s)), C.byref(b)) == E.EP_OK
+        sizes[s] = b.value
+    assert sizes[0] < 0.55 * sizes[1] and sizes[1] < sizes[2]
+    b = C.c_size_t(0)
+    assert L.ep_net_workspace_size(C.byref(_net_config(E, 31, -1)), C.byref(b)) == E.EP_EINVAL

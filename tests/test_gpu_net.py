@@ -10,6 +10,8 @@ reference: outputs and gradients within 2e-2 in L2 norm, and every entry of
 a layer's gradient within 3e-2 of that layer's largest entry; features within
 one bfloat16 unit; the Adam update to FP32 rounding.
 """
+import ctypes as C
+
 import numpy as np
 import pytest
 
@@ -236,3 +238,35 @@ def test_warm_start_pipeline_converges_to_the_plain_solution():
         err = np.abs(a[k] - b[k]).max() / max(np.abs(a[k]).max(), 1e-30)
         assert err < 1e-3, (k, err)
     n.close()
+
+
+def test_inference_only_network_matches_training_network():
+    """An inference-only network (max_samples = 0) with the parameters of a
+    training network gives bitwise the same forward pass and the same guess;
+    its training entry points are rejected."""
+    from paper_2305_01701_amd.ep import Solver, EP_EINVAL, lib
+    N = 15
+    m = Model(ndim=3, nx=N, ny=N, nz=N, dt=2e-4, tol=1e-6, n_check=10, incl_radius=0.2,
+              incl_centre=(0.05, -0.03, 0.02))
+    a = net(N, N, N, base=16, samples=1, scale=(3.5e-3, 3e-2, 0.5, 0.5))
+    ps = random_net(a, 16, seed=4)
+    b = net(N, N, N, base=16, samples=0, scale=(3.5e-3, 3e-2, 0.5, 0.5))
+    b.set_params(to_flat(ps))
+    sa, sb = Solver(m), Solver(m)
+    for s in (sa, sb):
+        for _ in range(3):
+            assert s.load_step()["status"] == 0
+    for n_, s in ((a, sa), (b, sb)):
+        n_.reset()
+        n_.observe(s)
+        n_.record(s, -1)
+    ya, yb = a.forward(-1), b.forward(-1)
+    assert np.array_equal(ya, yb)
+    a.predict(sa)
+    b.predict(sb)
+    fa, fb = sa.load_step(), sb.load_step()
+    assert fa["guess_used"] == fb["guess_used"] and fa["iters"] == fb["iters"] and fa["r_guess"] == fb["r_guess"]
+    slots = np.zeros(1, dtype=np.int32)
+    assert lib().ep_net_train(b.h, slots.ctypes.data_as(C.POINTER(C.c_int)), 1, 1, 1e-3, None) == EP_EINVAL
+    for x in (a, b, sa, sb):
+        x.close()
