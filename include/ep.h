@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define EP_ABI_VERSION 2
+#define EP_ABI_VERSION 3
 
 /* return codes */
 #define EP_OK          0
@@ -190,14 +190,18 @@ int ep_workspace_size(const ep_params* p, size_t* bytes);
 
 /* Create a solver in a caller-owned workspace.
  *  cohesion: n_cells FP64 values (x fastest) or NULL for 0; copied.
+ *  shear: n_cells FP64 shear moduli (x fastest), each in (0, p->shear], or NULL
+ *    for the uniform p->shear; copied; the same as ep_set_shear_modulus right
+ *    after creation (the heterogeneous setups of the initial-conditions
+ *    section).
  *  d_workspace/ws_bytes: device memory from the caller, >= ep_workspace_size.
  *  stream: hipStream_t (as void*) used for all work of the handle.
  * Initial state (model configuration section): p = tau = 0 and velocities
  * equal to the background pure-shear field v = erate * x (domain centred).
  * Errors: EP_EINVAL (psi outside [0, phi], cfl >= 1/sqrt(ndim), a size < 3, K, G, dt,
- * tol or visc not > 0, NULL out), EP_ENOMEM (workspace too small),
- * EP_EDEVICE. */
-int ep_init(const ep_params* p, const double* cohesion, void* d_workspace, size_t ws_bytes,
+ * tol or visc not > 0, NULL out, a shear modulus out of range), EP_ENOMEM (workspace too
+ * small), EP_EDEVICE. */
+int ep_init(const ep_params* p, const double* cohesion, const double* shear, void* d_workspace, size_t ws_bytes,
             void* stream, ep_handle** out);
 
 /* Solve one load increment: save the increment's starting stresses (p^,

@@ -943,8 +943,8 @@ int ep_workspace_size(const ep_params* p, size_t* bytes)
     return EP_OK;
 }
 
-int ep_init(const ep_params* p, const double* cohesion, void* d_workspace, size_t ws_bytes, void* stream,
-            ep_handle** out)
+int ep_init(const ep_params* p, const double* cohesion, const double* shear, void* d_workspace, size_t ws_bytes,
+            void* stream, ep_handle** out)
 {
     if (!out) return EP_EINVAL;
     *out = nullptr;
@@ -952,7 +952,19 @@ int ep_init(const ep_params* p, const double* cohesion, void* d_workspace, size_
     if (rc) return rc;
     if (!d_workspace || ws_bytes < carve(p, nullptr, nullptr)) return EP_ENOMEM;
     if (((uintptr_t)d_workspace & 255) != 0) return EP_EINVAL;
-    return handle_create(p, cohesion, (char*)d_workspace, (hipStream_t)stream, out);
+    if (shear) {            // checked before any device work
+        const long nc = (long)p->nx * p->ny * (p->ndim == 3 ? p->nz : 1);
+        for (long c = 0; c < nc; ++c)
+            if (!(shear[c] > 0.0) || !(shear[c] <= p->shear)) return EP_EINVAL;
+    }
+    rc = handle_create(p, cohesion, (char*)d_workspace, (hipStream_t)stream, out);
+    if (rc || !shear) return rc;
+    rc = ep_set_shear_modulus(*out, shear);
+    if (rc) {
+        handle_free(*out);
+        *out = nullptr;
+    }
+    return rc;
 }
 
 void ep_destroy(ep_handle* h)

@@ -97,7 +97,8 @@ def lib():
         vp = C.c_void_p
         L.ep_abi_version.restype = C.c_int
         L.ep_workspace_size.argtypes = [C.POINTER(ep_params), C.POINTER(C.c_size_t)]
-        L.ep_init.argtypes = [C.POINTER(ep_params), C.POINTER(C.c_double), vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.ep_init.argtypes = [C.POINTER(ep_params), C.POINTER(C.c_double), C.POINTER(C.c_double), vp, C.c_size_t, vp,
+                              C.POINTER(vp)]
         L.ep_load_step.argtypes = [vp, C.POINTER(ep_step_stats)]
         L.ep_sweep.argtypes = [vp, C.c_int, C.POINTER(C.c_double)]
         L.ep_residual.argtypes = [vp, C.POINTER(ep_residual_info)]
@@ -167,11 +168,14 @@ def ep_workspace_size(p: ep_params) -> int:
     return n.value
 
 
-def ep_init(p: ep_params, cohesion: Optional[np.ndarray], d_workspace: int, ws_bytes: int, stream: int):
+def ep_init(p: ep_params, cohesion: Optional[np.ndarray], d_workspace: int, ws_bytes: int, stream: int,
+            shear: Optional[np.ndarray] = None):
     h = C.c_void_p()
     coh = None if cohesion is None else np.ascontiguousarray(cohesion, dtype=np.float64)
     cp = None if coh is None else coh.ctypes.data_as(C.POINTER(C.c_double))
-    rc = lib().ep_init(C.byref(p), cp, C.c_void_p(d_workspace), ws_bytes, C.c_void_p(stream), C.byref(h))
+    sh = None if shear is None else np.ascontiguousarray(shear, dtype=np.float64)
+    sp = None if sh is None else sh.ctypes.data_as(C.POINTER(C.c_double))
+    rc = lib().ep_init(C.byref(p), cp, sp, C.c_void_p(d_workspace), ws_bytes, C.c_void_p(stream), C.byref(h))
     return rc, h
 
 
@@ -397,7 +401,8 @@ class Solver(ModelView):
 
     def __init__(self, model, cohesion: Optional[np.ndarray] = None, precision: int = EP_FP64,
                  sweep: int = EP_SWEEP_AUTO, fp32_switch: float = 0.0, fp32_stall: int = 0,
-                 guess_accept: float = 0.0, device: str = "cuda:0", stream=None):
+                 guess_accept: float = 0.0, device: str = "cuda:0", stream=None,
+                 shear: Optional[np.ndarray] = None):
         import torch
         if not torch.cuda.is_available():
             raise EpError("no GPU visible: the solver runs only on the device")
@@ -414,7 +419,7 @@ class Solver(ModelView):
             from ep_workloads import cohesion_field
             cohesion = cohesion_field(model)
         with torch.cuda.device(self.device):
-            rc, h = ep_init(self.params, cohesion, base, self.ws_bytes, self.stream.cuda_stream)
+            rc, h = ep_init(self.params, cohesion, base, self.ws_bytes, self.stream.cuda_stream, shear)
         if rc != EP_OK:
             raise EpError(f"ep_init failed with {rc}")
         self.h = h

@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol(E):
 
 
 def test_abi_version(E):
-    assert E.ep_abi_version() == 2
+    assert E.ep_abi_version() == 3
 
 
 def test_workspace_size_scales_with_grid_and_precision(E):
@@ -153,3 +153,17 @@ def test_inference_only_network_needs_less_workspace(E):
     assert sizes[0] < 0.55 * sizes[1] and sizes[1] < sizes[2]
     b = C.c_size_t(0)
     assert L.ep_net_workspace_size(C.byref(_net_config(E, 31, -1)), C.byref(b)) == E.EP_EINVAL
+
+
+def test_init_rejects_out_of_range_shear_before_device_work(E):
+    """A per-cell shear modulus outside (0, shear] fails at ep_init before the
+    workspace (here a dummy address) is touched."""
+    import numpy as np
+    m = c1_small_2d()
+    p = E.params_from_model(m)
+    need = E.ep_workspace_size(p)
+    for bad in (0.0, -1.0, 2.0 * m.shear, float("nan")):
+        g = np.full(m.nx * m.ny, m.shear)
+        g[17] = bad
+        rc, h = E.ep_init(p, None, 256, need, 0, shear=g)
+        assert rc == E.EP_EINVAL and not h.value, bad

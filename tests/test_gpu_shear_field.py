@@ -114,6 +114,29 @@ def test_rejected_fields():
     g.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_shear_field_at_init_equals_setting_it_after(prec):
+    """ep_init with a per-cell shear modulus is ep_init followed by
+    ep_set_shear_modulus: bitwise the same increments (3D, fused sweep)."""
+    from paper_2305_01701_amd.ep import Solver
+    from ep_workloads import cohesion_field
+    m = Model(ndim=3, nx=17, ny=15, nz=13, shear=1.2, dt=2e-4, tol=1e-8, n_check=10, incl_radius=0.25,
+              incl_centre=(0.04, -0.03, 0.02))
+    G = gaussian_G3(m)
+    a = Solver(m, cohesion_field(m), precision=prec, shear=G)
+    b = Solver(m, cohesion_field(m), precision=prec)
+    b.set_shear_modulus(G)
+    for n in range(4):
+        sa, sb = a.load_step(), b.load_step()
+        assert sa["status"] == 0 and sa["iters"] == sb["iters"], n
+    fa, fb = a.fields(it_names(m)), b.fields(it_names(m))
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
+    assert sa["n_yield"] > 0
+    a.close()
+    b.close()
+
+
 def gaussian_G3(m, centre=(0.06, -0.04, 0.03)):
     """3D: G from 1 near the centre to 1.2 towards the walls, off-centre."""
     ax = [-0.5 * e + (np.arange(n) + 0.5) * (e / n) for e, n in ((m.lx, m.nx), (m.ly, m.ny), (m.lz, m.nz))]
