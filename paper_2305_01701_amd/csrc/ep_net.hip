@@ -161,8 +161,18 @@ __global__ __launch_bounds__(256) void k_conv(const bf16_t* __restrict__ X, int 
             // (A) and of output channel r (B); A and B share the lane-to-
             // channel map, so the reduction covers the 32 channels whatever
             // order the matrix core takes them in
+            // the weights of tap t+1 are loaded while tap t computes
+            const bf16_t* wl = Wt + (long)r * 27 * cin + c0 + kq * 8;
+            const long wstep = 16L * 27 * cin;                   // next output-channel block
+            b8 bw[NB];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) bw[nb] = ld_b8(wl + nb * wstep);
             for (int t = 0; t < 27; ++t) {
                 const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;     // 0..2: tap offset + 1
+                b8 bn[NB];
+                const int tn = t + 1 < 27 ? t + 1 : t;
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) bn[nb] = ld_b8(wl + nb * wstep + (long)tn * cin);
                 b8 a[4];
 #pragma unroll
                 for (int mb = 0; mb < 4; ++mb) {
@@ -170,12 +180,12 @@ __global__ __launch_bounds__(256) void k_conv(const bf16_t* __restrict__ X, int 
                     a[mb] = ld_b8(tile + tv * CT_ROW + kq * 8);
                 }
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb) {
-                    const b8 bw = ld_b8(Wt + ((long)(nb * 16 + r) * 27 + t) * cin + c0 + kq * 8);
+                for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
                     for (int mb = 0; mb < 4; ++mb)
-                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], bw, acc[mb][nb], 0, 0, 0);
-                }
+                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], bw[nb], acc[mb][nb], 0, 0, 0);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) bw[nb] = bn[nb];
             }
         } else {
             // a 16-channel chunk (the 16-channel input layer): K = 16
