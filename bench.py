@@ -75,9 +75,8 @@ def workload(name):
         n = int(name[3:])
         # tol 1e-7: the FP64 physical residual (the acceptance certificate) of
         # this setup's small increments has a floor of 0.5-1e-8 of the
-        # reference, rising with the stress: the pseudo-time trial
-        # tau/(G~ dtau) + S is about 1e6 here against S of about 45, so
-        # tau = T / (D + Lambda) keeps some 11 significant digits.  Frozen
+        # reference, rising with the stress, while the iteration residual
+        # reaches 1e-11 of it.  Frozen
         # plasticity after 16 nx iterations: the localising increments of this
         # setup (uniform cohesion, perfect plasticity) have no unique solution
         # and the iteration wanders at about twice the reference residual
