@@ -73,10 +73,10 @@ def workload(name):
     if name.startswith("e2-"):
         from ep_workloads import e2_symmetry
         n = int(name[3:])
-        # tol 1e-7: the FP64 physical residual (the acceptance certificate) of
-        # this setup's small increments has a floor of 0.5-1e-8 of the
-        # reference, rising with the stress, while the iteration residual
-        # reaches 1e-11 of it.  Frozen
+        # tol 1e-7: at this resolution the FP64 physical residual (the
+        # acceptance certificate) of this setup's small increments stalls
+        # above 1e-9 of the reference, and above 1e-8 later in the schedule,
+        # while the iteration residual reaches 1e-11 of it.  Frozen
         # plasticity after 16 nx iterations: the localising increments of this
         # setup (uniform cohesion, perfect plasticity) have no unique solution
         # and the iteration wanders at about twice the reference residual
