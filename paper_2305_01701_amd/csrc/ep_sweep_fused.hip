@@ -488,19 +488,25 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
     else body(std::false_type{});
 }
 
-// Tile shapes and workgroup sizes.  FP32: 48 x 10 columns; 768 threads
-// cover the 52 x 14 halo plane (728 points) and every later stage in a
-// single pass, so no wave does a second round while the others wait at the
-// stage barrier; 73 KB of LDS, two workgroups per CU.  Rows of 52 values
-// touch fewer partly used 128-byte lines per value than the 36 of a 32-wide
-// tile (measured at 511^3: 2.14x against 2.35x the algorithmic reads,
-// 4.10 against 4.30 ms per sweep; 64 x 7, 56 x 8, 40 x 13 and 48 x 9 were
-// slower).
-template <typename R> struct Tile3;
-// E: waves per SIMD to fit in registers (two FP32 workgroups per CU).
-template <> struct Tile3<float> { static constexpr int X = 48, Y = 10, Z = 32, T = 768, E = 6; };
-// FP64: 16 x 8 tiles (52 KB of LDS, three workgroups per CU).
-template <> struct Tile3<double> { static constexpr int X = 16, Y = 8, Z = 32, T = 256, E = 3; };
+// Tile shapes and workgroup sizes (X, Y: column; Z: planes per chunk; T:
+// threads; E: waves per SIMD to fit in registers, two FP32 workgroups per
+// CU).  FP32 has two shapes, both with 768 threads covering the halo plane
+// and every later stage in a single pass (no wave does a second round while
+// the others wait at a stage barrier), 72-73 KB of LDS:
+//  - 48 x 10 (52 x 14 = 728 plane points): rows of 52 values touch fewer
+//    partly used 128-byte lines per value than the 36 of a 32-wide tile
+//    (measured at 511^3: 2.14x against 2.35x the algorithmic reads, 4.10
+//    against 4.30 ms per sweep; 64 x 7, 56 x 8, 40 x 13 and 48 x 9 slower);
+//  - 32 x 16 (36 x 20 = 720 points), which fits grids of 32-cell multiples
+//    with fewer workgroups (255^3: 1024 workgroups, two full rounds of 512,
+//    0.585 ms, against 1248 and 0.618 ms for 48 x 10).
+// FP64: 16 x 8 tiles (48 KB of LDS, three workgroups per CU).
+template <int X_, int Y_, int Z_, int T_, int E_> struct Tile {
+    static constexpr int X = X_, Y = Y_, Z = Z_, T = T_, E = E_;
+};
+using TileF_wide = Tile<48, 10, 32, 768, 6>;
+using TileF_square = Tile<32, 16, 32, 768, 6>;
+using TileD = Tile<16, 8, 32, 256, 3>;
 
 // first and one-past-last tile index along an axis whose tiles lie strictly
 // inside with their 2-point halo: 3 <= i0 and i0 + T + 2 <= n
@@ -512,10 +518,16 @@ inline void interior_range(int n, int T, int nb, int& b0, int& b1)
     if (b1 < b0) b1 = b0;
 }
 
-template <typename R, int MODE>
+template <typename S>
+long tile_count(int nx, int ny, int nz)
+{
+    return (long)((nx + S::X - 1) / S::X) * ((ny + S::Y - 1) / S::Y) * ((nz + S::Z - 1) / S::Z);
+}
+
+template <typename S, typename R, int MODE>
 void run_3d(const SweepArgs<R>& a, hipStream_t s)
 {
-    constexpr int TX = Tile3<R>::X, TY = Tile3<R>::Y, ZC = Tile3<R>::Z, NT = Tile3<R>::T, WPE = Tile3<R>::E;
+    constexpr int TX = S::X, TY = S::Y, ZC = S::Z, NT = S::T, WPE = S::E;
     TileSet ts;
     ts.nbx = (a.nx + TX - 1) / TX;
     ts.nby = (a.ny + TY - 1) / TY;
@@ -525,6 +537,36 @@ void run_3d(const SweepArgs<R>& a, hipStream_t s)
     const int nb = ts.nbx * ts.nby * ts.nbz;
     if (a.igdc) k_fused_3d<R, TX, TY, ZC, MODE, NT, WPE, true><<<nb, NT, 0, s>>>(a, ts);
     else k_fused_3d<R, TX, TY, ZC, MODE, NT, WPE, false><<<nb, NT, 0, s>>>(a, ts);
+}
+
+// Compute units of the current device (two FP32 workgroups run on each).
+int device_cus()
+{
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return 256;
+    }
+    return n;
+}
+
+// FP32 tile shape of a grid: rounds of resident workgroups times the cost of
+// a round, a 48 x 10 round costing 0.85 of a 32 x 16 one (measured at 511^3:
+// 18 rounds in 4.10 ms against 16 in 4.30 ms).
+bool wide_tile(int nx, int ny, int nz)
+{
+    static const int resident = 2 * device_cus();
+    const long rw = (tile_count<TileF_wide>(nx, ny, nz) + resident - 1) / resident;
+    const long rs = (tile_count<TileF_square>(nx, ny, nz) + resident - 1) / resident;
+    return 0.85 * (double)rw <= (double)rs;
+}
+
+template <typename R, int MODE>
+void run_3d(const SweepArgs<R>& a, hipStream_t s)
+{
+    if constexpr (sizeof(R) == 8) run_3d<TileD, R, MODE>(a, s);
+    else if (wide_tile(a.nx, a.ny, a.nz)) run_3d<TileF_wide, R, MODE>(a, s);
+    else run_3d<TileF_square, R, MODE>(a, s);
 }
 
 
