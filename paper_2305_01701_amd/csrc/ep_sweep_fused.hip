@@ -317,17 +317,16 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
                 const R nS2 = R(0.5) * (Sxx * Sxx + Syy * Syy + Szz * Szz);
                 const R sh2 = Sxyb * Sxyb + Sxzb * Sxzb + Syzb * Syzb;
                 const R ptr = pn;
-                R lam = centre_return(R(0.5) * (Txx * Txx + Tyy * Tyy + Tzz * Tzz), nS2, sh2, Dp, invDp, Dc, invDc,
-                                      pn, cc[u], a.A, a.B, a.Cik, a.vp, a.blend);
                 const bool own = la >= 2 && la < TX + 2 && lbb >= 2 && lbb < TY + 2 && c >= k0 && c < k1;
-                if (a.lam_mode != LAM_COMPUTE) {                 // frozen plasticity
-                    if (a.lam_mode == LAM_FROZEN) {
-                        lam = ld(a.lam + sz * c, ro[u]);
-                        // dilatancy of the held Lambda: lamdot = Lambda sqrt(J2(S)) / (Dp + Lambda)
-                        if (a.Cik != R(0)) pn = ptr + lam * fast_sqrt(nS2 + sh2) * fast_rcp(Dp + lam) * a.Cik;
-                    } else if (own) {
-                        st(a.lam + sz * c, ro[u], lam);
-                    }
+                R lam;
+                if (a.lam_mode == LAM_FROZEN) {                  // frozen plasticity: the held Lambda
+                    lam = ld(a.lam + sz * c, ro[u]);
+                    // dilatancy of the held Lambda: lamdot = Lambda sqrt(J2(S)) / (Dp + Lambda)
+                    if (a.Cik != R(0)) pn = ptr + lam * fast_sqrt(nS2 + sh2) * fast_rcp(Dp + lam) * a.Cik;
+                } else {
+                    lam = centre_return(R(0.5) * (Txx * Txx + Tyy * Tyy + Tzz * Tzz), nS2, sh2, Dp, invDp, Dc, invDc,
+                                        pn, cc[u], a.A, a.B, a.Cik, a.vp, a.blend);
+                    if (a.lam_mode != LAM_COMPUTE && own) st(a.lam + sz * c, ro[u], lam);     // stored for freezing
                 }
                 const R sc_ = fast_rcp(Dc + lam);
                 R txx = Txx * sc_, tyy = Tyy * sc_;
