@@ -136,15 +136,16 @@ __device__ __forceinline__ void sweep_tile_2d(const SweepArgs<R>& a, int bx, int
             const R Sb = R(0.25) * (s_Sxy[q] + s_Sxy[q + 1] + s_Sxy[q + W] + s_Sxy[q + W + 1]);
             const R nS2 = R(0.5) * (Sxx * Sxx + Syy * Syy), sh2 = Sb * Sb;
             const R ptr = pn;
-            R lam = centre_return(R(0.5) * (Txx * Txx + Tyy * Tyy), nS2, sh2, Dp, invDp, Dc, invDc, pn, gc[u], a.A,
-                                  a.B, a.Cik, a.vp, a.blend);
             const bool own = la >= 2 && la < TX + 2 && lbb >= 2 && lbb < TY + 2;
-            if (a.lam_mode == LAM_FROZEN) {
+            R lam;
+            if (a.lam_mode == LAM_FROZEN) {               // frozen plasticity: the held Lambda
                 lam = a.lam[e];
                 // dilatancy of the held Lambda: lamdot = Lambda sqrt(J2(S)) / (Dp + Lambda)
                 if (a.Cik != R(0)) pn = ptr + lam * fast_sqrt(nS2 + sh2) * fast_rcp(Dp + lam) * a.Cik;
-            } else if (a.lam_mode == LAM_STORE && own) {
-                a.lam[e] = lam;
+            } else {
+                lam = centre_return(R(0.5) * (Txx * Txx + Tyy * Tyy), nS2, sh2, Dp, invDp, Dc, invDc, pn, gc[u], a.A,
+                                    a.B, a.Cik, a.vp, a.blend);
+                if (a.lam_mode == LAM_STORE && own) a.lam[e] = lam;    // stored for freezing
             }
             const R sc_ = fast_rcp(Dc + lam);
             R txx = Txx * sc_, tyy = Tyy * sc_;
