@@ -50,7 +50,10 @@ typedef struct ep_net_config {
     int   base;              /* level-0 channels C: 16 or 32 */
     int   max_samples;       /* training samples held on the device (>= 0); 0: an inference-only
                                 network (no sample slots, no activation gradients: about half
-                                the workspace); ep_net_train and ep_net_gradient then fail */
+                                the workspace); ep_net_train and ep_net_gradient then fail.
+                                A training network (> 0) also holds a 32 MiB buffer of partial
+                                gradient sums, added in a fixed order: its gradients and training
+                                runs repeat bit for bit */
     float scale[4];          /* stress, plastic strain, input velocity change, output velocity change (> 0) */
     int   seed;              /* weight initialisation: He-normal, zero head */
 } ep_net_config;

@@ -51,6 +51,7 @@ __device__ __forceinline__ b8 ld_b8(const bf16_t* p) { return __builtin_bit_cast
 constexpr int NL = 11;      // convolutions
 constexpr int CIN0 = 16;    // input channels (11 used)
 constexpr int COUT = 16;    // output channels (3 used)
+constexpr long PART_FLOATS = 1L << 23;   // partial-sum buffer of the parameter gradients (32 MiB)
 
 // ------------------------------------------------------------ bfloat16
 __device__ __forceinline__ float bf2f(bf16_t b) { return __uint_as_float((unsigned)b << 16); }
@@ -236,13 +237,28 @@ __global__ __launch_bounds__(256) void k_conv(const bf16_t* __restrict__ X, int 
     }
 }
 
-// dW[o][t][i] += sum over voxels of G[v][o] X[v + off_t][i] (one tap per
-// blockIdx.y, a chunk of voxels per blockIdx.x).
+// Block index -> logical index so that consecutive logical indices run on
+// the same XCD (workgroups are dispatched round-robin over the 8 XCDs).
+// Bijective for any nb.
+__device__ __forceinline__ int xcd_order(int b, int nb)
+{
+    const int q = nb / 8, r = nb % 8;
+    const int x = b % 8, s = b / 8;
+    return x < r ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
+}
+
+// part[chunk][o][t][i] = sum over the chunk's voxels v of G[v][o] X[v + off_t][i],
+// one workgroup per (voxel chunk, tap); k_wsum adds the chunks up in a fixed
+// order, so a gradient does not depend on the order the workgroups run in.
+// The 27 taps of a chunk are consecutive logical workgroups on one XCD: the
+// chunk's output gradient and the overlapping input windows of its taps come
+// from HBM about once, then from that XCD's L2.
 template <int NBO, int NBI>
 __global__ __launch_bounds__(256) void k_wgrad(const bf16_t* __restrict__ X, const bf16_t* __restrict__ G,
-                                               float* __restrict__ dW, Vol g, long vchunk)
+                                               float* __restrict__ part, Vol g, long vchunk)
 {
     constexpr int CO = NBO * 16, CI = NBI * 16;
+    constexpr long E = 27L * CO * CI;                  // entries of one chunk's partial gradient
     constexpr int RW = 72;                             // 64 voxels + 8: rows of 144 bytes
     constexpr int NP = NBO * NBI, PW = (NP + 3) / 4;   // block pairs, per wave
     // channel-major (transposed) stage: a lane's 8 voxels of one channel are
@@ -250,9 +266,10 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16_t* __restrict__ X, con
     __shared__ __attribute__((aligned(16))) bf16_t sG[CO * RW], sX[CI * RW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, kq = lane >> 4;
-    const int t = blockIdx.y;
+    const int lb = xcd_order(blockIdx.x, gridDim.x);
+    const int t = lb % 27, chunk = lb / 27;
     const long off = tap_off(g, t);
-    const long v0 = (long)blockIdx.x * vchunk;
+    const long v0 = (long)chunk * vchunk;
     const long v1 = v0 + vchunk < g.V ? v0 + vchunk : g.V;
     f4 acc[PW];
 #pragma unroll
@@ -303,13 +320,34 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16_t* __restrict__ X, con
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int o = ob * 16 + kq * 4 + i, c = ib * 16 + r;
-            atomicAdd(dW + ((long)o * 27 + t) * CI + c, acc[q][i]);
+            part[chunk * E + ((long)o * 27 + t) * CI + c] = acc[q][i];
         }
     }
 }
 
-// db[c] += sum over voxels of G[v][c]
-__global__ void k_bias_grad(const bf16_t* __restrict__ G, int C, float* __restrict__ db, Vol g)
+// dW[e] += sum over chunks of part[chunk][e], in chunk order: thread (j, e)
+// of a 256-thread block (32 entries x 8) sums chunks j, j + 8, ..., then the
+// eight sums are added in j order.
+__global__ __launch_bounds__(256) void k_wsum(const float* __restrict__ part, long nch, long E, float* __restrict__ dW)
+{
+    __shared__ float s[8][32];
+    const int el = threadIdx.x & 31, jl = threadIdx.x >> 5;
+    const long e = (long)blockIdx.x * 32 + el;
+    float acc = 0.f;
+    if (e < E)
+        for (long c = jl; c < nch; c += 8) acc += part[c * E + e];
+    s[jl][el] = acc;
+    __syncthreads();
+    if (jl == 0 && e < E) {
+        float sum = s[0][el];
+        for (int j = 1; j < 8; ++j) sum += s[j][el];
+        dW[e] += sum;
+    }
+}
+
+// part[block][c] = sum over the block's voxels of G[v][c] (k_bsum adds the
+// blocks up in a fixed order)
+__global__ void k_bias_grad(const bf16_t* __restrict__ G, int C, float* __restrict__ part, Vol g)
 {
     // thread = (voxel slot, group of 8 channels): 16-byte loads, a block
     // covers 256 / (C / 8) voxels per step (C in {16, 32, 64, 128})
@@ -329,8 +367,26 @@ __global__ void k_bias_grad(const bf16_t* __restrict__ G, int C, float* __restri
         const int gq = threadIdx.x / 8, k = threadIdx.x % 8;
         float sum = 0.f;
         for (int q = 0; q < nv; ++q) sum += s[(q * ng + gq) * 8 + k];
-        atomicAdd(db + threadIdx.x, sum);
+        part[(long)blockIdx.x * C + threadIdx.x] = sum;
     }
+}
+
+// db[c] += sum over blocks of part[block][c], one workgroup per channel:
+// thread j sums blocks j, j + 256, ..., then a tree of fixed shape adds the
+// 256 sums.
+__global__ __launch_bounds__(256) void k_bsum(const float* __restrict__ part, int nb, int C, float* __restrict__ db)
+{
+    __shared__ float s[256];
+    const int c = blockIdx.x;
+    float acc = 0.f;
+    for (int b = threadIdx.x; b < nb; b += 256) acc += part[(long)b * C + c];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[c] += s[0];
 }
 
 // ------------------------------------------------------------ elementwise
@@ -594,6 +650,7 @@ struct ep_net {
     double* vlast;             // V0 x 3
     float* dvp;                // V0 x 4
     double* loss;
+    float* part;               // per-chunk partial sums of the weight and bias gradients (training only)
     bool have_last;
     long adam_t;
     char err[512];
@@ -686,6 +743,7 @@ size_t net_carve(const ep_net_config* c, ep_net* n, char* base)
     double* vlast = (double*)take((size_t)g0.V * 3 * 8);
     float* dvp = (float*)take((size_t)g0.V * 4 * 4);
     double* loss = (double*)take(8);
+    float* part = c->max_samples > 0 ? (float*)take(PART_FLOATS * 4) : nullptr;
     if (n) {
         n->g[0] = g0; n->g[1] = g1; n->g[2] = g2;
         std::memcpy(n->ch, ch, sizeof(ch));
@@ -701,7 +759,7 @@ size_t net_carve(const ep_net_config* c, ep_net* n, char* base)
         bf16_t** gd[21] = {&n->gy, &n->z9, &n->gc0, &n->z8, &n->t0, &n->gd1, &n->z7, &n->gc1, &n->z6, &n->t1, &n->gb2,
                            &n->z5, &n->z4, &n->t2, &n->gs1, &n->z3, &n->z2, &n->t3, &n->gs0, &n->z1, &n->z0};
         for (int q = 0; q < 21; ++q) *gd[q] = G[q];
-        n->sx = sx; n->stg = stg; n->vlast = vlast; n->dvp = dvp; n->loss = loss;
+        n->sx = sx; n->stg = stg; n->vlast = vlast; n->dvp = dvp; n->loss = loss; n->part = part;
     }
     return (off + 255) / 256 * 256;
 }
@@ -731,29 +789,39 @@ void conv(int epi, int cout, const bf16_t* X, int cin, const bf16_t* W, const fl
 }
 
 template <int NBO>
-void wgrad_o(int nbi, const bf16_t* X, const bf16_t* G, float* dW, const Vol& g, hipStream_t s)
+void wgrad_o(int nbi, const bf16_t* X, const bf16_t* G, float* part, float* dW, const Vol& g, hipStream_t s)
 {
-    // up to 512 voxel chunks per tap (27 x 512 workgroups keep the staging
-    // latency hidden); each adds its 16 x 16 blocks to the FP32 gradient once
-    const long vchunk = std::max<long>(2048, (g.V + 511) / 512 / 64 * 64);
-    dim3 grid((unsigned)((g.V + vchunk - 1) / vchunk), 27);
+    // voxel chunks of at least 2048 voxels (a multiple of 64), at most 512
+    // per tap (27 x 512 workgroups keep the staging latency hidden) and as
+    // many as the partial-sum buffer holds
+    const long E = 27L * NBO * 16 * nbi * 16;
+    long nch = std::min<long>((g.V + 2047) / 2048, std::min<long>(512, PART_FLOATS / E));
+    const long vchunk = ((g.V + nch - 1) / nch + 63) / 64 * 64;
+    nch = (g.V + vchunk - 1) / vchunk;
+    const unsigned grid = (unsigned)nch * 27u;
     switch (nbi) {
-    case 1: k_wgrad<NBO, 1><<<grid, 256, 0, s>>>(X, G, dW, g, vchunk); break;
-    case 2: k_wgrad<NBO, 2><<<grid, 256, 0, s>>>(X, G, dW, g, vchunk); break;
-    case 4: k_wgrad<NBO, 4><<<grid, 256, 0, s>>>(X, G, dW, g, vchunk); break;
-    default: k_wgrad<NBO, 8><<<grid, 256, 0, s>>>(X, G, dW, g, vchunk); break;
+    case 1: k_wgrad<NBO, 1><<<grid, 256, 0, s>>>(X, G, part, g, vchunk); break;
+    case 2: k_wgrad<NBO, 2><<<grid, 256, 0, s>>>(X, G, part, g, vchunk); break;
+    case 4: k_wgrad<NBO, 4><<<grid, 256, 0, s>>>(X, G, part, g, vchunk); break;
+    default: k_wgrad<NBO, 8><<<grid, 256, 0, s>>>(X, G, part, g, vchunk); break;
     }
+    k_wsum<<<(unsigned)((E + 31) / 32), 256, 0, s>>>(part, nch, E, dW);
 }
 
-void wgrad(int cout, int cin, const bf16_t* X, const bf16_t* G, float* dW, float* db, const Vol& g, hipStream_t s)
+// Weight and bias gradients of one layer, added to dW and db through the
+// partial-sum buffer part (PART_FLOATS floats), deterministically.
+void wgrad(float* part, int cout, int cin, const bf16_t* X, const bf16_t* G, float* dW, float* db, const Vol& g,
+           hipStream_t s)
 {
     switch (cout / 16) {
-    case 1: wgrad_o<1>(cin / 16, X, G, dW, g, s); break;
-    case 2: wgrad_o<2>(cin / 16, X, G, dW, g, s); break;
-    case 4: wgrad_o<4>(cin / 16, X, G, dW, g, s); break;
-    default: wgrad_o<8>(cin / 16, X, G, dW, g, s); break;
+    case 1: wgrad_o<1>(cin / 16, X, G, part, dW, g, s); break;
+    case 2: wgrad_o<2>(cin / 16, X, G, part, dW, g, s); break;
+    case 4: wgrad_o<4>(cin / 16, X, G, part, dW, g, s); break;
+    default: wgrad_o<8>(cin / 16, X, G, part, dW, g, s); break;
     }
-    k_bias_grad<<<(unsigned)std::min<long>(2048, (g.V * (cout / 8) + 255) / 256), 256, 0, s>>>(G, cout, db, g);
+    const int nb = (int)std::min<long>(1024, (g.V * (cout / 8) + 255) / 256);
+    k_bias_grad<<<(unsigned)nb, 256, 0, s>>>(G, cout, part, g);
+    k_bsum<<<(unsigned)cout, 256, 0, s>>>(part, nb, cout, db);
 }
 
 void refresh_bf16(ep_net* n)
@@ -805,37 +873,37 @@ void backward(ep_net* n, const bf16_t* x)
     auto GW = [&](int l) { return n->gr + n->woff[l]; };
     auto GB = [&](int l) { return n->gr + n->boff[l]; };
     k_fill_f<<<nblk(n->np), 256, 0, s>>>(n->gr, 0.f, n->np);
-    wgrad(COUT, C, n->d0, n->gy, GW(10), GB(10), g0, s);
+    wgrad(n->part, COUT, C, n->d0, n->gy, GW(10), GB(10), g0, s);
     conv(EPI_MASK, C, n->gy, COUT, WT(10), nullptr, n->z9, n->d0, g0, s);
-    wgrad(C, C, n->c0, n->z9, GW(9), GB(9), g0, s);
+    wgrad(n->part, C, C, n->c0, n->z9, GW(9), GB(9), g0, s);
     conv(EPI_LIN, C, n->z9, C, WT(9), nullptr, n->gc0, nullptr, g0, s);
     k_mask<<<nblk(g0.V * C), 256, 0, s>>>(n->gc0, n->r8, n->z8, C, g0);
-    wgrad(C, C2, n->u0, n->z8, GW(8), GB(8), g0, s);
+    wgrad(n->part, C, C2, n->u0, n->z8, GW(8), GB(8), g0, s);
     conv(EPI_LIN, C2, n->z8, C, WT(8), nullptr, n->t0, nullptr, g0, s);
     k_up_dx<<<nblk(g1.V * C2), 256, 0, s>>>(n->t0, n->gd1, C2, g0, g1);
     k_mask<<<nblk(g1.V * C2), 256, 0, s>>>(n->gd1, n->d1, n->z7, C2, g1);
-    wgrad(C2, C2, n->c1, n->z7, GW(7), GB(7), g1, s);
+    wgrad(n->part, C2, C2, n->c1, n->z7, GW(7), GB(7), g1, s);
     conv(EPI_LIN, C2, n->z7, C2, WT(7), nullptr, n->gc1, nullptr, g1, s);
     k_mask<<<nblk(g1.V * C2), 256, 0, s>>>(n->gc1, n->r6, n->z6, C2, g1);
-    wgrad(C2, C4, n->u1, n->z6, GW(6), GB(6), g1, s);
+    wgrad(n->part, C2, C4, n->u1, n->z6, GW(6), GB(6), g1, s);
     conv(EPI_LIN, C4, n->z6, C2, WT(6), nullptr, n->t1, nullptr, g1, s);
     k_up_dx<<<nblk(g2.V * C4), 256, 0, s>>>(n->t1, n->gb2, C4, g1, g2);
     k_mask<<<nblk(g2.V * C4), 256, 0, s>>>(n->gb2, n->b2, n->z5, C4, g2);
-    wgrad(C4, C4, n->a2, n->z5, GW(5), GB(5), g2, s);
+    wgrad(n->part, C4, C4, n->a2, n->z5, GW(5), GB(5), g2, s);
     conv(EPI_MASK, C4, n->z5, C4, WT(5), nullptr, n->z4, n->a2, g2, s);
-    wgrad(C4, C2, n->p1, n->z4, GW(4), GB(4), g2, s);
+    wgrad(n->part, C4, C2, n->p1, n->z4, GW(4), GB(4), g2, s);
     conv(EPI_LIN, C2, n->z4, C4, WT(4), nullptr, n->t2, nullptr, g2, s);
     k_add_pool_dx<<<nblk(g1.V * C2), 256, 0, s>>>(n->gc1, n->t2, n->gs1, C2, g1, g2);
     k_mask<<<nblk(g1.V * C2), 256, 0, s>>>(n->gs1, n->s1, n->z3, C2, g1);
-    wgrad(C2, C2, n->a1, n->z3, GW(3), GB(3), g1, s);
+    wgrad(n->part, C2, C2, n->a1, n->z3, GW(3), GB(3), g1, s);
     conv(EPI_MASK, C2, n->z3, C2, WT(3), nullptr, n->z2, n->a1, g1, s);
-    wgrad(C2, C, n->p0, n->z2, GW(2), GB(2), g1, s);
+    wgrad(n->part, C2, C, n->p0, n->z2, GW(2), GB(2), g1, s);
     conv(EPI_LIN, C, n->z2, C2, WT(2), nullptr, n->t3, nullptr, g1, s);
     k_add_pool_dx<<<nblk(g0.V * C), 256, 0, s>>>(n->gc0, n->t3, n->gs0, C, g0, g1);
     k_mask<<<nblk(g0.V * C), 256, 0, s>>>(n->gs0, n->s0, n->z1, C, g0);
-    wgrad(C, C, n->a0, n->z1, GW(1), GB(1), g0, s);
+    wgrad(n->part, C, C, n->a0, n->z1, GW(1), GB(1), g0, s);
     conv(EPI_MASK, C, n->z1, C, WT(1), nullptr, n->z0, n->a0, g0, s);
-    wgrad(C, CIN0, x, n->z0, GW(0), GB(0), g0, s);
+    wgrad(n->part, C, CIN0, x, n->z0, GW(0), GB(0), g0, s);
 }
 
 float inv_count(const ep_net* n)

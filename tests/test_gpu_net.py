@@ -134,6 +134,30 @@ def test_gradient_matches_oracle(grid):
     n.close()
 
 
+def test_gradients_and_training_are_reproducible():
+    """The parameter gradients are summed over voxel chunks and workgroups in
+    a fixed order (no floating-point atomics), so they repeat bit for bit: on
+    a grid of several voxel chunks per tap, two gradients of one sample agree
+    exactly, and so do two networks trained from the same start."""
+    base = 16
+    nets = [net(40, 24, 20, base=base, samples=1, seed=3) for _ in range(2)]
+    r = np.random.Generator(np.random.PCG64(8))
+    x = r.standard_normal(nets[0].dims + (16,))
+    t = r.standard_normal(nets[0].dims + (4,)) * 0.1
+    for n in nets:
+        random_net(n, base, seed=9)
+        n.set_sample(0, x=x, t=t)
+    _, g0 = nets[0].gradient(0)
+    _, g1 = nets[0].gradient(0)
+    assert np.abs(g0).max() > 0
+    assert np.array_equal(g0, g1)
+    for n in nets:
+        n.train([0], 20, lr=1e-3)
+    assert np.array_equal(nets[0].get_params(), nets[1].get_params())
+    for n in nets:
+        n.close()
+
+
 def test_adam_step_matches_oracle_and_training_reduces_loss():
     base = 16
     n = net(12, 8, 16, base=base)
