@@ -476,13 +476,14 @@ __global__ void k_mask(const bf16_t* __restrict__ a, const bf16_t* __restrict__ 
 // Loss: mean squared error over the interior faces; gy = its gradient.
 // Output channel d of voxel (x, y, z) is the lower d-face of that cell; the
 // face is interior when its index along d is in 1 .. n_d - 1.
+// Output gradient of the loss, and part[block] = the block's share of the
+// loss (k_lsum adds the blocks up in a fixed order).
 __global__ void k_loss(const float* __restrict__ y, const float* __restrict__ tg, bf16_t* __restrict__ gy, Vol g,
-                       int nx, int ny, int nz, float inv_n, double* __restrict__ loss)
+                       int nx, int ny, int nz, float inv_n, double* __restrict__ part)
 {
     __shared__ float s[256];
-    const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
     float acc = 0.f;
-    if (v < g.V) {
+    for (long v = (long)blockIdx.x * blockDim.x + threadIdx.x; v < g.V; v += (long)gridDim.x * blockDim.x) {
         const int x = (int)(v % g.W), yy = (int)((v / g.W) % g.H), z = (int)(v / ((long)g.W * g.H));
         const bool in = x < nx && yy < ny && z < nz;
         const long p = pidx(g, v);
@@ -502,16 +503,26 @@ __global__ void k_loss(const float* __restrict__ y, const float* __restrict__ tg
         if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicAdd(loss, (double)(s[0] * inv_n));
+    if (threadIdx.x == 0) part[blockIdx.x] = (double)s[0] * inv_n;
+}
+
+// loss = sum of the nb block shares, thread j taking blocks j, j + 256, ...,
+// then a tree of fixed shape (one workgroup of 256 threads)
+__global__ __launch_bounds__(256) void k_lsum(const double* __restrict__ part, int nb, double* __restrict__ loss)
+{
+    __shared__ double s[256];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) acc += part[b];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = s[0];
 }
 
 __global__ void k_fill_f(float* p, float v, long n)
-{
-    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < n) p[e] = v;
-}
-
-__global__ void k_fill_d(double* p, double v, long n)
 {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < n) p[e] = v;
@@ -918,10 +929,11 @@ int loss_and_grad(ep_net* n, int slot, double* loss_out)
     hipStream_t s = n->st;
     const bf16_t* x = slot_x(n, slot);
     forward(n, x);
-    k_fill_d<<<1, 64, 0, s>>>(n->loss, 0.0, 1);
     const Vol& g0 = n->g[0];
-    k_loss<<<nblk(g0.V), 256, 0, s>>>(n->y, slot_t(n, slot), n->gy, g0, n->cfg.nx, n->cfg.ny, n->cfg.nz,
-                                      inv_count(n), n->loss);
+    const unsigned nb = std::min(nblk(g0.V), 1024u);
+    k_loss<<<nb, 256, 0, s>>>(n->y, slot_t(n, slot), n->gy, g0, n->cfg.nx, n->cfg.ny, n->cfg.nz, inv_count(n),
+                              (double*)n->part);
+    k_lsum<<<1, 256, 0, s>>>((const double*)n->part, (int)nb, n->loss);
     backward(n, x);
     if (loss_out) {
         NCHK(n, hipMemcpyAsync(loss_out, n->loss, 8, hipMemcpyDeviceToHost, s));
