@@ -247,6 +247,20 @@ __device__ __forceinline__ int xcd_order(int b, int nb)
     return x < r ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
 }
 
+// Channels 0..7 of voxels v (a) and v + 1 (b) to eight channel rows of a
+// channel-major LDS stage: row k gets the dword (a_k, b_k) at d + k * rw
+// (d at an even voxel index, so every dword is aligned).
+__device__ __forceinline__ void stage_pair(bf16_t* d, int rw, const uint4& a, const uint4& b)
+{
+    const unsigned aw[4] = {a.x, a.y, a.z, a.w}, bw[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        // channel 2k: low halves of a and b; channel 2k + 1: high halves
+        *(unsigned*)(d + (2 * k) * rw) = (aw[k] & 0xffffu) | (bw[k] << 16);
+        *(unsigned*)(d + (2 * k + 1) * rw) = (aw[k] >> 16) | (bw[k] & 0xffff0000u);
+    }
+}
+
 // part[chunk][o][t][i] = sum over the chunk's voxels v of G[v][o] X[v + off_t][i],
 // one workgroup per (voxel chunk, tap); k_wsum adds the chunks up in a fixed
 // order, so a gradient does not depend on the order the workgroups run in.
@@ -276,25 +290,25 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16_t* __restrict__ X, con
     for (int q = 0; q < PW; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
     for (long vs = v0; vs < v1; vs += 64) {
         __syncthreads();
-        // stage 64 voxels: 8 channels (16 bytes) per thread and step, written
-        // transposed
-        for (int e = threadIdx.x; e < 64 * (CO / 8); e += 256) {
-            const int row = e / (CO / 8), q = e % (CO / 8);
+        // stage 64 voxels: a pair of voxels x 8 channels (two 16-byte loads)
+        // per thread and step, written transposed as 8 dwords (channel k of
+        // both voxels); the 32 lanes of a channel group take consecutive
+        // pairs, so that a wave's dword writes fall in distinct LDS banks
+        for (int e = threadIdx.x; e < 32 * (CO / 8); e += 256) {
+            const int row = 2 * (e % 32), q = e / 32;
             const long v = vs + row;
-            uint4 val = {0u, 0u, 0u, 0u};
-            if (v < v1) val = *(const uint4*)(G + pidx(g, v) * CO + q * 8);
-            const bf16_t* h = (const bf16_t*)&val;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) sG[(q * 8 + k) * RW + row] = h[k];
+            uint4 a = {0u, 0u, 0u, 0u}, b = {0u, 0u, 0u, 0u};
+            if (v < v1) a = *(const uint4*)(G + pidx(g, v) * CO + q * 8);
+            if (v + 1 < v1) b = *(const uint4*)(G + pidx(g, v + 1) * CO + q * 8);
+            stage_pair(sG + q * 8 * RW + row, RW, a, b);
         }
-        for (int e = threadIdx.x; e < 64 * (CI / 8); e += 256) {
-            const int row = e / (CI / 8), q = e % (CI / 8);
+        for (int e = threadIdx.x; e < 32 * (CI / 8); e += 256) {
+            const int row = 2 * (e % 32), q = e / 32;
             const long v = vs + row;
-            uint4 val = {0u, 0u, 0u, 0u};
-            if (v < v1) val = *(const uint4*)(X + (pidx(g, v) + off) * CI + q * 8);
-            const bf16_t* h = (const bf16_t*)&val;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) sX[(q * 8 + k) * RW + row] = h[k];
+            uint4 a = {0u, 0u, 0u, 0u}, b = {0u, 0u, 0u, 0u};
+            if (v < v1) a = *(const uint4*)(X + (pidx(g, v) + off) * CI + q * 8);
+            if (v + 1 < v1) b = *(const uint4*)(X + (pidx(g, v + 1) + off) * CI + q * 8);
+            stage_pair(sX + q * 8 * RW + row, RW, a, b);
         }
         __syncthreads();
 #pragma unroll
