@@ -288,29 +288,49 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16_t* __restrict__ X, con
     f4 acc[PW];
 #pragma unroll
     for (int q = 0; q < PW; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+    // stage 64 voxels: a pair of voxels x 8 channels (two 16-byte loads) per
+    // thread and task, loaded into registers one slab ahead and written
+    // transposed as 8 dwords (channel k of both voxels); the 32 lanes of a
+    // channel group take consecutive pairs, so that a wave's dword writes
+    // fall in distinct LDS banks
+    constexpr int NGT = 32 * (CO / 8), NXT = 32 * (CI / 8);
+    constexpr int NGL = (NGT + 255) / 256, NXL = (NXT + 255) / 256;
+    uint4 ga[NGL], gb[NGL], xa[NXL], xb[NXL];
+    auto load = [&](long vs) {
+#pragma unroll
+        for (int u = 0; u < NGL; ++u) {
+            const int e = threadIdx.x + 256 * u, row = 2 * (e % 32), q = e / 32;
+            const long v = vs + row;
+            ga[u] = uint4{0u, 0u, 0u, 0u};
+            gb[u] = uint4{0u, 0u, 0u, 0u};
+            if (e < NGT && v < v1) ga[u] = *(const uint4*)(G + pidx(g, v) * CO + q * 8);
+            if (e < NGT && v + 1 < v1) gb[u] = *(const uint4*)(G + pidx(g, v + 1) * CO + q * 8);
+        }
+#pragma unroll
+        for (int u = 0; u < NXL; ++u) {
+            const int e = threadIdx.x + 256 * u, row = 2 * (e % 32), q = e / 32;
+            const long v = vs + row;
+            xa[u] = uint4{0u, 0u, 0u, 0u};
+            xb[u] = uint4{0u, 0u, 0u, 0u};
+            if (e < NXT && v < v1) xa[u] = *(const uint4*)(X + (pidx(g, v) + off) * CI + q * 8);
+            if (e < NXT && v + 1 < v1) xb[u] = *(const uint4*)(X + (pidx(g, v + 1) + off) * CI + q * 8);
+        }
+    };
+    if (v0 < v1) load(v0);
     for (long vs = v0; vs < v1; vs += 64) {
         __syncthreads();
-        // stage 64 voxels: a pair of voxels x 8 channels (two 16-byte loads)
-        // per thread and step, written transposed as 8 dwords (channel k of
-        // both voxels); the 32 lanes of a channel group take consecutive
-        // pairs, so that a wave's dword writes fall in distinct LDS banks
-        for (int e = threadIdx.x; e < 32 * (CO / 8); e += 256) {
-            const int row = 2 * (e % 32), q = e / 32;
-            const long v = vs + row;
-            uint4 a = {0u, 0u, 0u, 0u}, b = {0u, 0u, 0u, 0u};
-            if (v < v1) a = *(const uint4*)(G + pidx(g, v) * CO + q * 8);
-            if (v + 1 < v1) b = *(const uint4*)(G + pidx(g, v + 1) * CO + q * 8);
-            stage_pair(sG + q * 8 * RW + row, RW, a, b);
+#pragma unroll
+        for (int u = 0; u < NGL; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            if (e < NGT) stage_pair(sG + (e / 32) * 8 * RW + 2 * (e % 32), RW, ga[u], gb[u]);
         }
-        for (int e = threadIdx.x; e < 32 * (CI / 8); e += 256) {
-            const int row = 2 * (e % 32), q = e / 32;
-            const long v = vs + row;
-            uint4 a = {0u, 0u, 0u, 0u}, b = {0u, 0u, 0u, 0u};
-            if (v < v1) a = *(const uint4*)(X + (pidx(g, v) + off) * CI + q * 8);
-            if (v + 1 < v1) b = *(const uint4*)(X + (pidx(g, v + 1) + off) * CI + q * 8);
-            stage_pair(sX + q * 8 * RW + row, RW, a, b);
+#pragma unroll
+        for (int u = 0; u < NXL; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            if (e < NXT) stage_pair(sX + (e / 32) * 8 * RW + 2 * (e % 32), RW, xa[u], xb[u]);
         }
         __syncthreads();
+        if (vs + 64 < v1) load(vs + 64);
 #pragma unroll
         for (int q = 0; q < PW; ++q) {
             const int pr = wave + 4 * q;
