@@ -267,13 +267,13 @@ __device__ __forceinline__ void stage_pair(bf16_t* d, int rw, const uint4& a, co
 // The 27 taps of a chunk are consecutive logical workgroups on one XCD: the
 // chunk's output gradient and the overlapping input windows of its taps come
 // from HBM about once, then from that XCD's L2.
-template <int NBO, int NBI>
+template <int NBO, int NBI, int SL>
 __global__ __launch_bounds__(256) void k_wgrad(const bf16_t* __restrict__ X, const bf16_t* __restrict__ G,
                                                float* __restrict__ part, Vol g, long vchunk)
 {
     constexpr int CO = NBO * 16, CI = NBI * 16;
     constexpr long E = 27L * CO * CI;                  // entries of one chunk's partial gradient
-    constexpr int RW = 72;                             // 64 voxels + 8: rows of 144 bytes
+    constexpr int RW = SL + 8;                         // SL voxels + 8: rows of 144 or 272 bytes
     constexpr int NP = NBO * NBI, PW = (NP + 3) / 4;   // block pairs, per wave
     // channel-major (transposed) stage: a lane's 8 voxels of one channel are
     // one 16-byte LDS read
@@ -288,18 +288,19 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16_t* __restrict__ X, con
     f4 acc[PW];
 #pragma unroll
     for (int q = 0; q < PW; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
-    // stage 64 voxels: a pair of voxels x 8 channels (two 16-byte loads) per
+    // stage SL voxels: a pair of voxels x 8 channels (two 16-byte loads) per
     // thread and task, loaded into registers one slab ahead and written
-    // transposed as 8 dwords (channel k of both voxels); the 32 lanes of a
-    // channel group take consecutive pairs, so that a wave's dword writes
+    // transposed as 8 dwords (channel k of both voxels); the SL / 2 lanes of
+    // a channel group take consecutive pairs, so that a wave's dword writes
     // fall in distinct LDS banks
-    constexpr int NGT = 32 * (CO / 8), NXT = 32 * (CI / 8);
+    constexpr int NPR = SL / 2;                        // voxel pairs per slab
+    constexpr int NGT = NPR * (CO / 8), NXT = NPR * (CI / 8);
     constexpr int NGL = (NGT + 255) / 256, NXL = (NXT + 255) / 256;
     uint4 ga[NGL], gb[NGL], xa[NXL], xb[NXL];
     auto load = [&](long vs) {
 #pragma unroll
         for (int u = 0; u < NGL; ++u) {
-            const int e = threadIdx.x + 256 * u, row = 2 * (e % 32), q = e / 32;
+            const int e = threadIdx.x + 256 * u, row = 2 * (e % NPR), q = e / NPR;
             const long v = vs + row;
             ga[u] = uint4{0u, 0u, 0u, 0u};
             gb[u] = uint4{0u, 0u, 0u, 0u};
@@ -308,7 +309,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16_t* __restrict__ X, con
         }
 #pragma unroll
         for (int u = 0; u < NXL; ++u) {
-            const int e = threadIdx.x + 256 * u, row = 2 * (e % 32), q = e / 32;
+            const int e = threadIdx.x + 256 * u, row = 2 * (e % NPR), q = e / NPR;
             const long v = vs + row;
             xa[u] = uint4{0u, 0u, 0u, 0u};
             xb[u] = uint4{0u, 0u, 0u, 0u};
@@ -317,27 +318,27 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16_t* __restrict__ X, con
         }
     };
     if (v0 < v1) load(v0);
-    for (long vs = v0; vs < v1; vs += 64) {
+    for (long vs = v0; vs < v1; vs += SL) {
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < NGL; ++u) {
             const int e = threadIdx.x + 256 * u;
-            if (e < NGT) stage_pair(sG + (e / 32) * 8 * RW + 2 * (e % 32), RW, ga[u], gb[u]);
+            if (e < NGT) stage_pair(sG + (e / NPR) * 8 * RW + 2 * (e % NPR), RW, ga[u], gb[u]);
         }
 #pragma unroll
         for (int u = 0; u < NXL; ++u) {
             const int e = threadIdx.x + 256 * u;
-            if (e < NXT) stage_pair(sX + (e / 32) * 8 * RW + 2 * (e % 32), RW, xa[u], xb[u]);
+            if (e < NXT) stage_pair(sX + (e / NPR) * 8 * RW + 2 * (e % NPR), RW, xa[u], xb[u]);
         }
         __syncthreads();
-        if (vs + 64 < v1) load(vs + 64);
+        if (vs + SL < v1) load(vs + SL);
 #pragma unroll
         for (int q = 0; q < PW; ++q) {
             const int pr = wave + 4 * q;
             if (pr >= NP) break;
             const int ob = pr / NBI, ib = pr % NBI;
 #pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
+            for (int ks = 0; ks < SL / 32; ++ks) {
                 // K = 32 voxels: lane (r, kq) holds voxels ks*32 + kq*8 .. +7 of
                 // output channel ob*16 + r (A) and input channel ib*16 + r (B)
                 const b8 a = ld_b8(sG + (ob * 16 + r) * RW + ks * 32 + kq * 8);
@@ -833,22 +834,32 @@ void conv(int epi, int cout, const bf16_t* X, int cin, const bf16_t* W, const fl
     else conv_epi<EPI_F32>(nb, X, cin, W, b, Y, M, g, s);
 }
 
+// Slabs of 128 voxels where neither tensor has more than 32 channels (fewer
+// barriers per voxel; the two stages still take only 17 KB of LDS), else 64.
+template <int NBO, int NBI>
+void launch_wgrad(unsigned grid, const bf16_t* X, const bf16_t* G, float* part, const Vol& g, long vchunk,
+                  hipStream_t s)
+{
+    constexpr int SL = (NBO <= 2 && NBI <= 2) ? 128 : 64;
+    k_wgrad<NBO, NBI, SL><<<grid, 256, 0, s>>>(X, G, part, g, vchunk);
+}
+
 template <int NBO>
 void wgrad_o(int nbi, const bf16_t* X, const bf16_t* G, float* part, float* dW, const Vol& g, hipStream_t s)
 {
-    // voxel chunks of at least 2048 voxels (a multiple of 64), at most 512
-    // per tap (27 x 512 workgroups keep the staging latency hidden) and as
-    // many as the partial-sum buffer holds
+    // voxel chunks of at least 2048 voxels (a multiple of 128, so of either
+    // slab size), at most 512 per tap (27 x 512 workgroups keep the staging
+    // latency hidden) and as many as the partial-sum buffer holds
     const long E = 27L * NBO * 16 * nbi * 16;
     long nch = std::min<long>((g.V + 2047) / 2048, std::min<long>(512, PART_FLOATS / E));
-    const long vchunk = ((g.V + nch - 1) / nch + 63) / 64 * 64;
+    const long vchunk = ((g.V + nch - 1) / nch + 127) / 128 * 128;
     nch = (g.V + vchunk - 1) / vchunk;
     const unsigned grid = (unsigned)nch * 27u;
     switch (nbi) {
-    case 1: k_wgrad<NBO, 1><<<grid, 256, 0, s>>>(X, G, part, g, vchunk); break;
-    case 2: k_wgrad<NBO, 2><<<grid, 256, 0, s>>>(X, G, part, g, vchunk); break;
-    case 4: k_wgrad<NBO, 4><<<grid, 256, 0, s>>>(X, G, part, g, vchunk); break;
-    default: k_wgrad<NBO, 8><<<grid, 256, 0, s>>>(X, G, part, g, vchunk); break;
+    case 1: launch_wgrad<NBO, 1>(grid, X, G, part, g, vchunk, s); break;
+    case 2: launch_wgrad<NBO, 2>(grid, X, G, part, g, vchunk, s); break;
+    case 4: launch_wgrad<NBO, 4>(grid, X, G, part, g, vchunk, s); break;
+    default: launch_wgrad<NBO, 8>(grid, X, G, part, g, vchunk, s); break;
     }
     k_wsum<<<(unsigned)((E + 31) / 32), 256, 0, s>>>(part, nch, E, dW);
 }
