@@ -1,7 +1,7 @@
 """GPU parity of the per-cell shear modulus (the heterogeneous setups of the
 section on initial conditions and heterogeneities) against the oracle:
 single sweeps from random states with a random G field (2D tile and unfused
-sweeps, 3D unfused) within 1e-11; the 2D heterogeneous setup (Gaussian G
+sweeps, 3D fused and unfused) within 1e-11; the 2D heterogeneous setup (Gaussian G
 from 1 to 1.2 and Gaussian cohesion with its wall jump, off-centre) with
 identical FP64 iteration counts, FP32 fields, frozen plasticity; a 3D
 trajectory with a Gaussian G; rejected inputs."""
@@ -147,8 +147,10 @@ def gaussian_G3(m, centre=(0.06, -0.04, 0.03)):
 
 @pytest.mark.parametrize("sweep", [0, 2], ids=["auto", "unfused"])
 def test_3d_single_sweeps_with_a_random_field(sweep):
-    """3D: a G field routes the sweeps to the unfused kernels (also under
-    EP_SWEEP_AUTO, whose default in 3D is the fused kernel)."""
+    """3D with a random G field: EP_SWEEP_AUTO (the fused kernel in 3D, which
+    reads the cell compliances through its plane ring) and the unfused
+    kernels, on one tile; the fused kernel's interior tiles with a G field
+    are covered by the single-sweep option tests."""
     m = Model(ndim=3, nx=13, ny=11, nz=9, shear=1.5, c0=1e-4)
     r = np.random.Generator(np.random.PCG64(47))
     G = r.uniform(0.5, 1.5, m.n_cells)
