@@ -264,9 +264,10 @@ __device__ __forceinline__ void stage_pair(bf16_t* d, int rw, const uint4& a, co
 // part[chunk][o][t][i] = sum over the chunk's voxels v of G[v][o] X[v + off_t][i],
 // one workgroup per (voxel chunk, tap); k_wsum adds the chunks up in a fixed
 // order, so a gradient does not depend on the order the workgroups run in.
-// The 27 taps of a chunk are consecutive logical workgroups on one XCD: the
-// chunk's output gradient and the overlapping input windows of its taps come
-// from HBM about once, then from that XCD's L2.
+// The 27 taps of a chunk are consecutive logical workgroups on one XCD, so
+// that the chunk's output gradient and the overlapping input windows of its
+// taps can be served from that XCD's L2 (no change in time measured: the
+// kernel is bound by its LDS staging).
 template <int NBO, int NBI, int SL>
 __global__ __launch_bounds__(256) void k_wgrad(const bf16_t* __restrict__ X, const bf16_t* __restrict__ G,
                                                float* __restrict__ part, Vol g, long vchunk)
