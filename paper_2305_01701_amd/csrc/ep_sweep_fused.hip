@@ -499,13 +499,17 @@ void k_fused_3d(SweepArgs<R> a, TileSet ts)
 //  - 32 x 16 (36 x 20 = 720 points), which fits grids of 32-cell multiples
 //    with fewer workgroups (255^3: 1024 workgroups, two full rounds of 512,
 //    0.585 ms, against 1248 and 0.618 ms for 48 x 10).
-// FP64: 16 x 8 tiles (48 KB of LDS, three workgroups per CU).
+// FP64: 32 x 16 tiles with 768 threads as well (144-154 KB of LDS, one
+// workgroup and three waves per SIMD per CU, the occupancy three 256-thread
+// 16 x 8 workgroups had): the wider halo plane cuts the re-read halo (the
+// FP64 sweep moves 2.06x its algorithmic bytes on 16 x 8 tiles), 511^3:
+// 8.42 against 9.39 ms per sweep (48 x 10: 8.77 ms).
 template <int X_, int Y_, int Z_, int T_, int E_> struct Tile {
     static constexpr int X = X_, Y = Y_, Z = Z_, T = T_, E = E_;
 };
 using TileF_wide = Tile<48, 10, 32, 768, 6>;
 using TileF_square = Tile<32, 16, 32, 768, 6>;
-using TileD = Tile<16, 8, 32, 256, 3>;
+using TileD = Tile<32, 16, 32, 768, 3>;
 
 // first and one-past-last tile index along an axis whose tiles lie strictly
 // inside with their 2-point halo: 3 <= i0 and i0 + T + 2 <= n
