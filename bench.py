@@ -97,7 +97,8 @@ def workload(name):
 
 
 def bytes_per_cell(ndim, prec_bytes):
-    # updated fields read + written, previous-increment stresses and cohesion read
+    # updated fields read + written (3D 9, 2D 6); the previous increment's
+    # pressure and stress components (3D 1 + 5, 2D 1 + 3) and the cohesion read
     return (25 if ndim == 3 else 17) * prec_bytes
 
 
